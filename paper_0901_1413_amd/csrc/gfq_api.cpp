@@ -1,0 +1,269 @@
+// gfq_api.cpp -- the C ABI declared in include/gfq.h: argument validation, launch
+// configuration, workspace and stream handling around the kernels of gfq_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "../../include/gfq.h"
+#include "gfq_internal.h"
+
+using namespace gfq;
+
+namespace {
+
+thread_local hipStream_t t_stream = nullptr;
+thread_local char t_hip_error[256] = "";
+
+int hip_fail(hipError_t e, const char *what) {
+    snprintf(t_hip_error, sizeof t_hip_error, "%s: %s", what, hipGetErrorString(e));
+    return GFQ_EHIP;
+}
+
+bool valid_field(int q) { return q == 3 || q == 4 || q == 5 || q == 7; }
+
+// Device workspace for split-l partial products, one growing buffer per device.
+struct Workspace {
+    std::mutex mu;
+    std::vector<void *> ptr;
+    std::vector<size_t> bytes;
+};
+Workspace g_ws;
+
+int workspace(size_t need, void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_ws.mu);
+    if ((int)g_ws.ptr.size() <= dev) {
+        g_ws.ptr.resize(dev + 1, nullptr);
+        g_ws.bytes.resize(dev + 1, 0);
+    }
+    if (g_ws.bytes[dev] < need) {
+        if (g_ws.ptr[dev]) {
+            // kernels queued on any stream may still read the old buffer
+            e = hipDeviceSynchronize();
+            if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+            (void)hipFree(g_ws.ptr[dev]);
+            g_ws.ptr[dev] = nullptr;
+            g_ws.bytes[dev] = 0;
+        }
+        size_t sz = std::max(need, (size_t)64 << 20);
+        e = hipMalloc(&g_ws.ptr[dev], sz);
+        if (e != hipSuccess) {
+            g_ws.ptr[dev] = nullptr;
+            hip_fail(e, "hipMalloc(workspace)");
+            return GFQ_ENOMEM;
+        }
+        g_ws.bytes[dev] = sz;
+    }
+    *out = g_ws.ptr[dev];
+    return GFQ_OK;
+}
+
+bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
+    const char *pa = (const char *)a, *pb = (const char *)b;
+    return na && nb && pa < pb + nb && pb < pa + na;
+}
+
+// Largest LDS layout whose table (2^k entries x P planes x super-row bytes) fits the
+// table budget; wider super-rows make the 16-lane gathers conflict-free.
+int layout_for(int P, int k) {
+    const size_t budget = 131072;
+    for (int lay = LAYOUT_W32_R2; lay <= LAYOUT_W8_R1; lay++)
+        if (((size_t)1 << k) * P * layout_srb(lay) <= budget) return lay;
+    return -1;
+}
+
+int check_config(int q, const gfq_config &c) {
+    if (c.k < 1 || c.k > KMAX) return GFQ_EINVAL;
+    if (c.rows != 128 && c.rows != 256 && c.rows != 512) return GFQ_EINVAL;
+    if (c.split < 1 || c.split > 64) return GFQ_EINVAL;
+    if (layout_for(planes_of(q), c.k) < 0) return GFQ_EINVAL;
+    return GFQ_OK;
+}
+
+int validate_mm(int q, int64_t m, int64_t l, int64_t n, const void *A, const void *B, void *C) {
+    if (!valid_field(q)) return GFQ_EFIELD;
+    if (m < 0 || l < 0 || n < 0 || l >= GFQ_MAX_DIM || m >= ((int64_t)1 << 28) || n >= ((int64_t)1 << 28))
+        return GFQ_EDIM;
+    if (m == 0 || n == 0) return GFQ_OK;
+    if (!C || (l > 0 && (!A || !B))) return GFQ_ENULL;
+    if (((uintptr_t)C & 15) || (l > 0 && (((uintptr_t)A & 15) || ((uintptr_t)B & 15)))) return GFQ_EALIGN;
+    const size_t bc = gfq_packed_bytes(q, m, n);
+    if (l > 0 && (overlaps(C, bc, A, gfq_packed_bytes(q, m, l)) || overlaps(C, bc, B, gfq_packed_bytes(q, l, n))))
+        return GFQ_EALIAS;
+    return GFQ_OK;
+}
+
+}  // namespace
+
+int gfq::rows_tile_of(int layout, int rowsTile) {
+    const int lpr = layout_twd(layout) / 4;
+    int R = rowsTile * lpr / 512;
+    R = R <= 1 ? 1 : (R == 2 ? 2 : (R <= 4 ? 4 : 8));
+    return (512 / lpr) * R;
+}
+
+extern "C" {
+
+size_t gfq_packed_bytes(int q, int64_t rows, int64_t cols) {
+    if (!valid_field(q) || rows < 0 || cols < 0) return 0;
+    return (size_t)rows * planes_of(q) * words_of(cols) * 4;
+}
+
+int gfq_set_stream(void *s) {
+    t_stream = (hipStream_t)s;
+    return GFQ_OK;
+}
+
+int gfq_sync(void) {
+    hipError_t e = hipStreamSynchronize(t_stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "asynchronous error");
+    return GFQ_OK;
+}
+
+const char *gfq_last_hip_error(void) { return t_hip_error; }
+
+const char *gfq_strerror(int s) {
+    switch (s) {
+    case GFQ_OK: return "ok";
+    case GFQ_EINVAL: return "invalid argument";
+    case GFQ_EFIELD: return "unsupported field (q must be 3, 4, 5 or 7)";
+    case GFQ_EDIM: return "invalid dimension or leading dimension";
+    case GFQ_ENULL: return "null pointer";
+    case GFQ_EALIGN: return "packed buffer not 16-byte aligned";
+    case GFQ_EALIAS: return "output overlaps an input";
+    case GFQ_ENOMEM: return "workspace allocation failed";
+    case GFQ_EHIP: return "HIP runtime error";
+    case GFQ_EBUDGET: return "request exceeds the memory budget";
+    case GFQ_EAGAIN: return "not ready, try again";
+    default: return "unknown status";
+    }
+}
+
+int gfq_pack(int q, int64_t rows, int64_t cols, const uint8_t *src, int64_t ld_src, void *dst) {
+    if (!valid_field(q)) return GFQ_EFIELD;
+    if (rows < 0 || cols < 0 || rows >= ((int64_t)1 << 28) || cols >= ((int64_t)1 << 28)) return GFQ_EDIM;
+    if (rows == 0 || cols == 0) return GFQ_OK;
+    if (ld_src < cols) return GFQ_EDIM;
+    if (!src || !dst) return GFQ_ENULL;
+    if ((uintptr_t)dst & 15) return GFQ_EALIGN;
+    if (overlaps(src, (size_t)((rows - 1) * ld_src + cols), dst, gfq_packed_bytes(q, rows, cols))) return GFQ_EALIAS;
+    hipError_t e = launch_pack(q, src, ld_src, (u32 *)dst, (int)rows, (int)cols, words_of(cols), t_stream);
+    return e == hipSuccess ? GFQ_OK : hip_fail(e, "pack launch");
+}
+
+int gfq_unpack(int q, int64_t rows, int64_t cols, const void *src, uint8_t *dst, int64_t ld_dst) {
+    if (!valid_field(q)) return GFQ_EFIELD;
+    if (rows < 0 || cols < 0 || rows >= ((int64_t)1 << 28) || cols >= ((int64_t)1 << 28)) return GFQ_EDIM;
+    if (rows == 0 || cols == 0) return GFQ_OK;
+    if (ld_dst < cols) return GFQ_EDIM;
+    if (!src || !dst) return GFQ_ENULL;
+    if ((uintptr_t)src & 15) return GFQ_EALIGN;
+    if (overlaps(dst, (size_t)((rows - 1) * ld_dst + cols), src, gfq_packed_bytes(q, rows, cols))) return GFQ_EALIAS;
+    hipError_t e = launch_unpack(q, (const u32 *)src, dst, ld_dst, (int)rows, (int)cols, words_of(cols), t_stream);
+    return e == hipSuccess ? GFQ_OK : hip_fail(e, "unpack launch");
+}
+
+int gfq_choose_config(int q, int64_t m, int64_t l, int64_t n, gfq_config *out) {
+    if (!valid_field(q)) return GFQ_EFIELD;
+    if (!out) return GFQ_ENULL;
+    if (m < 0 || l < 0 || n < 0) return GFQ_EDIM;
+    const int P = planes_of(q);
+    gfq_config c;
+    c.reserved = 0;
+    c.k = P == 2 ? 8 : 7;                       // widest table with 256-byte super-rows
+    if (l > 0 && l < c.k) c.k = (int)l;
+    if (c.k < 1) c.k = 1;
+    c.rows = m >= 4096 ? 512 : (m >= 512 ? 256 : 128);
+    const int lay = layout_for(P, c.k);
+    const int TM = rows_tile_of(lay, c.rows);
+    const int64_t tiles = ((words_of(n) + layout_twd(lay) - 1) / layout_twd(lay)) * ((m + TM - 1) / TM);
+    const int64_t S = l > 0 ? (l + c.k - 1) / c.k : 1;
+    // enough workgroups for 256 compute units, keeping at least 32 slabs per slice
+    int64_t split = tiles >= 256 ? 1 : (256 + tiles - 1) / tiles;
+    split = std::min<int64_t>(split, std::max<int64_t>(1, S / 32));
+    c.split = (int)std::max<int64_t>(1, std::min<int64_t>(split, 64));
+    *out = c;
+    return GFQ_OK;
+}
+
+int gfq_matmul_config(int q, int64_t m, int64_t l, int64_t n, const void *A, const void *B, void *C,
+                      const gfq_config *cfg) {
+    int st = validate_mm(q, m, l, n, A, B, C);
+    if (st != GFQ_OK) return st;
+    if (m == 0 || n == 0) return GFQ_OK;
+    gfq_config c;
+    if (cfg) {
+        c = *cfg;
+        st = check_config(q, c);
+        if (st != GFQ_OK) return st;
+    } else {
+        gfq_choose_config(q, m, l, n, &c);
+    }
+    const int P = planes_of(q);
+    const int Wn = words_of(n);
+    if (l == 0) {
+        hipError_t e = hipMemsetAsync(C, 0, gfq_packed_bytes(q, m, n), t_stream);
+        return e == hipSuccess ? GFQ_OK : hip_fail(e, "hipMemsetAsync");
+    }
+    MMArgs a;
+    a.A = (const u32 *)A;
+    a.B = (const u32 *)B;
+    a.m = (int)m;
+    a.l = (int)l;
+    a.n = (int)n;
+    a.Wl = words_of(l);
+    a.Wn = Wn;
+    a.k = c.k;
+    a.S = (int)((l + c.k - 1) / c.k);
+    int split = std::min(c.split, a.S);
+    a.slabs_per_split = (a.S + split - 1) / split;
+    split = (a.S + a.slabs_per_split - 1) / a.slabs_per_split;
+    a.split_stride = (size_t)m * P * Wn;
+    const int lay = layout_for(P, c.k);
+    if (split == 1) {
+        a.out = (u32 *)C;
+        a.canon = 1;
+        hipError_t e = launch_matmul(q, a, lay, c.rows, t_stream);
+        return e == hipSuccess ? GFQ_OK : hip_fail(e, "matmul launch");
+    }
+    void *ws = nullptr;
+    st = workspace(a.split_stride * 4 * split, &ws);
+    if (st != GFQ_OK) return st;
+    a.out = (u32 *)ws;
+    a.canon = 0;
+    hipError_t e = launch_matmul(q, a, lay, c.rows, t_stream);
+    if (e != hipSuccess) return hip_fail(e, "matmul launch");
+    e = launch_reduce(q, (const u32 *)ws, (u32 *)C, (int)m, (int)n, Wn, split, a.split_stride, t_stream);
+    return e == hipSuccess ? GFQ_OK : hip_fail(e, "reduce launch");
+}
+
+int gfq_matmul(int q, int64_t m, int64_t l, int64_t n, const void *A, const void *B, void *C) {
+    return gfq_matmul_config(q, m, l, n, A, B, C, nullptr);
+}
+
+int gfq_matmul_batched(int count, const gfq_problem *problems) {
+    if (count < 0) return GFQ_EINVAL;
+    if (count == 0) return GFQ_OK;
+    if (!problems) return GFQ_ENULL;
+    for (int i = 0; i < count; i++) {
+        const gfq_problem &p = problems[i];
+        int st = validate_mm(p.q, p.m, p.l, p.n, p.A, p.B, p.C);
+        if (st != GFQ_OK) return st;
+    }
+    for (int i = 0; i < count; i++) {
+        const gfq_problem &p = problems[i];
+        int st = gfq_matmul(p.q, p.m, p.l, p.n, p.A, p.B, p.C);
+        if (st != GFQ_OK) return st;
+    }
+    return GFQ_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,177 @@
+"""ctypes binding of libgfq.so (C ABI in include/gfq.h).
+
+Argument marshalling only: torch tensors provide device memory, torch's current stream
+is handed to the library before every call, and every computation runs in the HIP
+kernels of the library.  A missing library raises; nothing falls back to another path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgfq.so")
+
+GFQ_OK = 0
+FIELDS = (3, 4, 5, 7)
+
+
+class GfqError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(msg)
+        self.status = status
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int), ("rows", ctypes.c_int), ("split", ctypes.c_int),
+                ("reserved", ctypes.c_int)]
+
+    def as_dict(self):
+        return {"k": self.k, "rows": self.rows, "split": self.split}
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_int), ("m", ctypes.c_int64), ("l", ctypes.c_int64),
+                ("n", ctypes.c_int64), ("A", ctypes.c_void_p), ("B", ctypes.c_void_p),
+                ("C", ctypes.c_void_p)]
+
+
+_lib = None
+_I64 = ctypes.c_int64
+_VP = ctypes.c_void_p
+_SIGS = {
+    "gfq_packed_bytes": (ctypes.c_size_t, [ctypes.c_int, _I64, _I64]),
+    "gfq_pack": (ctypes.c_int, [ctypes.c_int, _I64, _I64, _VP, _I64, _VP]),
+    "gfq_unpack": (ctypes.c_int, [ctypes.c_int, _I64, _I64, _VP, _VP, _I64]),
+    "gfq_matmul": (ctypes.c_int, [ctypes.c_int, _I64, _I64, _I64, _VP, _VP, _VP]),
+    "gfq_matmul_config": (ctypes.c_int, [ctypes.c_int, _I64, _I64, _I64, _VP, _VP, _VP,
+                                         ctypes.POINTER(Config)]),
+    "gfq_choose_config": (ctypes.c_int, [ctypes.c_int, _I64, _I64, _I64, ctypes.POINTER(Config)]),
+    "gfq_matmul_batched": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(Problem)]),
+    "gfq_set_stream": (ctypes.c_int, [_VP]),
+    "gfq_sync": (ctypes.c_int, []),
+    "gfq_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "gfq_last_hip_error": (ctypes.c_char_p, []),
+}
+
+
+def load():
+    """Load libgfq.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def lib():
+    return load()
+
+
+def _check(status: int, what: str):
+    if status != GFQ_OK:
+        l = load()
+        msg = l.gfq_strerror(status).decode()
+        hip = l.gfq_last_hip_error().decode()
+        raise GfqError(status, f"{what}: {msg}" + (f" ({hip})" if hip else ""))
+
+
+def _bind_stream():
+    import torch
+    load().gfq_set_stream(ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+
+
+def planes(q: int) -> int:
+    return 2 if q in (3, 4) else 3
+
+
+def packed_bytes(q: int, rows: int, cols: int) -> int:
+    return int(load().gfq_packed_bytes(q, rows, cols))
+
+
+def empty_packed(q: int, rows: int, cols: int, device="cuda"):
+    import torch
+    return torch.empty(max(packed_bytes(q, rows, cols), 16), dtype=torch.uint8, device=device)
+
+
+def pack(q: int, X, out=None):
+    """Pack a device uint8 matrix X (rows x cols, row-major, any leading dimension)."""
+    import torch
+    assert X.dtype == torch.uint8 and X.dim() == 2 and X.is_cuda
+    rows, cols = X.shape
+    if X.stride(1) != 1:
+        X = X.contiguous()
+    if out is None:
+        out = empty_packed(q, rows, cols, X.device)
+    _bind_stream()
+    _check(load().gfq_pack(q, rows, cols, _VP(X.data_ptr()), max(X.stride(0), cols), _VP(out.data_ptr())), "gfq_pack")
+    return out
+
+
+def unpack(q: int, Pk, rows: int, cols: int, out=None):
+    import torch
+    if out is None:
+        out = torch.empty((rows, cols), dtype=torch.uint8, device=Pk.device)
+    _bind_stream()
+    _check(load().gfq_unpack(q, rows, cols, _VP(Pk.data_ptr()), _VP(out.data_ptr()), max(out.stride(0), cols)),
+           "gfq_unpack")
+    return out
+
+
+def choose_config(q: int, m: int, l: int, n: int) -> dict:
+    c = Config()
+    _check(load().gfq_choose_config(q, m, l, n, ctypes.byref(c)), "gfq_choose_config")
+    return c.as_dict()
+
+
+def matmul(q: int, A, B, m: int, l: int, n: int, out=None, k: int = 0, rows: int = 0, split: int = 0):
+    """C = A B on packed device operands; returns the packed product."""
+    if out is None:
+        out = empty_packed(q, m, n, A.device)
+    _bind_stream()
+    if k or rows or split:
+        c = Config()
+        _check(load().gfq_choose_config(q, m, l, n, ctypes.byref(c)), "gfq_choose_config")
+        if k:
+            c.k = k
+        if rows:
+            c.rows = rows
+        if split:
+            c.split = split
+        _check(load().gfq_matmul_config(q, m, l, n, _VP(A.data_ptr()), _VP(B.data_ptr()), _VP(out.data_ptr()),
+                                        ctypes.byref(c)), "gfq_matmul_config")
+    else:
+        _check(load().gfq_matmul(q, m, l, n, _VP(A.data_ptr()), _VP(B.data_ptr()), _VP(out.data_ptr())),
+               "gfq_matmul")
+    return out
+
+
+def matmul_batched(problems: Sequence[tuple]):
+    """problems: [(q, m, l, n, A, B, C)] with packed device tensors."""
+    arr = (Problem * len(problems))()
+    for i, (q, m, l, n, A, B, C) in enumerate(problems):
+        arr[i] = Problem(q, m, l, n, A.data_ptr(), B.data_ptr(), C.data_ptr())
+    _bind_stream()
+    _check(load().gfq_matmul_batched(len(problems), arr), "gfq_matmul_batched")
+
+
+def sync():
+    _bind_stream()
+    _check(load().gfq_sync(), "gfq_sync")
+
+
+def matmul_unpacked(q: int, A_u8, B_u8, **kw):
+    """Convenience: pack both operands, multiply, unpack (all on the GPU)."""
+    m, l = A_u8.shape
+    n = B_u8.shape[1]
+    Ap = pack(q, A_u8)
+    Bp = pack(q, B_u8)
+    Cp = matmul(q, Ap, Bp, m, l, n, **kw)
+    return unpack(q, Cp, m, n)

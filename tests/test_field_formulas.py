@@ -1,0 +1,71 @@
+"""Truth tables of the library's bitsliced field formulas (host build of gfq_field.h).
+
+Every formula is run on every input representative and checked against the value it
+must have: the residue of the integer it encodes (F_5, F_7: any 3-bit representative;
+F_3: the three codes of Section 4.1), or the GF(4) rule x^2 = x + 1.
+"""
+import os
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+F3_VAL = {(0, 0): 0, (1, 0): 1, (1, 1): 2}
+
+
+@pytest.fixture(scope="module")
+def table(tmp_path_factory):
+    exe = str(tmp_path_factory.mktemp("field") / "field_host_check")
+    subprocess.check_call(["g++", "-O2", "-std=c++14", "-Wall", "-I",
+                           os.path.join(ROOT, "paper_0901_1413_amd", "csrc"),
+                           os.path.join(ROOT, "tests", "field_host_check.cpp"), "-o", exe])
+    out = subprocess.check_output([exe], text=True)
+    return [l.split() for l in out.splitlines()]
+
+
+def test_f3(table):
+    rows = [r for r in table if r[0] == "f3"]
+    assert len(rows) == 9
+    for r in rows:
+        xu, xs, yu, ys = map(int, r[1:5])
+        add = (int(r[6]), int(r[7]))
+        sub = (int(r[9]), int(r[10]))
+        x, y = F3_VAL[(xu, xs)], F3_VAL[(yu, ys)]
+        assert add in F3_VAL and F3_VAL[add] == (x + y) % 3, r
+        assert sub in F3_VAL and F3_VAL[sub] == (x - y) % 3, r
+    for r in (r for r in table if r[0] == "f3neg"):
+        x = F3_VAL[(int(r[1]), int(r[2]))]
+        assert F3_VAL[(int(r[3]), int(r[4]))] == (-x) % 3
+
+
+def test_f5_f7_binary(table):
+    rows = [r for r in table if r[0] == "p3"]
+    assert len(rows) == 64
+    for r in rows:
+        a, b, f7, f5 = int(r[1]), int(r[2]), int(r[4]), int(r[6])
+        assert f7 % 7 == (a + b) % 7, r
+        assert f5 % 5 == (a + b) % 5, r
+    for r in (r for r in table if r[0] == "p1"):
+        a = int(r[1])
+        f7dbl, f7neg, f7red, f5dbl, f5neg, f5red = (int(r[i]) for i in (3, 5, 7, 9, 11, 13))
+        assert f7dbl % 7 == (2 * a) % 7
+        assert f7neg % 7 == (-a) % 7
+        assert f7red == a % 7                      # canonical in [0, 7)
+        assert f5dbl % 5 == (2 * a) % 5
+        assert f5neg % 5 == (-a) % 5
+        assert f5red == a % 5                      # canonical in [0, 5)
+
+
+def test_fold5(table):
+    rows = [r for r in table if r[0] == "fold5"]
+    assert len(rows) == 16
+    for r in rows:
+        assert int(r[2]) % 5 == int(r[1]) % 5, r
+
+
+def test_gf4(table):
+    mul = [[0, 0, 0, 0], [0, 1, 2, 3], [0, 2, 3, 1], [0, 3, 1, 2]]
+    for r in (r for r in table if r[0] == "g4"):
+        a, b, s, mx = map(int, (r[1], r[2], r[4], r[6]))
+        assert s == a ^ b
+        assert mx == mul[2][a]
