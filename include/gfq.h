@@ -81,10 +81,14 @@ int gfq_unpack(int q, int64_t rows, int64_t cols, const void *src, uint8_t *dst,
  * no-op; l == 0 writes a zero C.  Pad bits of A and B are ignored. */
 int gfq_matmul(int q, int64_t m, int64_t l, int64_t n, const void *A, const void *B, void *C);
 
-/* Explicit launch configuration for gfq_matmul_config (0 in a field = library's choice).
- *   k      slab width, 1..10 (table of 2^k binary row combinations per slab; the table
- *          needs 2^k * P * 256 bytes of LDS, so k <= 9 for P = 2 and k <= 8 for P = 3)
- *   rows   rows of C per workgroup, one of 128, 256, 512
+/* Explicit launch configuration for gfq_matmul_config (used by the autotuner and the k
+ * sweep).
+ *   k      slab width, 1..10: each slab of k rows of B gets a table of its 2^k binary row
+ *          combinations.  Two tables live in LDS at once; up to k = 7 (F_3, GF(4)) or
+ *          k = 6 (F_5, F_7) their rows are 256 bytes wide, larger k narrows the rows and
+ *          lets 128-bit LDS reads conflict.
+ *   rows   requested rows of C per workgroup: 256, 512, 1024 or 2048 (F_5 and F_7 are
+ *          capped by their register use; the library covers what fits)
  *   split  number of slices of the inner dimension computed by separate workgroups and
  *          summed afterwards, 1..64 */
 typedef struct { int k; int rows; int split; int reserved; } gfq_config;
@@ -117,6 +121,14 @@ int gfq_set_stream(void *hip_stream);
 
 /* Wait for the calling thread's stream; asynchronous HIP errors surface here as GFQ_EHIP. */
 int gfq_sync(void);
+
+/* Kernel timing for measurement tools (off by default).  While on, every launch of the
+ * product kernel and of the partial-sum kernel made by this thread is bracketed by HIP
+ * events on the launch stream.  gfq_timing_read waits for the recorded events, returns
+ * the summed milliseconds and launch counts of both kernels (any pointer may be NULL) and
+ * clears the record. */
+int gfq_set_timing(int on);
+int gfq_timing_read(double *product_ms, int *product_launches, double *reduce_ms, int *reduce_launches);
 
 /* Static description of a status code. */
 const char *gfq_strerror(int status);

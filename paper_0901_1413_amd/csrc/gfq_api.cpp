@@ -25,6 +25,32 @@ int hip_fail(hipError_t e, const char *what) {
 
 bool valid_field(int q) { return q == 3 || q == 4 || q == 5 || q == 7; }
 
+// Optional per-launch timing (gfq_set_timing).
+struct TimedLaunch { hipEvent_t e0, e1; int kind; };   // kind 0: product, 1: partial sum
+thread_local bool t_timing = false;
+thread_local std::vector<TimedLaunch> t_timed;
+
+hipEvent_t timing_mark() {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventRecord(e, t_stream) != hipSuccess) { (void)hipEventDestroy(e); return nullptr; }
+    return e;
+}
+
+// Launch f() and, when timing is on, bracket it with events.
+template <typename Fn> hipError_t timed(int kind, Fn f) {
+    if (!t_timing) return f();
+    hipEvent_t e0 = timing_mark();
+    hipError_t e = f();
+    hipEvent_t e1 = timing_mark();
+    if (e0 && e1) t_timed.push_back({e0, e1, kind});
+    else {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+    return e;
+}
+
 // Device workspace for split-l partial products, one growing buffer per device.
 struct Workspace {
     std::mutex mu;
@@ -69,20 +95,11 @@ bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
     return na && nb && pa < pb + nb && pb < pa + na;
 }
 
-// Largest LDS layout whose table (2^k entries x P planes x super-row bytes) fits the
-// table budget; wider super-rows make the 16-lane gathers conflict-free.
-int layout_for(int P, int k) {
-    const size_t budget = 131072;
-    for (int lay = LAYOUT_W32_R2; lay <= LAYOUT_W8_R1; lay++)
-        if (((size_t)1 << k) * P * layout_srb(lay) <= budget) return lay;
-    return -1;
-}
-
 int check_config(int q, const gfq_config &c) {
     if (c.k < 1 || c.k > KMAX) return GFQ_EINVAL;
-    if (c.rows != 128 && c.rows != 256 && c.rows != 512) return GFQ_EINVAL;
+    if (c.rows != 256 && c.rows != 512 && c.rows != 1024 && c.rows != 2048) return GFQ_EINVAL;
     if (c.split < 1 || c.split > 64) return GFQ_EINVAL;
-    if (layout_for(planes_of(q), c.k) < 0) return GFQ_EINVAL;
+    if (mm_plan(q, c.k, c.rows).srb == 0) return GFQ_EINVAL;
     return GFQ_OK;
 }
 
@@ -100,13 +117,6 @@ int validate_mm(int q, int64_t m, int64_t l, int64_t n, const void *A, const voi
 }
 
 }  // namespace
-
-int gfq::rows_tile_of(int layout, int rowsTile) {
-    const int lpr = layout_twd(layout) / 4;
-    int R = rowsTile * lpr / 512;
-    R = R <= 1 ? 1 : (R == 2 ? 2 : (R <= 4 ? 4 : 8));
-    return (512 / lpr) * R;
-}
 
 extern "C" {
 
@@ -129,6 +139,33 @@ int gfq_sync(void) {
 }
 
 const char *gfq_last_hip_error(void) { return t_hip_error; }
+
+int gfq_set_timing(int on) {
+    t_timing = on != 0;
+    return GFQ_OK;
+}
+
+int gfq_timing_read(double *product_ms, int *product_launches, double *reduce_ms, int *reduce_launches) {
+    double ms[2] = {0.0, 0.0};
+    int cnt[2] = {0, 0};
+    int status = GFQ_OK;
+    for (TimedLaunch &t : t_timed) {
+        float x = 0.f;
+        hipError_t e = hipEventSynchronize(t.e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&x, t.e0, t.e1);
+        if (e != hipSuccess) status = hip_fail(e, "timing events");
+        ms[t.kind] += x;
+        cnt[t.kind] += 1;
+        (void)hipEventDestroy(t.e0);
+        (void)hipEventDestroy(t.e1);
+    }
+    t_timed.clear();
+    if (product_ms) *product_ms = ms[0];
+    if (product_launches) *product_launches = cnt[0];
+    if (reduce_ms) *reduce_ms = ms[1];
+    if (reduce_launches) *reduce_launches = cnt[1];
+    return status;
+}
 
 const char *gfq_strerror(int s) {
     switch (s) {
@@ -175,22 +212,35 @@ int gfq_choose_config(int q, int64_t m, int64_t l, int64_t n, gfq_config *out) {
     if (!valid_field(q)) return GFQ_EFIELD;
     if (!out) return GFQ_ENULL;
     if (m < 0 || l < 0 || n < 0) return GFQ_EDIM;
-    const int P = planes_of(q);
-    gfq_config c;
-    c.reserved = 0;
-    c.k = P == 2 ? 8 : 7;                       // widest table with 256-byte super-rows
-    if (l > 0 && l < c.k) c.k = (int)l;
-    if (c.k < 1) c.k = 1;
-    c.rows = m >= 4096 ? 512 : (m >= 512 ? 256 : 128);
-    const int lay = layout_for(P, c.k);
-    const int TM = rows_tile_of(lay, c.rows);
-    const int64_t tiles = ((words_of(n) + layout_twd(lay) - 1) / layout_twd(lay)) * ((m + TM - 1) / TM);
-    const int64_t S = l > 0 ? (l + c.k - 1) / c.k : 1;
-    // enough workgroups for 256 compute units, keeping at least 32 slabs per slice
-    int64_t split = tiles >= 256 ? 1 : (256 + tiles - 1) / tiles;
-    split = std::min<int64_t>(split, std::max<int64_t>(1, S / 32));
-    c.split = (int)std::max<int64_t>(1, std::min<int64_t>(split, 64));
-    *out = c;
+    gfq_config best = {};
+    double best_cost = 0.0;
+    // k = 7: the widest slab whose two tables fit LDS with 128-bit reads that conflict at
+    // most two ways (measured best or near-best for every field on the large products).
+    // Then the tallest tile (the table build is amortised over its rows) and just enough
+    // slices of the inner dimension to give every compute unit a workgroup.
+    const int kk = (l > 0 && l < 7) ? (int)l : 7;
+    const int twd = twd_of(srb_for(q, kk));
+    const int64_t ctiles = (words_of(n) + twd - 1) / twd;
+    const int64_t S = l > 0 ? (l + kk - 1) / kk : 1;
+    for (int rows = 2048; rows >= 256; rows >>= 1) {
+        const MMPlan p = mm_plan(q, kk, rows);
+        if (!p.srb) continue;
+        const int64_t tiles = ctiles * ((m + p.TM - 1) / p.TM);
+        int64_t split = tiles >= 256 ? 1 : (256 + tiles - 1) / tiles;
+        split = std::max<int64_t>(1, std::min<int64_t>({split, std::max<int64_t>(1, S / 32), 64}));
+        const int64_t rounds = (tiles * split + 255) / 256;
+        // relative time: rounds x rows x slabs per slice x (accumulate + table build)
+        const double slabs = (double)((S + split - 1) / split);
+        const double cost = (double)rounds * p.TM * slabs * (1.0 + (double)(1 << kk) / p.TM);
+        if (best_cost == 0.0 || cost < best_cost * 0.999) {
+            best_cost = cost;
+            best.k = kk;
+            best.rows = rows;
+            best.split = (int)split;
+        }
+    }
+    best.reserved = 0;
+    *out = best;
     return GFQ_OK;
 }
 
@@ -227,21 +277,21 @@ int gfq_matmul_config(int q, int64_t m, int64_t l, int64_t n, const void *A, con
     a.slabs_per_split = (a.S + split - 1) / split;
     split = (a.S + a.slabs_per_split - 1) / a.slabs_per_split;
     a.split_stride = (size_t)m * P * Wn;
-    const int lay = layout_for(P, c.k);
+    const MMPlan plan = mm_plan(q, c.k, c.rows);
     if (split == 1) {
         a.out = (u32 *)C;
-        a.canon = 1;
-        hipError_t e = launch_matmul(q, a, lay, c.rows, t_stream);
+        hipError_t e = timed(0, [&] { return launch_matmul(q, a, plan, t_stream); });
         return e == hipSuccess ? GFQ_OK : hip_fail(e, "matmul launch");
     }
     void *ws = nullptr;
     st = workspace(a.split_stride * 4 * split, &ws);
     if (st != GFQ_OK) return st;
     a.out = (u32 *)ws;
-    a.canon = 0;
-    hipError_t e = launch_matmul(q, a, lay, c.rows, t_stream);
+    hipError_t e = timed(0, [&] { return launch_matmul(q, a, plan, t_stream); });
     if (e != hipSuccess) return hip_fail(e, "matmul launch");
-    e = launch_reduce(q, (const u32 *)ws, (u32 *)C, (int)m, (int)n, Wn, split, a.split_stride, t_stream);
+    e = timed(1, [&] {
+        return launch_reduce(q, (const u32 *)ws, (u32 *)C, (int)m, (int)n, Wn, split, a.split_stride, t_stream);
+    });
     return e == hipSuccess ? GFQ_OK : hip_fail(e, "reduce launch");
 }
 

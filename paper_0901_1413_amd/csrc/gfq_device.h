@@ -1,0 +1,138 @@
+// gfq_device.h -- per-field traits used by the kernels.
+//
+// Three representations meet in the product kernel:
+//   storage     the packed format of the C ABI (Section 4 encodings), P planes;
+//   table       how table entries (sums of rows of B) are held in LDS, P planes;
+//   accumulator how a lane keeps its running row of C, PA planes (carry-save pairs of
+//               residues modulo 2^NB - 1, see gfq_field.h).
+// Every trait works on one 32-bit word per plane (32 columns); the kernels apply it to
+// the four words of a 128-bit LDS read.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#define GFQ_HD __host__ __device__ __forceinline__
+#include "gfq_field.h"
+
+namespace gfq {
+
+template <int Q> struct FT;
+
+// F_3 (Section 4.1).  Basis {1, -1}: phi_0 = [a = 1] = x0 ^ x1, phi_1 = [a = -1] = x1.
+// Table entries are binary residues mod 3; the accumulator is a carry-save pair mod 3 and
+// receives T[phi_0] and -T[phi_1] (the complement) per slab.
+template <> struct FT<3> {
+    static constexpr int P = 2, D = 2, PA = 4;
+    __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0] ^ x[1]; f[1] = x[1]; }
+    __device__ static void to_table(const u32 *x, u32 *t) { f3_to_bin(x[0], x[1], t); }
+    __device__ static void tadd(const u32 *a, const u32 *b, u32 *r) { f3b_add(a, b, r); }
+    __device__ static void tsub(const u32 *a, const u32 *b, u32 *r) { f3b_sub(a, b, r); }
+    __device__ static void acc_zero(u32 *c) { for (int i = 0; i < PA; i++) c[i] = 0u; }
+    __device__ static void accumulate(u32 *c, const u32 (*t)[P]) {
+        u32 *S = c, *K = c + 2;
+        csa_step<2>(S, K, t[0]);
+        csa_step_neg<2>(S, K, t[1]);
+    }
+    __device__ static void finish(const u32 *c, u32 *out) {
+        u32 v[2];
+        f3b_add(c, c + 2, v);
+        f3_from_bin(v, &out[0], &out[1]);
+    }
+    __device__ static void sadd(const u32 *a, const u32 *b, u32 *r) {
+        F3v z = f3_add(F3v{a[0], a[1]}, F3v{b[0], b[1]});
+        r[0] = z.u; r[1] = z.s;
+    }
+    __device__ static void scanon(u32 *) {}
+};
+
+// F_7 (Section 4.2).  Basis {1, 2, 4}, phi_d = plane d.  Doubling modulo 7 rotates the
+// planes, so alpha_d T[phi_d] costs nothing; the accumulator is a carry-save pair mod 7.
+template <> struct FT<7> {
+    static constexpr int P = 3, D = 3, PA = 6;
+    __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; f[2] = x[2]; }
+    __device__ static void to_table(const u32 *x, u32 *t) { t[0] = x[0]; t[1] = x[1]; t[2] = x[2]; }
+    __device__ static void tadd(const u32 *a, const u32 *b, u32 *r) {
+        P3v z = f7_add(P3v{a[0], a[1], a[2]}, P3v{b[0], b[1], b[2]});
+        r[0] = z.b0; r[1] = z.b1; r[2] = z.b2;
+    }
+    __device__ static void tsub(const u32 *a, const u32 *b, u32 *r) {
+        const u32 nb[3] = {~b[0], ~b[1], ~b[2]};
+        tadd(a, nb, r);
+    }
+    __device__ static void acc_zero(u32 *c) { for (int i = 0; i < PA; i++) c[i] = 0u; }
+    __device__ static void accumulate(u32 *c, const u32 (*t)[P]) {
+        u32 *S = c, *K = c + 3;
+        csa_step<3>(S, K, t[0]);
+        const u32 x1[3] = {t[1][2], t[1][0], t[1][1]};   // 2 t
+        csa_step<3>(S, K, x1);
+        const u32 x2[3] = {t[2][1], t[2][2], t[2][0]};   // 4 t
+        csa_step<3>(S, K, x2);
+    }
+    __device__ static void finish(const u32 *c, u32 *out) {
+        P3v z = f7_reduce(f7_add(P3v{c[0], c[1], c[2]}, P3v{c[3], c[4], c[5]}));
+        out[0] = z.b0; out[1] = z.b1; out[2] = z.b2;
+    }
+    __device__ static void sadd(const u32 *a, const u32 *b, u32 *r) { tadd(a, b, r); }
+    __device__ static void scanon(u32 *v) {
+        P3v z = f7_reduce(P3v{v[0], v[1], v[2]});
+        v[0] = z.b0; v[1] = z.b1; v[2] = z.b2;
+    }
+};
+
+// F_5 (Section 4.2).  Basis {1, 2, 4}, phi_d = plane d; table entries are 3-bit
+// representatives (4-bit sum, then fold5).  The accumulator works modulo 15 (4 planes per
+// half of the carry-save pair) and is reduced mod 5 once, at the end.
+template <> struct FT<5> {
+    static constexpr int P = 3, D = 3, PA = 8;
+    __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; f[2] = x[2]; }
+    __device__ static void to_table(const u32 *x, u32 *t) { t[0] = x[0]; t[1] = x[1]; t[2] = x[2]; }
+    __device__ static void tadd(const u32 *a, const u32 *b, u32 *r) {
+        P3v z = f5_add(P3v{a[0], a[1], a[2]}, P3v{b[0], b[1], b[2]});
+        r[0] = z.b0; r[1] = z.b1; r[2] = z.b2;
+    }
+    __device__ static void tsub(const u32 *a, const u32 *b, u32 *r) {
+        P3v nb = f5_neg(P3v{b[0], b[1], b[2]});
+        const u32 n[3] = {nb.b0, nb.b1, nb.b2};
+        tadd(a, n, r);
+    }
+    __device__ static void acc_zero(u32 *c) { for (int i = 0; i < PA; i++) c[i] = 0u; }
+    __device__ static void accumulate(u32 *c, const u32 (*t)[P]) {
+        u32 *S = c, *K = c + 4, x[4];
+        f5w_scaled(t[0], 1, x);
+        csa_step<4>(S, K, x);
+        f5w_scaled(t[1], 2, x);
+        csa_step<4>(S, K, x);
+        f5w_scaled(t[2], 4, x);
+        csa_step<4>(S, K, x);
+    }
+    __device__ static void finish(const u32 *c, u32 *out) {
+        P3v s = fold5(c[0], c[1], c[2], c[3]);
+        P3v k = fold5(c[4], c[5], c[6], c[7]);
+        P3v z = f5_reduce(f5_add(s, k));
+        out[0] = z.b0; out[1] = z.b1; out[2] = z.b2;
+    }
+    __device__ static void sadd(const u32 *a, const u32 *b, u32 *r) { tadd(a, b, r); }
+    __device__ static void scanon(u32 *v) {
+        P3v z = f5_reduce(P3v{v[0], v[1], v[2]});
+        v[0] = z.b0; v[1] = z.b1; v[2] = z.b2;
+    }
+};
+
+// GF(4) (Section 4.3).  Basis {1, x}, phi_d = c_d.  Per slab the row receives
+// T[phi_0] + x T[phi_1]; with x (c0 + c1 x) = c1 + (c0 + c1) x that is two XOR planes.
+template <> struct FT<4> {
+    static constexpr int P = 2, D = 2, PA = 2;
+    __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; }
+    __device__ static void to_table(const u32 *x, u32 *t) { t[0] = x[0]; t[1] = x[1]; }
+    __device__ static void tadd(const u32 *a, const u32 *b, u32 *r) { r[0] = a[0] ^ b[0]; r[1] = a[1] ^ b[1]; }
+    __device__ static void tsub(const u32 *a, const u32 *b, u32 *r) { tadd(a, b, r); }
+    __device__ static void acc_zero(u32 *c) { c[0] = c[1] = 0u; }
+    __device__ static void accumulate(u32 *c, const u32 (*t)[P]) {
+        c[0] = xor3(c[0], t[0][0], t[1][1]);
+        c[1] = xor3(c[1], t[0][1], t[1][0]) ^ t[1][1];
+    }
+    __device__ static void finish(const u32 *c, u32 *out) { out[0] = c[0]; out[1] = c[1]; }
+    __device__ static void sadd(const u32 *a, const u32 *b, u32 *r) { tadd(a, b, r); }
+    __device__ static void scanon(u32 *) {}
+};
+
+}  // namespace gfq

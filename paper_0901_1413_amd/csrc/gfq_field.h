@@ -18,7 +18,20 @@ namespace gfq {
 
 typedef uint32_t u32;
 
+// Three-input primitives.  In the device pass each is one v_bitop3_b32 (truth table over
+// operands (a, b, c) weighted 0xF0, 0xCC, 0xAA); the host pass spells them out so the
+// truth-table checks run the same formulas.  The "n" forms complement their third operand.
+#if defined(__HIP_DEVICE_COMPILE__)
+GFQ_HD u32 xor3(u32 a, u32 b, u32 c) { return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96); }
+GFQ_HD u32 maj3(u32 a, u32 b, u32 c) { return __builtin_amdgcn_bitop3_b32(a, b, c, 0xE8); }
+GFQ_HD u32 xor3n(u32 a, u32 b, u32 c) { return __builtin_amdgcn_bitop3_b32(a, b, c, 0x69); }
+GFQ_HD u32 maj3n(u32 a, u32 b, u32 c) { return __builtin_amdgcn_bitop3_b32(a, b, c, 0xD4); }
+#else
+GFQ_HD u32 xor3(u32 a, u32 b, u32 c) { return a ^ b ^ c; }
 GFQ_HD u32 maj3(u32 a, u32 b, u32 c) { return (a & b) | (c & (a | b)); }
+GFQ_HD u32 xor3n(u32 a, u32 b, u32 c) { return a ^ b ^ ~c; }
+GFQ_HD u32 maj3n(u32 a, u32 b, u32 c) { return (a & b) | (~c & (a | b)); }
+#endif
 
 // ---------------------------------------------------------------------------------------
 // F_3 (Section 4.1).  Planes (x0, x1): x0 marks a unit, x1 the sign; 0 = 00, 1 = 10,
@@ -63,9 +76,9 @@ GFQ_HD P4v add3x3(P3v a, P3v b) {
     P4v s;
     u32 c1 = a.b0 & b.b0;
     s.b0 = a.b0 ^ b.b0;
-    s.b1 = a.b1 ^ b.b1 ^ c1;
+    s.b1 = xor3(a.b1, b.b1, c1);
     u32 c2 = maj3(a.b1, b.b1, c1);
-    s.b2 = a.b2 ^ b.b2 ^ c2;
+    s.b2 = xor3(a.b2, b.b2, c2);
     s.b3 = maj3(a.b2, b.b2, c2);
     return s;
 }
@@ -140,5 +153,76 @@ GFQ_HD P3v f5_reduce(P3v a) {
 struct G4v { u32 c0, c1; };
 GFQ_HD G4v g4_add(G4v a, G4v b) { G4v r; r.c0 = a.c0 ^ b.c0; r.c1 = a.c1 ^ b.c1; return r; }
 GFQ_HD G4v g4_mulx(G4v a) { G4v r; r.c0 = a.c1; r.c1 = a.c0 ^ a.c1; return r; }
+
+
+// ---------------------------------------------------------------------------------------
+// Working representations used inside the product kernel (not storage formats).
+//
+// Binary residues modulo 2^NB - 1.  A value is an NB-bit integer taken modulo M = 2^NB - 1,
+// so the all-ones word also means 0 and a carry out of the top bit re-enters at bit 0
+// (2^NB = 1 mod M).  F_3 is worked modulo 3 = 2^2 - 1 and F_7 modulo 7 = 2^3 - 1; F_5 is
+// worked modulo 15 = 2^4 - 1, which 5 divides, and reduced mod 5 only at the end.
+//
+// Carry-save accumulation: a running sum is kept as two such integers (S, K) whose sum is
+// the value; adding one more integer X costs one full adder per bit, i.e. a three-input
+// XOR and a three-input majority per plane (one v_bitop3_b32 each), with no carry chain.
+// ---------------------------------------------------------------------------------------
+
+// One carry-save step modulo 2^NB - 1: (S, K) <- S + K + X.
+template <int NB> GFQ_HD void csa_step(u32 *S, u32 *K, const u32 *X) {
+    u32 c[NB];
+#pragma unroll
+    for (int i = 0; i < NB; i++) {
+        const u32 s = xor3(S[i], K[i], X[i]);
+        c[(i + 1) % NB] = maj3(S[i], K[i], X[i]);
+        S[i] = s;
+    }
+#pragma unroll
+    for (int i = 0; i < NB; i++) K[i] = c[i];
+}
+
+// The same step adding -X, i.e. the complement of X (negation modulo 2^NB - 1).
+template <int NB> GFQ_HD void csa_step_neg(u32 *S, u32 *K, const u32 *X) {
+    u32 c[NB];
+#pragma unroll
+    for (int i = 0; i < NB; i++) {
+        const u32 s = xor3n(S[i], K[i], X[i]);
+        c[(i + 1) % NB] = maj3n(S[i], K[i], X[i]);
+        S[i] = s;
+    }
+#pragma unroll
+    for (int i = 0; i < NB; i++) K[i] = c[i];
+}
+
+// F_3 in binary modulo 3: planes (b0, b1) of b0 + 2 b1, where 3 also means 0.
+// From the storage code (unit x0, sign x1): 1 = 10 -> 01 and -1 = 11 -> 10.
+GFQ_HD void f3_to_bin(u32 x0, u32 x1, u32 *b) { b[0] = x0 ^ x1; b[1] = x1; }
+
+// Addition modulo 3 of two 2-bit residues with the end-around carry.
+GFQ_HD void f3b_add(const u32 *a, const u32 *b, u32 *r) {
+    const u32 c1 = a[0] & b[0];
+    const u32 s0 = a[0] ^ b[0];
+    const u32 s1 = xor3(a[1], b[1], c1);
+    const u32 c2 = maj3(a[1], b[1], c1);          // carry of weight 4 = 1 (mod 3)
+    r[0] = s0 ^ c2;
+    r[1] = s1 ^ (s0 & c2);
+}
+
+// Negation modulo 2^NB - 1 is the complement: (2^NB - 1) - x.
+GFQ_HD void f3b_sub(const u32 *a, const u32 *b, u32 *r) {
+    const u32 nb[2] = {~b[0], ~b[1]};
+    f3b_add(a, nb, r);
+}
+
+// Back to the storage code: residue 0 (00 or 11) -> 00, 1 -> 10, 2 -> 11.
+GFQ_HD void f3_from_bin(const u32 *b, u32 *x0, u32 *x1) { *x0 = b[0] ^ b[1]; *x1 = b[1] & ~b[0]; }
+
+// F_5 addends in the modulo-15 working form: alpha * t for a 3-bit representative t and
+// alpha in {1, 2, 4}.  Doubling modulo 15 is a rotation of the four planes.
+GFQ_HD void f5w_scaled(const u32 *t, int alpha, u32 *x) {
+    if (alpha == 1) { x[0] = t[0]; x[1] = t[1]; x[2] = t[2]; x[3] = 0u; }
+    else if (alpha == 2) { x[0] = 0u; x[1] = t[0]; x[2] = t[1]; x[3] = t[2]; }
+    else { x[0] = t[2]; x[1] = 0u; x[2] = t[0]; x[3] = t[1]; }   // 4 t = t2 + 4 t0 + 8 t1 (mod 15)
+}
 
 }  // namespace gfq

@@ -8,15 +8,11 @@ namespace gfq {
 
 typedef uint32_t u32;
 
-constexpr int KMAX = 10;   // largest slab width
-constexpr int GMAX = 4;    // longest Gray walk kept in registers during the table build
+constexpr int KMAX = 10;          // largest slab width
+constexpr int NT_MM = 512;        // threads per product workgroup
+constexpr size_t TABLES_LDS = 131072;   // LDS for the two table buffers
 
 constexpr int log2_floor(int x) { return x <= 1 ? 0 : 1 + log2_floor(x / 2); }
-
-// LDS table layouts: tile width in 32-bit words (per plane) and copies per super-row.
-enum Layout { LAYOUT_W32_R2 = 0, LAYOUT_W32_R1 = 1, LAYOUT_W16_R1 = 2, LAYOUT_W8_R1 = 3 };
-inline int layout_twd(int lay) { return lay <= LAYOUT_W32_R1 ? 32 : (lay == LAYOUT_W16_R1 ? 16 : 8); }
-inline int layout_srb(int lay) { return lay == LAYOUT_W32_R2 ? 256 : layout_twd(lay) * 4; }
 
 struct MMArgs {
     const u32 *A;          // packed m x l
@@ -28,16 +24,68 @@ struct MMArgs {
     int S;                 // slabs = ceil(l / k)
     int slabs_per_split;   // slabs per grid.z slice
     size_t split_stride;   // words between consecutive partial products
-    int canon;             // 1: write canonical C; 0: write a raw partial product
+    u32 tb1;               // LDS offset of the second table (set by the launcher)
 };
 
 inline int planes_of(int q) { return (q == 3 || q == 4) ? 2 : 3; }
 inline int words_of(int64_t cols) { return (int)(((cols + 127) / 128) * 4); }
+inline int max_rows_per_lane(int q) { return q == 5 || q == 7 ? 4 : 8; }
 
-hipError_t launch_matmul(int q, const MMArgs &a, int layout, int rowsTile, hipStream_t st);
+// Table super-row bytes for field q and slab width k: the widest of 256, 128, 64, 32, 16
+// such that both table buffers fit TABLES_LDS (0 if none does).
+inline int srb_for(int q, int k) {
+    for (int srb = 256; srb >= 16; srb >>= 1)
+        if (2 * ((size_t)1 << k) * planes_of(q) * srb <= TABLES_LDS) return srb;
+    return 0;
+}
+inline int twd_of(int srb) { return srb >= 64 ? 16 : srb / 4; }   // tile words per plane
+
+// Everything a product launch needs, derived from (field, slab width, requested tile rows).
+struct MMPlan {
+    int srb;      // table super-row bytes
+    int twd;      // tile width in words per plane
+    int rep;      // copies of the tile row per super-row
+    int R;        // rows of C per lane (2, 4 or 8)
+    int TM;       // rows of C per workgroup
+    u32 tb1;      // LDS offset of the second table
+    size_t lds;   // dynamic LDS bytes
+};
+
+inline size_t mm_lds_bytes(int q, int k, int srb, int TM, u32 *tb1_out) {
+    const int P = planes_of(q), D = P;
+    const u32 tbytes = (u32)(1u << k) * P * srb;
+    u32 tb1 = 16;
+    while (tb1 < tbytes) tb1 <<= 1;
+    if (tb1_out) *tb1_out = tb1;
+    return (size_t)tb1 + tbytes + 2 * KMAX * P * twd_of(srb) * 4 + 3 * (size_t)TM * ((D + 1) / 2) * 4;
+}
+
+// srb = 0 when k is out of range; otherwise the largest R (rows per lane) not above the
+// request whose LDS footprint fits the 160 KiB of a workgroup.
+inline MMPlan mm_plan(int q, int k, int rowsTile) {
+    MMPlan p = {};
+    if (k < 1 || k > KMAX) return p;
+    p.srb = srb_for(q, k);
+    if (!p.srb) return p;
+    p.twd = twd_of(p.srb);
+    p.rep = p.srb / (4 * p.twd);
+    const int lpr = p.twd / 4;
+    int r = rowsTile * lpr / NT_MM;
+    r = r <= 2 ? 2 : (r <= 4 ? 4 : 8);
+    if (r > max_rows_per_lane(q)) r = max_rows_per_lane(q);
+    for (; r >= 2; r /= 2) {
+        p.R = r;
+        p.TM = NT_MM / lpr * r;
+        p.lds = mm_lds_bytes(q, k, p.srb, p.TM, &p.tb1);
+        if (p.lds <= 163840) return p;
+    }
+    p.srb = 0;
+    return p;
+}
+
+hipError_t launch_matmul(int q, const MMArgs &a, const MMPlan &plan, hipStream_t st);
 hipError_t launch_reduce(int q, const u32 *part, u32 *C, int m, int n, int Wn, int splits, size_t stride, hipStream_t st);
 hipError_t launch_pack(int q, const uint8_t *src, int64_t ld, u32 *dst, int rows, int cols, int W, hipStream_t st);
 hipError_t launch_unpack(int q, const u32 *src, uint8_t *dst, int64_t ld, int rows, int cols, int W, hipStream_t st);
-int rows_tile_of(int layout, int rowsTile);   // rows of C one workgroup really covers
 
 }  // namespace gfq

@@ -51,6 +51,9 @@ _SIGS = {
     "gfq_matmul_batched": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(Problem)]),
     "gfq_set_stream": (ctypes.c_int, [_VP]),
     "gfq_sync": (ctypes.c_int, []),
+    "gfq_set_timing": (ctypes.c_int, [ctypes.c_int]),
+    "gfq_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
+                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
     "gfq_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "gfq_last_hip_error": (ctypes.c_char_p, []),
 }
@@ -160,6 +163,20 @@ def matmul_batched(problems: Sequence[tuple]):
         arr[i] = Problem(q, m, l, n, A.data_ptr(), B.data_ptr(), C.data_ptr())
     _bind_stream()
     _check(load().gfq_matmul_batched(len(problems), arr), "gfq_matmul_batched")
+
+
+def set_timing(on: bool):
+    load().gfq_set_timing(1 if on else 0)
+
+
+def timing_read() -> dict:
+    """Summed kernel milliseconds and launch counts since the last read (needs set_timing)."""
+    pm, rm = ctypes.c_double(), ctypes.c_double()
+    pc, rc = ctypes.c_int(), ctypes.c_int()
+    _check(load().gfq_timing_read(ctypes.byref(pm), ctypes.byref(pc), ctypes.byref(rm), ctypes.byref(rc)),
+           "gfq_timing_read")
+    return {"product_ms": pm.value, "product_launches": pc.value, "reduce_ms": rm.value,
+            "reduce_launches": rc.value}
 
 
 def sync():

@@ -28,5 +28,34 @@ int main() {
         G4v s = g4_add(x, y), mx = g4_mulx(x);
         printf("g4 %u %u add %u mulx %u\n", a, b, bit(s.c0) | bit(s.c1) << 1, bit(mx.c0) | bit(mx.c1) << 1);
     }
+    // binary mod 3 working form
+    for (unsigned a = 0; a < 4; a++) for (unsigned b = 0; b < 4; b++) {
+        u32 x[2] = {a & 1, a >> 1}, y[2] = {b & 1, b >> 1}, r[2], d[2];
+        f3b_add(x, y, r); f3b_sub(x, y, d);
+        u32 c0, c1; f3_from_bin(x, &c0, &c1);
+        printf("f3b %u %u add %u sub %u tocode %u %u\n", a, b, bit(r[0]) | bit(r[1]) << 1, bit(d[0]) | bit(d[1]) << 1, bit(c0), bit(c1));
+    }
+    for (int i = 0; i < 3; i++) { u32 b[2]; f3_to_bin(codes[i][0], codes[i][1], b); printf("f3tobin %u %u %u\n", codes[i][0], codes[i][1], bit(b[0]) | bit(b[1]) << 1); }
+    // carry-save steps: every (S, K, X) for NB = 2, 3, 4
+    for (unsigned S = 0; S < 16; S++) for (unsigned K = 0; K < 16; K++) for (unsigned X = 0; X < 16; X++) {
+        u32 s4[4], k4[4], x4[4];
+        for (int i = 0; i < 4; i++) { s4[i] = (S >> i) & 1; k4[i] = (K >> i) & 1; x4[i] = (X >> i) & 1; }
+        u32 s3[3] = {s4[0], s4[1], s4[2]}, k3[3] = {k4[0], k4[1], k4[2]}, x3[3] = {x4[0], x4[1], x4[2]};
+        u32 s2[2] = {s4[0], s4[1]}, k2[2] = {k4[0], k4[1]}, x2[2] = {x4[0], x4[1]};
+        u32 n2s[2] = {s2[0], s2[1]}, n2k[2] = {k2[0], k2[1]};
+        csa_step<4>(s4, k4, x4); csa_step<3>(s3, k3, x3); csa_step<2>(s2, k2, x2);
+        csa_step_neg<2>(n2s, n2k, x2);
+        unsigned v4s = 0, v4k = 0, v3s = 0, v3k = 0, v2s = 0, v2k = 0;
+        for (int i = 0; i < 4; i++) { v4s |= bit(s4[i]) << i; v4k |= bit(k4[i]) << i; }
+        for (int i = 0; i < 3; i++) { v3s |= bit(s3[i]) << i; v3k |= bit(k3[i]) << i; }
+        for (int i = 0; i < 2; i++) { v2s |= bit(s2[i]) << i; v2k |= bit(k2[i]) << i; }
+        unsigned vns = bit(n2s[0]) | bit(n2s[1]) << 1, vnk = bit(n2k[0]) | bit(n2k[1]) << 1;
+        printf("csa %u %u %u  %u %u  %u %u  %u %u  %u %u\n", S, K, X, v4s, v4k, v3s, v3k, v2s, v2k, vns, vnk);
+    }
+    for (unsigned t = 0; t < 8; t++) for (int al = 1; al <= 4; al *= 2) {
+        u32 tt[3] = {t & 1, (t >> 1) & 1, (t >> 2) & 1}, x[4];
+        f5w_scaled(tt, al, x);
+        printf("f5w %u %d %u\n", t, al, bit(x[0]) | bit(x[1]) << 1 | bit(x[2]) << 2 | bit(x[3]) << 3);
+    }
     return 0;
 }

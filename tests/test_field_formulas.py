@@ -69,3 +69,30 @@ def test_gf4(table):
         a, b, s, mx = map(int, (r[1], r[2], r[4], r[6]))
         assert s == a ^ b
         assert mx == mul[2][a]
+
+
+def test_f3_binary_working_form(table):
+    for r in (r for r in table if r[0] == "f3b"):
+        a, b, add, sub, c0, c1 = int(r[1]), int(r[2]), int(r[4]), int(r[6]), int(r[8]), int(r[9])
+        assert add % 3 == (a + b) % 3 and add < 4
+        assert sub % 3 == (a - b) % 3 and sub < 4
+        assert F3_VAL[(c0, c1)] == a % 3
+    for r in (r for r in table if r[0] == "f3tobin"):
+        assert int(r[3]) == F3_VAL[(int(r[1]), int(r[2]))]
+
+
+def test_carry_save_steps(table):
+    rows = [r for r in table if r[0] == "csa"]
+    assert len(rows) == 16 ** 3
+    for r in rows:
+        S, K, X, s4, k4, s3, k3, s2, k2, n2, m2 = map(int, r[1:])
+        assert (s4 + k4) % 15 == (S + K + X) % 15
+        assert (s3 + k3) % 7 == ((S & 7) + (K & 7) + (X & 7)) % 7
+        assert (s2 + k2) % 3 == ((S & 3) + (K & 3) + (X & 3)) % 3
+        assert (n2 + m2) % 3 == ((S & 3) + (K & 3) - (X & 3)) % 3
+
+
+def test_f5_scaled_addends(table):
+    for r in (r for r in table if r[0] == "f5w"):
+        t, al, x = int(r[1]), int(r[2]), int(r[3])
+        assert x % 15 == (al * t) % 15

@@ -73,7 +73,7 @@ def test_matmul_every_k(gfq_gpu, q, k):
 
 
 @pytest.mark.parametrize("q", FIELDS)
-@pytest.mark.parametrize("rows,split", [(128, 1), (256, 1), (512, 1), (128, 3), (256, 7), (512, 64)])
+@pytest.mark.parametrize("rows,split", [(256, 1), (512, 1), (1024, 1), (2048, 1), (256, 3), (512, 7), (1024, 64)])
 def test_matmul_tiles_and_splits(gfq_gpu, q, rows, split):
     A, B = inputs.pair(q, 600, 700, 300, cfg=204, idx=rows + split)
     check(gfq_gpu, q, A, B, rows=rows, split=split)
