@@ -8,7 +8,7 @@
 #include <mutex>
 #include <vector>
 
-#include "../../include/gfq.h"
+#include "gfq.h"
 #include "gfq_internal.h"
 
 using namespace gfq;

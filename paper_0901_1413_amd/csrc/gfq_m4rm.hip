@@ -19,8 +19,8 @@
 //   build   the table of slab s+1 into the idle table buffer, in Gray-code order;
 //   gather  for every row, D table rows of slab s, alpha_d-scaled into the accumulator;
 //   barrier.
-// The build of slab s+1 and the gathers of slab s are independent, so their latencies
-// overlap inside every wave.
+// The build of slab s+1 and the gathers of slab s are independent: half of the waves
+// build first, the other half gather first, so every SIMD overlaps the two.
 //
 // LDS table layout.  One (entry, plane) "super-row" is SRB bytes holding REP copies of
 // the TWD-word tile row.  gfx950 serves a 128-bit LDS read of 16 lanes from 64 four-byte
@@ -254,6 +254,8 @@ __global__ __launch_bounds__(NT) void m4rm_kernel(MMArgs a) {
         }
     };
 
+    const bool build_first = (tid / 64) < (NT / 128);   // first half of the waves
+
     // ---- prologue: stage slabs s0 and s0+1, build slab s0 ----
     uint4 bpre = make_uint4(0u, 0u, 0u, 0u);
     if (s_begin < s_end) {
@@ -278,8 +280,17 @@ __global__ __launch_bounds__(NT) void m4rm_kernel(MMArgs a) {
             advance(s + 3);
         }
         if (s + 3 < s_end) bpre = load_b(s + 3);
-        if (s + 1 < s_end) build(s + 1);
-        gather(s);
+        // The two waves sharing a SIMD (w and w + NT/256) run the independent build and
+        // gather phases in opposite orders, so one wave's VALU-heavy gathers fill the other
+        // wave's waits on the table build's chain of LDS round trips.
+#pragma unroll 1
+        for (int phase = 0; phase < 2; phase++) {
+            if ((phase == 0) == build_first) {
+                if (s + 1 < s_end) build(s + 1);
+            } else {
+                gather(s);
+            }
+        }
         __syncthreads();
     }
 

@@ -56,68 +56,116 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const u32 *part, u
 }
 
 // ---------------------------------------------------------------------------------------
-// Pack / unpack.  One wave per (row, 64 columns): each lane takes one element, and a
-// wave-wide ballot of one plane bit yields that plane's 64-bit word pair.
+// Pack / unpack.  One thread per (row, 32-column word): it owns bit j of that word in
+// every plane for the 32 elements of its columns.
 // ---------------------------------------------------------------------------------------
-template <int Q>
-__device__ __forceinline__ void encode(u32 v, u32 *bits) {
+
+// Plane bits of the residue of byte v, bit p of the code at bit 8p (p < P).
+template <int Q> __device__ __forceinline__ u32 encode_spread(u32 v) {
     if (Q == 3) {
-        v %= 3u;
-        bits[0] = v != 0u;
-        bits[1] = v == 2u;
-    } else if (Q == 4) {
-        bits[0] = v & 1u;
-        bits[1] = (v >> 1) & 1u;
-    } else {
-        v %= (u32)Q;
-        bits[0] = v & 1u; bits[1] = (v >> 1) & 1u; bits[2] = (v >> 2) & 1u;
+        v %= 3u;                                  // 0 = 00, 1 = 10, -1 = 11 (unit, sign)
+        return (v != 0u ? 1u : 0u) | (v == 2u ? 1u << 8 : 0u);
     }
+    if (Q == 4) return (v & 1u) | ((v >> 1) & 1u) << 8;
+    v %= (u32)Q;                                  // binary digits (F_5, F_7)
+    return (v & 1u) | ((v >> 1) & 1u) << 8 | ((v >> 2) & 1u) << 16;
 }
 
 template <int Q>
-__global__ __launch_bounds__(256) void pack_kernel(const uint8_t *src, int64_t ld, u32 *dst, int rows, int cols, int W) {
+__global__ __launch_bounds__(256) void pack_kernel(const uint8_t *src, int64_t ld, u32 *dst, int rows, int cols, int W,
+                                                   int aligned) {
     constexpr int P = FT<Q>::P;
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    const int chunks = W / 2;                    // 64-column chunks per row
-    const int64_t items = (int64_t)rows * chunks;
-    for (int64_t it = wave; it < items; it += nwaves) {
-        const int row = (int)(it / chunks), ch = (int)(it % chunks);
-        const int col = ch * 64 + lane;
-        u32 v = col < cols ? src[(int64_t)row * ld + col] : 0u;
-        u32 bits[P];
-        encode<Q>(v, bits);
-        if (col >= cols) {
-#pragma unroll
-            for (int p = 0; p < P; p++) bits[p] = 0u;
-        }
-#pragma unroll
-        for (int p = 0; p < P; p++) {
-            const uint64_t b = __ballot(bits[p] != 0u);
-            if (lane == 0) {
-                uint2 wv = make_uint2((u32)b, (u32)(b >> 32));
-                *reinterpret_cast<uint2 *>(dst + ((size_t)row * P + p) * W + ch * 2) = wv;
-            }
-        }
-    }
-}
-
-template <int Q>
-__global__ __launch_bounds__(256) void unpack_kernel(const u32 *src, uint8_t *dst, int64_t ld, int rows, int cols, int W) {
-    constexpr int P = FT<Q>::P;
-    const int64_t total = (int64_t)rows * cols;
+    __shared__ u32 enc[256];
+    enc[threadIdx.x] = encode_spread<Q>(threadIdx.x);
+    __syncthreads();
+    const int64_t total = (int64_t)rows * W;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
          idx += (int64_t)gridDim.x * blockDim.x) {
-        const int row = (int)(idx / cols), col = (int)(idx % cols);
-        u32 b[P];
+        const int row = (int)(idx / W), w = (int)(idx % W);
+        const int c0 = w * 32;
+        u32 b[8];
+        const uint8_t *rp = src + (int64_t)row * ld + c0;
+        if (aligned && c0 + 32 <= cols) {
+            const uint4 x = *reinterpret_cast<const uint4 *>(rp);
+            const uint4 y = *reinterpret_cast<const uint4 *>(rp + 16);
+            b[0] = x.x; b[1] = x.y; b[2] = x.z; b[3] = x.w; b[4] = y.x; b[5] = y.y; b[6] = y.z; b[7] = y.w;
+        } else {
 #pragma unroll
-        for (int p = 0; p < P; p++) b[p] = (src[((size_t)row * P + p) * W + (col >> 5)] >> (col & 31)) & 1u;
-        u32 v;
-        if (Q == 3) v = b[0] ? (b[1] ? 2u : 1u) : 0u;
-        else if (Q == 4) v = b[0] | (b[1] << 1);
-        else v = (b[0] | (b[1] << 1) | (b[2] << 2)) % (u32)Q;
-        dst[(int64_t)row * ld + col] = (uint8_t)v;
+            for (int i = 0; i < 8; i++) {
+                u32 v = 0u;
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    const int c = c0 + 4 * i + j;
+                    v |= (c < cols ? (u32)rp[4 * i + j] : 0u) << (8 * j);   // 0 encodes as 0
+                }
+                b[i] = v;
+            }
+        }
+        u32 out[P];
+#pragma unroll
+        for (int p = 0; p < P; p++) out[p] = 0u;
+#pragma unroll
+        for (int g = 0; g < 4; g++) {             // eight elements per group
+            u32 acc = 0u;
+#pragma unroll
+            for (int i = 0; i < 8; i++) {
+                const u32 byte = (b[2 * g + (i >> 2)] >> (8 * (i & 3))) & 0xffu;
+                acc |= enc[byte] << i;
+            }
+#pragma unroll
+            for (int p = 0; p < P; p++) out[p] |= ((acc >> (8 * p)) & 0xffu) << (8 * g);
+        }
+#pragma unroll
+        for (int p = 0; p < P; p++) dst[((size_t)row * P + p) * W + w] = out[p];
+    }
+}
+
+// Four bits (n < 16) to bit 0 of four bytes: n * (1 + 2^7 + 2^14 + 2^21) has no carries.
+__device__ __forceinline__ u32 spread4(u32 n) { return (n * 0x00204081u) & 0x01010101u; }
+
+template <int Q>
+__global__ __launch_bounds__(256) void unpack_kernel(const u32 *src, uint8_t *dst, int64_t ld, int rows, int cols, int W,
+                                                     int aligned) {
+    constexpr int P = FT<Q>::P;
+    const int Wc = (cols + 31) / 32;
+    const int64_t total = (int64_t)rows * Wc;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int row = (int)(idx / Wc), w = (int)(idx % Wc);
+        u32 pw[P];
+#pragma unroll
+        for (int p = 0; p < P; p++) pw[p] = src[((size_t)row * P + p) * W + w];
+        u32 o[8];
+#pragma unroll
+        for (int g = 0; g < 8; g++) {             // four elements per group, one per byte
+            u32 code = 0u;
+#pragma unroll
+            for (int p = 0; p < P; p++) code |= spread4((pw[p] >> (4 * g)) & 0xfu) << p;
+            u32 v;
+            if (Q == 3) {
+                v = (code & 0x01010101u) + ((code >> 1) & 0x01010101u);            // unit + sign
+            } else if (Q == 4) {
+                v = code;
+            } else if (Q == 7) {
+                const u32 is7 = code & (code >> 1) & (code >> 2) & 0x01010101u;    // 7 = 0
+                v = code ^ (is7 * 7u);
+            } else {
+                const u32 ge5 = (code >> 2) & (code | (code >> 1)) & 0x01010101u;  // 5, 6, 7
+                v = code - ge5 * 5u;
+            }
+            o[g] = v;
+        }
+        uint8_t *rp = dst + (int64_t)row * ld + w * 32;
+        if (aligned && w * 32 + 32 <= cols) {
+            *reinterpret_cast<uint4 *>(rp) = make_uint4(o[0], o[1], o[2], o[3]);
+            *reinterpret_cast<uint4 *>(rp + 16) = make_uint4(o[4], o[5], o[6], o[7]);
+        } else {
+#pragma unroll
+            for (int g = 0; g < 8; g++)
+#pragma unroll
+                for (int j = 0; j < 4; j++)
+                    if (w * 32 + 4 * g + j < cols) rp[4 * g + j] = (uint8_t)(o[g] >> (8 * j));
+        }
     }
 }
 
@@ -141,24 +189,25 @@ static unsigned grid_for(int64_t work, int per_block) {
 }
 
 hipError_t launch_pack(int q, const uint8_t *src, int64_t ld, u32 *dst, int rows, int cols, int W, hipStream_t st) {
-    const int64_t items = (int64_t)rows * (W / 2);
-    dim3 grid(grid_for(items, 4));
+    const int aligned = ((uintptr_t)src % 16 == 0) && (ld % 16 == 0);
+    dim3 grid(grid_for((int64_t)rows * W, 256));
     switch (q) {
-    case 3: hipLaunchKernelGGL(pack_kernel<3>, grid, dim3(256), 0, st, src, ld, dst, rows, cols, W); break;
-    case 4: hipLaunchKernelGGL(pack_kernel<4>, grid, dim3(256), 0, st, src, ld, dst, rows, cols, W); break;
-    case 5: hipLaunchKernelGGL(pack_kernel<5>, grid, dim3(256), 0, st, src, ld, dst, rows, cols, W); break;
-    default: hipLaunchKernelGGL(pack_kernel<7>, grid, dim3(256), 0, st, src, ld, dst, rows, cols, W); break;
+    case 3: hipLaunchKernelGGL(pack_kernel<3>, grid, dim3(256), 0, st, src, ld, dst, rows, cols, W, aligned); break;
+    case 4: hipLaunchKernelGGL(pack_kernel<4>, grid, dim3(256), 0, st, src, ld, dst, rows, cols, W, aligned); break;
+    case 5: hipLaunchKernelGGL(pack_kernel<5>, grid, dim3(256), 0, st, src, ld, dst, rows, cols, W, aligned); break;
+    default: hipLaunchKernelGGL(pack_kernel<7>, grid, dim3(256), 0, st, src, ld, dst, rows, cols, W, aligned); break;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_unpack(int q, const u32 *src, uint8_t *dst, int64_t ld, int rows, int cols, int W, hipStream_t st) {
-    dim3 grid(grid_for((int64_t)rows * cols, 256));
+    const int aligned = ((uintptr_t)dst % 16 == 0) && (ld % 16 == 0);
+    dim3 grid(grid_for((int64_t)rows * ((cols + 31) / 32), 256));
     switch (q) {
-    case 3: hipLaunchKernelGGL(unpack_kernel<3>, grid, dim3(256), 0, st, src, dst, ld, rows, cols, W); break;
-    case 4: hipLaunchKernelGGL(unpack_kernel<4>, grid, dim3(256), 0, st, src, dst, ld, rows, cols, W); break;
-    case 5: hipLaunchKernelGGL(unpack_kernel<5>, grid, dim3(256), 0, st, src, dst, ld, rows, cols, W); break;
-    default: hipLaunchKernelGGL(unpack_kernel<7>, grid, dim3(256), 0, st, src, dst, ld, rows, cols, W); break;
+    case 3: hipLaunchKernelGGL(unpack_kernel<3>, grid, dim3(256), 0, st, src, dst, ld, rows, cols, W, aligned); break;
+    case 4: hipLaunchKernelGGL(unpack_kernel<4>, grid, dim3(256), 0, st, src, dst, ld, rows, cols, W, aligned); break;
+    case 5: hipLaunchKernelGGL(unpack_kernel<5>, grid, dim3(256), 0, st, src, dst, ld, rows, cols, W, aligned); break;
+    default: hipLaunchKernelGGL(unpack_kernel<7>, grid, dim3(256), 0, st, src, dst, ld, rows, cols, W, aligned); break;
     }
     return hipGetLastError();
 }

@@ -122,6 +122,7 @@ def unpack(q: int, Pk, rows: int, cols: int, out=None):
     import torch
     if out is None:
         out = torch.empty((rows, cols), dtype=torch.uint8, device=Pk.device)
+    assert out.dim() == 2 and out.stride(1) == 1 and out.dtype == torch.uint8
     _bind_stream()
     _check(load().gfq_unpack(q, rows, cols, _VP(Pk.data_ptr()), _VP(out.data_ptr()), max(out.stride(0), cols)),
            "gfq_unpack")

@@ -149,3 +149,22 @@ def test_c1_f3_512(gfq_gpu):
     """F_3, A and B 512 x 512 uniform: the whole product against the oracle."""
     A, B = inputs.pair(3, 512, 512, 512, cfg=1)
     check(gfq_gpu, 3, A, B)
+
+
+@pytest.mark.parametrize("q", FIELDS)
+def test_pack_unpack_strided_and_offset(gfq_gpu, q):
+    """Leading dimensions above the column count and sources/destinations that are not
+    16-byte aligned take the byte-wise path; aligned ones take the 128-bit path."""
+    import torch
+    g = gfq_gpu
+    big = inputs.matrix(q, 37, 300, 208, q)
+    for c0, cols in ((0, 256), (1, 255), (3, 129), (16, 64), (5, 33)):
+        X = dev(big)[:, c0:c0 + cols]                 # ld = 300, offset c0
+        P = g.pack(q, X)
+        want = oracle.pack(q, big[:, c0:c0 + cols]).view(np.uint8).reshape(-1)
+        assert np.array_equal(P.cpu().numpy()[:want.size], want), (c0, cols)
+        out = torch.full((37, 320), 0xEE, dtype=torch.uint8, device="cuda")
+        g.unpack(q, P, 37, cols, out=out[:, 7:7 + cols])
+        o = out.cpu().numpy()
+        assert np.array_equal(o[:, 7:7 + cols], big[:, c0:c0 + cols]), (c0, cols)
+        assert (o[:, :7] == 0xEE).all() and (o[:, 7 + cols:] == 0xEE).all()   # nothing outside
