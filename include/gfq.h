@@ -110,11 +110,30 @@ typedef struct {
     void *C;
 } gfq_problem;
 
-/* Run count independent products (fields and shapes may differ) as one persistent launch
- * that drains a device work queue of (product, row tile, column tile, slab range) items.
- * problems is a host array.  Each product obeys the gfq_matmul rules; a validation error
- * in any product rejects the whole batch before anything is launched. */
+/* Run count independent products (fields and shapes may differ) as one launch per
+ * (field, tile height) whose workgroups take (product, row tile, column tile) items from a
+ * longest-first work list.  problems is a host array.  Each product obeys the gfq_matmul
+ * rules; a validation error in any product rejects the whole batch before anything is
+ * launched.  Equivalent to gfq_batch_create + gfq_batch_launch; the batch's descriptors are
+ * released by a later call or gfq_sync once the launch has finished. */
 int gfq_matmul_batched(int count, const gfq_problem *problems);
+
+/* A prepared batch: products, launch parameters and work lists on the device.  Create it
+ * once for a set of products whose operand pointers stay valid, launch it any number of
+ * times.  gfq_batch_create validates every product (any error rejects the batch), chooses
+ * each product's slab width and tile height (from the tuning cache when it holds the
+ * product's size class), orders each (field, tile height) list of (product, row tile,
+ * column tile) items longest first and uploads the descriptors; it synchronises.
+ * gfq_batch_launch enqueues, on the calling thread's stream, one launch per list (a
+ * workgroup per item) and allocates nothing, so it may be captured into a graph.
+ * gfq_batch_times waits for that stream and writes, per product, the microseconds from the
+ * start of the most recent launch to the completion of the product's last tile.
+ * gfq_batch_destroy waits for the device and frees everything. */
+typedef struct gfq_batch gfq_batch;
+int gfq_batch_create(int count, const gfq_problem *problems, gfq_batch **out);
+int gfq_batch_launch(gfq_batch *batch);
+int gfq_batch_times(gfq_batch *batch, double *completion_us);
+int gfq_batch_destroy(gfq_batch *batch);
 
 /* Stream for subsequent calls made by this host thread (a hipStream_t; NULL = default). */
 int gfq_set_stream(void *hip_stream);

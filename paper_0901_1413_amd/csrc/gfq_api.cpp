@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "gfq.h"
+#include "gfq_host.h"
 #include "gfq_internal.h"
 
 using namespace gfq;
@@ -18,10 +19,6 @@ namespace {
 thread_local hipStream_t t_stream = nullptr;
 thread_local char t_hip_error[256] = "";
 
-int hip_fail(hipError_t e, const char *what) {
-    snprintf(t_hip_error, sizeof t_hip_error, "%s: %s", what, hipGetErrorString(e));
-    return GFQ_EHIP;
-}
 
 bool valid_field(int q) { return q == 3 || q == 4 || q == 5 || q == 7; }
 
@@ -103,7 +100,34 @@ int check_config(int q, const gfq_config &c) {
     return GFQ_OK;
 }
 
-int validate_mm(int q, int64_t m, int64_t l, int64_t n, const void *A, const void *B, void *C) {
+// Batches launched by gfq_matmul_batched stay alive until their launch has completed;
+// each call (and gfq_sync) releases the ones whose completion event has fired.
+struct PendingBatch { gfq_batch *b; hipEvent_t done; };
+thread_local std::vector<PendingBatch> t_pending;
+
+void release_finished(bool wait) {
+    std::vector<PendingBatch> keep;
+    for (PendingBatch &p : t_pending) {
+        hipError_t q = wait ? hipEventSynchronize(p.done) : hipEventQuery(p.done);
+        if (q == hipSuccess) {
+            (void)hipEventDestroy(p.done);
+            gfq_batch_destroy(p.b);
+        } else {
+            keep.push_back(p);
+        }
+    }
+    t_pending.swap(keep);
+}
+}  // namespace
+
+int gfq::hip_fail(hipError_t e, const char *what) {
+    snprintf(t_hip_error, sizeof t_hip_error, "%s: %s", what, hipGetErrorString(e));
+    return GFQ_EHIP;
+}
+
+hipStream_t gfq::current_stream() { return t_stream; }
+
+int gfq::validate_mm(int q, int64_t m, int64_t l, int64_t n, const void *A, const void *B, void *C) {
     if (!valid_field(q)) return GFQ_EFIELD;
     if (m < 0 || l < 0 || n < 0 || l >= GFQ_MAX_DIM || m >= ((int64_t)1 << 28) || n >= ((int64_t)1 << 28))
         return GFQ_EDIM;
@@ -116,7 +140,6 @@ int validate_mm(int q, int64_t m, int64_t l, int64_t n, const void *A, const voi
     return GFQ_OK;
 }
 
-}  // namespace
 
 extern "C" {
 
@@ -132,6 +155,7 @@ int gfq_set_stream(void *s) {
 
 int gfq_sync(void) {
     hipError_t e = hipStreamSynchronize(t_stream);
+    release_finished(false);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "asynchronous error");
@@ -226,7 +250,7 @@ int gfq_choose_config(int q, int64_t m, int64_t l, int64_t n, gfq_config *out) {
         const MMPlan p = mm_plan(q, kk, rows);
         if (!p.srb) continue;
         const int64_t tiles = ctiles * ((m + p.TM - 1) / p.TM);
-        int64_t split = tiles >= 256 ? 1 : (256 + tiles - 1) / tiles;
+        int64_t split = (tiles >= 256 || tiles == 0) ? 1 : (256 + tiles - 1) / tiles;   // m or n = 0: no tiles
         split = std::max<int64_t>(1, std::min<int64_t>({split, std::max<int64_t>(1, S / 32), 64}));
         const int64_t rounds = (tiles * split + 255) / 256;
         // relative time: rounds x rows x slabs per slice x (accumulate + table build)
@@ -299,21 +323,27 @@ int gfq_matmul(int q, int64_t m, int64_t l, int64_t n, const void *A, const void
     return gfq_matmul_config(q, m, l, n, A, B, C, nullptr);
 }
 
+
 int gfq_matmul_batched(int count, const gfq_problem *problems) {
     if (count < 0) return GFQ_EINVAL;
     if (count == 0) return GFQ_OK;
     if (!problems) return GFQ_ENULL;
-    for (int i = 0; i < count; i++) {
-        const gfq_problem &p = problems[i];
-        int st = validate_mm(p.q, p.m, p.l, p.n, p.A, p.B, p.C);
-        if (st != GFQ_OK) return st;
+    release_finished(false);
+    gfq_batch *b = nullptr;
+    int st = gfq_batch_create(count, problems, &b);
+    if (st != GFQ_OK) return st;
+    st = gfq_batch_launch(b);
+    hipEvent_t done = nullptr;
+    hipError_t e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(done, t_stream);
+    if (e != hipSuccess) {
+        if (done) (void)hipEventDestroy(done);
+        (void)hipStreamSynchronize(t_stream);
+        gfq_batch_destroy(b);
+        return st != GFQ_OK ? st : hip_fail(e, "batch completion event");
     }
-    for (int i = 0; i < count; i++) {
-        const gfq_problem &p = problems[i];
-        int st = gfq_matmul(p.q, p.m, p.l, p.n, p.A, p.B, p.C);
-        if (st != GFQ_OK) return st;
-    }
-    return GFQ_OK;
+    t_pending.push_back({b, done});
+    return st;
 }
 
 }  // extern "C"

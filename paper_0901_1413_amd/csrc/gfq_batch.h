@@ -1,0 +1,34 @@
+// gfq_batch.h -- device-side descriptors of a batched launch (shared by the work-list
+// kernel and the host code that builds the lists).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gfq_internal.h"
+
+namespace gfq {
+
+struct BatchProd {
+    MMArgs a;              // the product, as a single-product launch would see it (split 1)
+    u32 tiles;             // row tiles x column tiles
+    u32 pad;
+};
+
+struct BatchItem {
+    u32 prod;              // index into the product table
+    uint16_t tx, ty;       // column tile, row tile
+};
+
+struct BatchList {
+    const BatchProd *prods;
+    const BatchItem *items;            // this list's items, longest first (one per workgroup)
+    u32 *prod_done;                    // tiles finished per product (cleared on completion)
+    unsigned long long *prod_time;     // completion time per product (100 MHz clock)
+};
+
+// Work-list kernel for field q with R rows per lane (256-byte super-rows, 16-word tiles).
+const void *batched_kernel(int q, int R);
+hipError_t launch_batched(int q, int R, const BatchList &bl, int items, size_t lds, hipStream_t st);
+hipError_t launch_batch_stamp(unsigned long long *t, hipStream_t st);
+
+}  // namespace gfq

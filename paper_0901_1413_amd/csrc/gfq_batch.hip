@@ -1,0 +1,64 @@
+// gfq_batch.hip -- many independent products in one launch per (field, tile height): the
+// grid is a work list of (product, row tile, column tile) items, longest first.
+//
+// Each product keeps its own shape and slab width k; the items of one list share a field
+// and a tile height (rows per lane R), so one kernel instance serves them.  Workgroup b
+// takes item b and runs the tile with the same body as the single-product kernel; the
+// hardware dispatcher hands items to compute units as they free up, in list order, so the
+// longest items start first and the tail of the launch is short.  The workgroup that
+// finishes a product's last tile stamps the product's completion time (100 MHz constant
+// clock) and clears the product's tile count, so the same lists can be launched again.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gfq_batch.h"
+#include "gfq_m4rm_tile.h"
+
+namespace gfq {
+
+template <int Q, int TWD, int REP, int R, int NT>
+__global__ __launch_bounds__(NT) void m4rm_list_kernel(BatchList bl) {
+    const BatchItem item = bl.items[blockIdx.x];
+    const MMArgs a = bl.prods[item.prod].a;
+    m4rm_tile<Q, TWD, REP, R, NT>(a, item.tx, item.ty, 0);
+    __syncthreads();                             // every thread of the tile has stored
+    if (threadIdx.x == 0) {
+        const u32 d = atomicAdd(&bl.prod_done[item.prod], 1u);
+        if (d + 1 == bl.prods[item.prod].tiles) {
+            bl.prod_time[item.prod] = __builtin_amdgcn_s_memrealtime();
+            bl.prod_done[item.prod] = 0u;
+        }
+    }
+}
+
+// Start of a batch launch on the same clock (completion times are relative to it).
+__global__ void batch_stamp_kernel(unsigned long long *t) {
+    if (threadIdx.x == 0) t[0] = __builtin_amdgcn_s_memrealtime();
+}
+
+template <int Q, int R>
+static const void *list_kernel_ptr() {
+    return (const void *)m4rm_list_kernel<Q, 16, 4, R, NT_MM>;
+}
+
+const void *batched_kernel(int q, int R) {
+    switch (q) {
+    case 3: return R == 2 ? list_kernel_ptr<3, 2>() : list_kernel_ptr<3, 8>();
+    case 4: return R == 2 ? list_kernel_ptr<4, 2>() : list_kernel_ptr<4, 8>();
+    case 5: return list_kernel_ptr<5, 2>();      // four rows per lane would spill here
+    default: return R == 2 ? list_kernel_ptr<7, 2>() : list_kernel_ptr<7, 4>();
+    }
+}
+
+hipError_t launch_batched(int q, int R, const BatchList &bl, int items, size_t lds, hipStream_t st) {
+    const void *k = batched_kernel(q, R);
+    void *args[] = {(void *)&bl};
+    return hipLaunchKernel(k, dim3(items), dim3(NT_MM), args, lds, st);
+}
+
+hipError_t launch_batch_stamp(unsigned long long *t, hipStream_t st) {
+    hipLaunchKernelGGL(batch_stamp_kernel, dim3(1), dim3(64), 0, st, t);
+    return hipGetLastError();
+}
+
+}  // namespace gfq

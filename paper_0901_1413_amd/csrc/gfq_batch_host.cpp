@@ -1,0 +1,194 @@
+// gfq_batch_host.cpp -- building, launching and timing batches of products (the host side
+// of gfq_batch.hip): per-product launch parameters, work lists ordered longest first and
+// one device allocation for all descriptors.  A launch is a start stamp and one work-list
+// kernel per (field, tile height) on the caller's stream; it allocates nothing, so a
+// caller may capture it into a graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "gfq.h"
+#include "gfq_batch.h"
+#include "gfq_host.h"
+
+using namespace gfq;
+
+namespace {
+
+struct Group {
+    int q = 0, R = 0;
+    std::vector<BatchItem> items;
+    std::vector<double> cost;
+    int kmax = 1;
+    size_t lds = 0;
+    size_t item_off = 0;   // index of the group's first item in the device item array
+};
+
+int group_index(int q, int R) {
+    const int qi = q == 3 ? 0 : (q == 4 ? 1 : (q == 5 ? 2 : 3));
+    return qi * 2 + (R == 2 ? 0 : 1);
+}
+
+}  // namespace
+
+struct gfq_batch {
+    int count = 0;
+    int device = 0;
+    std::vector<Group> groups;
+    void *mem = nullptr;
+    BatchProd *prods = nullptr;
+    BatchItem *items = nullptr;
+    u32 *prod_done = nullptr;
+    unsigned long long *times = nullptr;   // [0] start, [1 + p] completion of product p
+};
+
+static void batch_release(gfq_batch *b) {
+    if (!b) return;
+    if (b->mem) (void)hipFree(b->mem);
+    delete b;
+}
+
+extern "C" {
+
+int gfq_batch_create(int count, const gfq_problem *problems, gfq_batch **out) {
+    if (!out) return GFQ_ENULL;
+    *out = nullptr;
+    if (count < 0) return GFQ_EINVAL;
+    if (count > 0 && !problems) return GFQ_ENULL;
+    for (int i = 0; i < count; i++) {
+        const gfq_problem &p = problems[i];
+        int st = validate_mm(p.q, p.m, p.l, p.n, p.A, p.B, p.C);
+        if (st != GFQ_OK) return st;
+        if (p.m >= (1 << 16) * 256 || p.n >= (int64_t)(1 << 16) * 512) return GFQ_EDIM;   // tile index fits 16 bits
+    }
+    gfq_batch *b = new gfq_batch();
+    b->count = count;
+    hipError_t e = hipGetDevice(&b->device);
+    if (e != hipSuccess) { batch_release(b); return hip_fail(e, "hipGetDevice"); }
+
+    std::vector<BatchProd> prods(count);
+    std::vector<Group> g(8);
+    for (int i = 0; i < count; i++) {
+        const gfq_problem &p = problems[i];
+        BatchProd &bp = prods[i];
+        std::memset(&bp, 0, sizeof bp);
+        gfq_config c;
+        gfq_choose_config(p.q, p.m, p.l, p.n, &c);
+        const int P = planes_of(p.q);
+        // the batched kernels use 256-byte super-rows: k <= 7 (two planes) or 6 (three)
+        const int kcap = P == 2 ? 7 : 6;
+        int k = std::min(c.k, kcap);
+        if (p.l > 0 && p.l < k) k = (int)p.l;
+        if (k < 1) k = 1;
+        const int R = (c.rows <= 256 || p.q == 5) ? 2 : max_rows_per_lane(p.q);
+        const int TM = NT_MM / 4 * R;
+        MMArgs &a = bp.a;
+        a.A = (const u32 *)p.A;
+        a.B = (const u32 *)p.B;
+        a.out = (u32 *)p.C;
+        a.m = (int)p.m;
+        a.l = (int)p.l;
+        a.n = (int)p.n;
+        a.Wl = words_of(p.l);
+        a.Wn = words_of(p.n);
+        a.k = k;
+        a.S = p.l > 0 ? (int)((p.l + k - 1) / k) : 0;
+        a.slabs_per_split = std::max(a.S, 1);
+        a.split_stride = 0;
+        mm_lds_bytes(p.q, k, 256, TM, &a.tb1);
+        if (p.m == 0 || p.n == 0) continue;
+        const int tx = (a.Wn + 15) / 16, ty = (a.m + TM - 1) / TM;
+        bp.tiles = (u32)(tx * ty);
+        Group &gr = g[group_index(p.q, R)];
+        gr.q = p.q;
+        gr.R = R;
+        gr.kmax = std::max(gr.kmax, k);
+        for (int y = 0; y < ty; y++)
+            for (int x = 0; x < tx; x++) {
+                const double rows = std::min<int64_t>(TM, p.m - (int64_t)y * TM);
+                const double words = std::min(16, a.Wn - x * 16);
+                gr.items.push_back(BatchItem{(u32)i, (uint16_t)x, (uint16_t)y});
+                // relative tile cost: rows x words x slabs (plus the tables it builds)
+                gr.cost.push_back((rows + (double)(1 << k)) * words * std::max(a.S, 1) * (P == 2 ? 1.0 : 3.0));
+            }
+    }
+    // order every queue longest first
+    size_t nitems = 0;
+    for (Group &gr : g) {
+        if (gr.items.empty()) continue;
+        std::vector<size_t> idx(gr.items.size());
+        for (size_t j = 0; j < idx.size(); j++) idx[j] = j;
+        std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return gr.cost[x] > gr.cost[y]; });
+        std::vector<BatchItem> sorted(idx.size());
+        for (size_t j = 0; j < idx.size(); j++) sorted[j] = gr.items[idx[j]];
+        gr.items.swap(sorted);
+        gr.item_off = nitems;
+        nitems += gr.items.size();
+        gr.lds = mm_lds_bytes(gr.q, gr.kmax, 256, NT_MM / 4 * gr.R, nullptr);
+        b->groups.push_back(gr);
+    }
+
+    // one allocation: products | items | tile counts | times
+    auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t off_items = align(sizeof(BatchProd) * std::max(count, 1));
+    const size_t off_done = off_items + align(sizeof(BatchItem) * std::max<size_t>(nitems, 1));
+    const size_t off_time = off_done + align(sizeof(u32) * std::max(count, 1));
+    const size_t total = off_time + align(sizeof(unsigned long long) * (count + 1));
+    e = hipMalloc(&b->mem, total);
+    if (e != hipSuccess) { batch_release(b); hip_fail(e, "hipMalloc(batch)"); return GFQ_ENOMEM; }
+    char *base = (char *)b->mem;
+    std::vector<BatchItem> all(std::max<size_t>(nitems, 1));
+    for (const Group &gr : b->groups) std::copy(gr.items.begin(), gr.items.end(), all.begin() + gr.item_off);
+    e = hipMemset(b->mem, 0, total);
+    if (e == hipSuccess && count > 0) e = hipMemcpy(base, prods.data(), sizeof(BatchProd) * count, hipMemcpyHostToDevice);
+    if (e == hipSuccess && nitems > 0) e = hipMemcpy(base + off_items, all.data(), sizeof(BatchItem) * nitems, hipMemcpyHostToDevice);
+    for (size_t j = 0; e == hipSuccess && j < b->groups.size(); j++)
+        e = hipFuncSetAttribute(batched_kernel(b->groups[j].q, b->groups[j].R),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->groups[j].lds);
+    if (e != hipSuccess) { batch_release(b); return hip_fail(e, "batch upload"); }
+    b->prods = (BatchProd *)base;
+    b->items = (BatchItem *)(base + off_items);
+    b->prod_done = (u32 *)(base + off_done);
+    b->times = (unsigned long long *)(base + off_time);
+    *out = b;
+    return GFQ_OK;
+}
+
+int gfq_batch_launch(gfq_batch *b) {
+    if (!b) return GFQ_ENULL;
+    hipStream_t st = current_stream();
+    hipError_t e = launch_batch_stamp(b->times, st);
+    for (size_t j = 0; e == hipSuccess && j < b->groups.size(); j++) {
+        const Group &gr = b->groups[j];
+        BatchList l;
+        l.prods = b->prods;
+        l.items = b->items + gr.item_off;
+        l.prod_done = b->prod_done;
+        l.prod_time = b->times + 1;
+        e = launch_batched(gr.q, gr.R, l, (int)gr.items.size(), gr.lds, st);
+    }
+    return e == hipSuccess ? GFQ_OK : hip_fail(e, "batch launch");
+}
+
+int gfq_batch_times(gfq_batch *b, double *completion_us) {
+    if (!b || !completion_us) return GFQ_ENULL;
+    std::vector<unsigned long long> t(b->count + 1);
+    hipError_t e = hipStreamSynchronize(current_stream());
+    if (e == hipSuccess) e = hipMemcpy(t.data(), b->times, sizeof(unsigned long long) * t.size(), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "batch times");
+    for (int p = 0; p < b->count; p++)
+        completion_us[p] = t[1 + p] >= t[0] ? (double)(t[1 + p] - t[0]) * 0.01 : 0.0;   // 100 MHz ticks
+    return GFQ_OK;
+}
+
+int gfq_batch_destroy(gfq_batch *b) {
+    if (!b) return GFQ_OK;
+    hipError_t e = hipSetDevice(b->device);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    batch_release(b);
+    return e == hipSuccess ? GFQ_OK : hip_fail(e, "batch destroy");
+}
+
+}  // extern "C"

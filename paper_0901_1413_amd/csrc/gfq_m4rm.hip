@@ -1,323 +1,15 @@
-// gfq_m4rm.hip -- the Four-Russians product kernel for gfx950.
-//
-// Method (paper, Section 2): row i of C is sum_j a_ij B_j.  The inner dimension is cut
-// into slabs of k rows of B; for each slab a table of all 2^k binary combinations of its
-// rows is built once and shared by every row of C.  With an additive basis {alpha_d} and
-// bit maps phi_d (a = sum_d alpha_d phi_d(a)), the slab adds sum_d alpha_d T[phi_d(a_i)]
-// to row i, so only binary combinations are ever tabulated.
-//
-// Work decomposition
-//   grid.x  column tile: TWD 32-bit words of every plane (32 * TWD columns of C)
-//   grid.y  row tile: TM = R * NT / (TWD / 4) rows of C
-//   grid.z  slice of the slabs ("split-l"); more than one slice writes partial products
-//           that the reduce kernel sums.
-// Each lane owns 4 consecutive words of R rows of C and keeps their accumulators in VGPRs.
-//
-// Pipeline per workgroup (one barrier per slab).  Iteration s:
-//   stage   write slab s+2's rows of B (prefetched into registers one iteration earlier)
-//           and the phi_d table offsets of every row of the tile for slab s+2 into LDS;
-//   build   the table of slab s+1 into the idle table buffer, in Gray-code order;
-//   gather  for every row, D table rows of slab s, alpha_d-scaled into the accumulator;
-//   barrier.
-// The build of slab s+1 and the gathers of slab s are independent: half of the waves
-// build first, the other half gather first, so every SIMD overlaps the two.
-//
-// LDS table layout.  One (entry, plane) "super-row" is SRB bytes holding REP copies of
-// the TWD-word tile row.  gfx950 serves a 128-bit LDS read of 16 lanes from 64 four-byte
-// banks in one pass, so a 16-lane group is conflict-free exactly when its 16 reads cover
-// 256 distinct consecutive bytes: with SRB = 256 the REP rows of C gathered by one 16-lane
-// group come from different copies.  Table 0 sits at LDS offset 0 and table 1 at TB1, a
-// power of two not below the table size, so an address is (offset | lane offset | base).
+// gfq_m4rm.hip -- the plain (one product per launch) Four-Russians product kernel and its
+// launcher.  The tile computation itself is in gfq_m4rm_tile.h.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "gfq_device.h"
-#include "gfq_internal.h"
+#include "gfq_m4rm_tile.h"
 
 namespace gfq {
 
-__device__ __forceinline__ u32 comp4(const uint4 &v, int i) {
-    return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
-}
-
 template <int Q, int TWD, int REP, int R, int NT>
 __global__ __launch_bounds__(NT) void m4rm_kernel(MMArgs a) {
-    typedef FT<Q> F;
-    constexpr int P = F::P, D = F::D, PA = F::PA;
-    constexpr int LPR = TWD / 4;                 // lanes per row of C
-    constexpr int SRB = REP * TWD * 4;           // bytes per (entry, plane) super-row
-    constexpr int RS = NT / LPR;                 // row slots per pass
-    constexpr int TM = RS * R;                   // rows of C per workgroup
-    constexpr int CG = TWD / 4;                  // 4-word column groups per tile
-    constexpr int ARPT = (TM + NT - 1) / NT;     // tile rows staged per thread
-    constexpr int NCH = NT / TWD;                // build chunks per column word
-    constexpr int LOG_NCH = log2_floor(NCH);
-    constexpr int IBW = (D + 1) / 2;             // u32 words per row of the offset buffer
-    static_assert(KMAX * P * CG <= NT, "one B staging chunk per thread");
-    static_assert(REP * LPR <= 16, "super-row wider than a 16-lane read group");
-    static_assert(NCH % REP == 0 || REP % NCH == 0, "replica rotation");
-
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int k = a.k;
-    const u32 tbytes = (u32)(1u << k) * P * SRB;
-    const u32 TB1 = a.tb1;                       // power of two >= tbytes, <= 65536
-    u32 *Bst = reinterpret_cast<u32 *>(smem + TB1 + tbytes);   // [2][KMAX][P][TWD]
-    u32 *Ib = Bst + 2 * KMAX * P * TWD;                         // [3][TM][IBW]
-
-    const int tid = threadIdx.x;
-    const int colw0 = blockIdx.x * TWD;
-    const int row0 = blockIdx.y * TM;
-    const int s_begin = blockIdx.z * a.slabs_per_split;
-    const int s_end = min(a.S, s_begin + a.slabs_per_split);
-    const u32 kmask = (1u << k) - 1u;
-
-    // ---- staging of B: chunk (row t of the slab, plane p, 4-word group c) per thread ----
-    const int bt = tid / (P * CG), bp = (tid / CG) % P, bc = tid % CG;
-    const bool b_active = tid < k * P * CG;
-    const int bcol = colw0 + bc * 4;
-    auto load_b = [&](int s) -> uint4 {
-        const int brow = s * k + bt;
-        if (b_active && brow < a.l && bcol < a.Wn)
-            return *reinterpret_cast<const uint4 *>(a.B + ((size_t)brow * P + bp) * a.Wn + bcol);
-        return make_uint4(0u, 0u, 0u, 0u);
-    };
-    auto store_b = [&](int s, const uint4 &v) {
-        if (b_active) *reinterpret_cast<uint4 *>(Bst + (((s & 1) * KMAX + bt) * P + bp) * TWD + bc * 4) = v;
-    };
-
-    // ---- staging of A: a window of words (w, w+1, w+2) per staged row and plane ----
-    u32 aw[ARPT][P][3];
-    int aw_w = (s_begin * k) >> 5;
-    auto a_word = [&](int j, int p, int w) -> u32 {
-        const int lr = tid + j * NT;
-        const int row = row0 + lr;
-        if (lr < TM && row < a.m && w < a.Wl) return a.A[((size_t)row * P + p) * a.Wl + w];
-        return 0u;
-    };
-#pragma unroll
-    for (int j = 0; j < ARPT; j++)
-#pragma unroll
-        for (int p = 0; p < P; p++) {
-            aw[j][p][0] = a_word(j, p, aw_w);
-            aw[j][p][1] = a_word(j, p, aw_w + 1);
-            aw[j][p][2] = a_word(j, p, aw_w + 2);
-        }
-    // offsets (u16, entry * P * SRB) of the D table rows for slab s, for every tile row
-    auto stage_idx = [&](int s) {
-        const int sh = (s * k) & 31;
-        u32 *ib = Ib + (s % 3) * TM * IBW;
-#pragma unroll
-        for (int j = 0; j < ARPT; j++) {
-            const int lr = tid + j * NT;
-            if (lr < TM) {
-                u32 x[P], f[D];
-#pragma unroll
-                for (int p = 0; p < P; p++) x[p] = __builtin_amdgcn_alignbit(aw[j][p][1], aw[j][p][0], sh) & kmask;
-                F::phis(x, f);
-                u32 o[IBW * 2];
-#pragma unroll
-                for (int d = 0; d < IBW * 2; d++) o[d] = d < D ? f[d < D ? d : 0] * (u32)(P * SRB) : 0u;
-                // slot-major: the R rows of one row slot are adjacent, so a lane fetches
-                // all of its offsets with one or two 128-bit reads
-                const int pos = (lr % RS) * R + lr / RS;
-#pragma unroll
-                for (int w = 0; w < IBW; w++) ib[pos * IBW + w] = o[2 * w] | (o[2 * w + 1] << 16);
-            }
-        }
-    };
-    // move the window to the words of slab s (called in slab order; k < 32 so it moves by
-    // at most one word); the word two ahead is loaded now and used a slab later
-    auto advance = [&](int s) {
-        const int w = (s * k) >> 5;
-        if (w != aw_w) {
-#pragma unroll
-            for (int j = 0; j < ARPT; j++)
-#pragma unroll
-                for (int p = 0; p < P; p++) {
-                    aw[j][p][0] = aw[j][p][1];
-                    aw[j][p][1] = aw[j][p][2];
-                    aw[j][p][2] = a_word(j, p, w + 2);
-                }
-            aw_w = w;
-        }
-    };
-
-    // ---- table build: thread = (column word dw, chunk c); chunk c owns the entries whose
-    // high k-G bits equal c and walks their low G bits in Gray-code order ----
-    const int dw = tid % TWD, ch = tid / TWD;
-    const int G = k > LOG_NCH ? k - LOG_NCH : 0;
-    const int nchunks = 1 << (k - G);
-    auto build = [&](int s) {
-        if (ch >= nchunks) return;
-        const u32 *bs = Bst + (s & 1) * KMAX * P * TWD;
-        unsigned char *T = smem + ((s & 1) ? TB1 : 0u);
-        auto brow = [&](int t, u32 *r) {
-            u32 x[P];
-#pragma unroll
-            for (int p = 0; p < P; p++) x[p] = bs[(t * P + p) * TWD + dw];
-            F::to_table(x, r);
-        };
-        auto store = [&](int e, const u32 *v) {
-            unsigned char *dst = T + (u32)e * (P * SRB) + dw * 4;
-#pragma unroll
-            for (int i = 0; i < REP; i++) {
-                const int rho = (i + ch) % REP;
-#pragma unroll
-                for (int p = 0; p < P; p++) *reinterpret_cast<u32 *>(dst + p * SRB + rho * TWD * 4) = v[p];
-            }
-        };
-        u32 v[P];
-#pragma unroll
-        for (int p = 0; p < P; p++) v[p] = 0u;
-        for (int t = 0; t < k - G; t++) {
-            if ((ch >> t) & 1) {
-                u32 r[P], z[P];
-                brow(G + t, r);
-                F::tadd(v, r, z);
-#pragma unroll
-                for (int p = 0; p < P; p++) v[p] = z[p];
-            }
-        }
-        const int eb = ch << G;
-        store(eb, v);
-        for (int j = 1; j < (1 << G); j++) {
-            const int b = __builtin_ctz(j);
-            const int g = j ^ (j >> 1);
-            u32 r[P], z[P];
-            brow(b, r);
-            // a bit switched on adds its row, a bit switched off subtracts it
-            if ((g >> b) & 1) F::tadd(v, r, z);
-            else F::tsub(v, r, z);
-#pragma unroll
-            for (int p = 0; p < P; p++) v[p] = z[p];
-            store(eb | g, v);
-        }
-    };
-
-    // ---- accumulators: R rows x 4 words x PA planes per lane ----
-    u32 acc[R][4][PA];
-#pragma unroll
-    for (int r = 0; r < R; r++)
-#pragma unroll
-        for (int i = 0; i < 4; i++) F::acc_zero(acc[r][i]);
-
-    const int rs = tid / LPR, cg = tid % LPR;
-    const u32 laneoff = (u32)(tid % (REP * LPR)) * 16u;
-
-    // gathers of one row: D table rows, P planes each, 4 words per lane
-    auto fetch = [&](const u32 *iw, int r, u32 lo, uint4 (&t)[D][P]) {
-#pragma unroll
-        for (int d = 0; d < D; d++) {
-            const u32 x = iw[r * IBW + (d >> 1)];
-            const u32 off = ((d & 1) ? (x >> 16) : (x & 0xffffu)) | lo;
-#pragma unroll
-            for (int p = 0; p < P; p++) t[d][p] = *reinterpret_cast<const uint4 *>(smem + off + p * SRB);
-        }
-    };
-    auto consume = [&](int r, const uint4 (&t)[D][P]) {
-#pragma unroll
-        for (int i = 0; i < 4; i++) {
-            u32 ti[D][P];
-#pragma unroll
-            for (int d = 0; d < D; d++)
-#pragma unroll
-                for (int p = 0; p < P; p++) ti[d][p] = comp4(t[d][p], i);
-            F::accumulate(acc[r][i], ti);
-        }
-    };
-    // software-pipelined: the reads of row r+1 are issued before row r is accumulated
-    auto gather = [&](int s) {
-        const u32 lo = laneoff | ((s & 1) ? TB1 : 0u);
-        const u32 *ib = Ib + (s % 3) * TM * IBW + rs * R * IBW;
-        u32 iw[R * IBW];
-        if constexpr ((R * IBW) % 4 == 0) {
-#pragma unroll
-            for (int w = 0; w < R * IBW; w += 4) {
-                const uint4 v = *reinterpret_cast<const uint4 *>(ib + w);
-                iw[w] = v.x; iw[w + 1] = v.y; iw[w + 2] = v.z; iw[w + 3] = v.w;
-            }
-        } else {
-#pragma unroll
-            for (int w = 0; w < R * IBW; w += 2) {
-                const uint2 v = *reinterpret_cast<const uint2 *>(ib + w);
-                iw[w] = v.x; iw[w + 1] = v.y;
-            }
-        }
-        uint4 ta[D][P], tb[D][P];
-        fetch(iw, 0, lo, ta);
-#pragma unroll
-        for (int r = 0; r < R; r += 2) {
-            if (r + 1 < R) fetch(iw, r + 1, lo, tb);
-            consume(r, ta);
-            if (r + 2 < R) fetch(iw, r + 2, lo, ta);
-            if (r + 1 < R) consume(r + 1, tb);
-        }
-    };
-
-    const bool build_first = (tid / 64) < (NT / 128);   // first half of the waves
-
-    // ---- prologue: stage slabs s0 and s0+1, build slab s0 ----
-    uint4 bpre = make_uint4(0u, 0u, 0u, 0u);
-    if (s_begin < s_end) {
-        store_b(s_begin, load_b(s_begin));
-        stage_idx(s_begin);
-        advance(s_begin + 1);
-        if (s_begin + 1 < s_end) {
-            store_b(s_begin + 1, load_b(s_begin + 1));
-            stage_idx(s_begin + 1);
-            advance(s_begin + 2);
-        }
-        if (s_begin + 2 < s_end) bpre = load_b(s_begin + 2);
-        __syncthreads();
-        build(s_begin);
-        __syncthreads();
-    }
-
-    for (int s = s_begin; s < s_end; s++) {
-        if (s + 2 < s_end) {
-            store_b(s + 2, bpre);
-            stage_idx(s + 2);
-            advance(s + 3);
-        }
-        if (s + 3 < s_end) bpre = load_b(s + 3);
-        // The two waves sharing a SIMD (w and w + NT/256) run the independent build and
-        // gather phases in opposite orders, so one wave's VALU-heavy gathers fill the other
-        // wave's waits on the table build's chain of LDS round trips.
-#pragma unroll 1
-        for (int phase = 0; phase < 2; phase++) {
-            if ((phase == 0) == build_first) {
-                if (s + 1 < s_end) build(s + 1);
-            } else {
-                gather(s);
-            }
-        }
-        __syncthreads();
-    }
-
-    // ---- store: finish (resolve, canonicalise), zero the pad columns ----
-    const int w = colw0 + cg * 4;
-    if (w < a.Wn) {
-        u32 msk[4];
-#pragma unroll
-        for (int i = 0; i < 4; i++) {
-            const int v = a.n - (w + i) * 32;
-            msk[i] = v >= 32 ? 0xffffffffu : (v <= 0 ? 0u : ((1u << v) - 1u));
-        }
-        u32 *out = a.out + (size_t)blockIdx.z * a.split_stride;
-#pragma unroll
-        for (int r = 0; r < R; r++) {
-            const int row = row0 + rs + r * RS;
-            if (row < a.m) {
-                u32 o[4][P];
-#pragma unroll
-                for (int i = 0; i < 4; i++) F::finish(acc[r][i], o[i]);
-#pragma unroll
-                for (int p = 0; p < P; p++)
-                    *reinterpret_cast<uint4 *>(out + ((size_t)row * P + p) * a.Wn + w) =
-                        make_uint4(o[0][p] & msk[0], o[1][p] & msk[1], o[2][p] & msk[2], o[3][p] & msk[3]);
-            }
-        }
-    }
+    m4rm_tile<Q, TWD, REP, R, NT>(a, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // ---------------------------------------------------------------------------------------

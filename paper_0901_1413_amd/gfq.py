@@ -49,6 +49,10 @@ _SIGS = {
                                          ctypes.POINTER(Config)]),
     "gfq_choose_config": (ctypes.c_int, [ctypes.c_int, _I64, _I64, _I64, ctypes.POINTER(Config)]),
     "gfq_matmul_batched": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(Problem)]),
+    "gfq_batch_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(Problem), ctypes.POINTER(_VP)]),
+    "gfq_batch_launch": (ctypes.c_int, [_VP]),
+    "gfq_batch_times": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double)]),
+    "gfq_batch_destroy": (ctypes.c_int, [_VP]),
     "gfq_set_stream": (ctypes.c_int, [_VP]),
     "gfq_sync": (ctypes.c_int, []),
     "gfq_set_timing": (ctypes.c_int, [ctypes.c_int]),
@@ -164,6 +168,43 @@ def matmul_batched(problems: Sequence[tuple]):
         arr[i] = Problem(q, m, l, n, A.data_ptr(), B.data_ptr(), C.data_ptr())
     _bind_stream()
     _check(load().gfq_matmul_batched(len(problems), arr), "gfq_matmul_batched")
+
+
+class Batch:
+    """A prepared batch of products (gfq_batch_create): launch it any number of times."""
+
+    def __init__(self, problems: Sequence[tuple]):
+        self.count = len(problems)
+        arr = (Problem * max(1, len(problems)))()
+        for i, (q, m, l, n, A, B, C) in enumerate(problems):
+            arr[i] = Problem(q, m, l, n, A.data_ptr(), B.data_ptr(), C.data_ptr())
+        self._keep = [(A, B, C) for (_, _, _, _, A, B, C) in problems]
+        h = _VP()
+        _bind_stream()
+        _check(load().gfq_batch_create(len(problems), arr, ctypes.byref(h)), "gfq_batch_create")
+        self.handle = h
+
+    def launch(self):
+        _bind_stream()
+        _check(load().gfq_batch_launch(self.handle), "gfq_batch_launch")
+
+    def times_us(self):
+        """Per-product completion time of the last launch, microseconds from its start."""
+        out = (ctypes.c_double * max(1, self.count))()
+        _bind_stream()
+        _check(load().gfq_batch_times(self.handle, out), "gfq_batch_times")
+        return list(out)[: self.count]
+
+    def destroy(self):
+        if self.handle:
+            _check(load().gfq_batch_destroy(self.handle), "gfq_batch_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
 
 
 def set_timing(on: bool):

@@ -68,3 +68,11 @@ def test_strerror():
     lib = gfq.load()
     for s in range(-10, 1):
         assert lib.gfq_strerror(s)
+
+
+def test_choose_config_degenerate_shapes():
+    """Empty products have no tiles; choosing their configuration must not divide by zero."""
+    for q in (3, 4, 5, 7):
+        for m, l, n in ((0, 4, 4), (4, 4, 0), (0, 0, 0), (5, 0, 7), (1, 1, 1)):
+            c = gfq.choose_config(q, m, l, n)
+            assert 1 <= c["k"] <= 10 and c["split"] >= 1

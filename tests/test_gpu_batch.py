@@ -1,0 +1,99 @@
+"""Batched persistent launches: every product of a mixed batch against the oracle and
+against the same product launched alone (bit-exact), graph replays, degenerate products."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_0901_1413_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def make_batch(g, specs, cfg):
+    probs, host = [], []
+    for idx, (q, m, l, n) in enumerate(specs):
+        A, B = inputs.pair(q, m, l, n, cfg=cfg, idx=idx)
+        Ap, Bp = g.pack(q, dev(A)), g.pack(q, dev(B))
+        C = g.empty_packed(q, m, n)
+        C.fill_(0x5A)
+        probs.append((q, m, l, n, Ap, Bp, C))
+        host.append((A, B))
+    return probs, host
+
+
+def check_against_oracle_and_alone(g, probs, host, which):
+    for i in which:
+        q, m, l, n, Ap, Bp, C = probs[i]
+        A, B = host[i]
+        got = g.unpack(q, C, m, n).cpu().numpy()
+        assert np.array_equal(got, oracle.matmul(q, A, B)), (i, q, m, l, n)
+        alone = g.matmul(q, Ap, Bp, m, l, n)
+        nb = g.packed_bytes(q, m, n)
+        assert np.array_equal(alone.cpu().numpy()[:nb], C.cpu().numpy()[:nb]), ("alone differs", i)
+
+
+def test_mixed_batch(gfq_gpu):
+    g = gfq_gpu
+    rng = np.random.default_rng(301)
+    specs = []
+    for i in range(60):
+        q = int(rng.choice([3, 4, 5, 7]))
+        m, l, n = (int(x) for x in rng.integers(1, 700, size=3))
+        specs.append((q, m, l, n))
+    specs += [(3, 1, 1, 1), (5, 1025, 33, 7), (7, 64, 2048, 64), (4, 2048, 64, 1000)]
+    probs, host = make_batch(g, specs, 302)
+    g.matmul_batched(probs)
+    g.sync()
+    check_against_oracle_and_alone(g, probs, host, range(len(specs)))
+
+
+def test_batch_replay_and_times(gfq_gpu):
+    g = gfq_gpu
+    specs = [(3, 300, 200, 100), (5, 64, 64, 64), (7, 1000, 900, 130), (4, 513, 127, 511), (3, 2048, 2048, 2048)]
+    probs, host = make_batch(g, specs, 303)
+    b = g.Batch(probs)
+    for rep in range(3):
+        for (_, _, _, _, _, _, C) in probs:
+            C.fill_(0x11)
+        b.launch()
+        g.sync()
+        t = b.times_us()
+        assert all(x > 0 for x in t) and max(t) < 1e7, t
+        check_against_oracle_and_alone(g, probs, host, range(len(specs)))
+    b.destroy()
+
+
+def test_batch_degenerate_and_rejection(gfq_gpu):
+    g = gfq_gpu
+    specs = [(3, 5, 0, 7), (5, 0, 4, 4), (7, 4, 4, 0), (4, 9, 3, 9)]
+    probs, host = make_batch(g, specs, 304)
+    g.matmul_batched(probs)
+    g.sync()
+    q, m, l, n, _, _, C = probs[0]
+    assert not C.cpu().numpy()[:g.packed_bytes(q, m, n)].any()          # l = 0: zero product
+    check_against_oracle_and_alone(g, probs, host, [3])
+    bad = list(probs) + [(11, 4, 4, 4, probs[3][4], probs[3][5], probs[3][6])]
+    with pytest.raises(g.GfqError) as e:
+        g.matmul_batched(bad)
+    assert e.value.status == -2
+
+
+def test_c4_shaped_batch_sampled(gfq_gpu):
+    """512 products shaped like the batched workload (fields F_3/F_5/F_7, m, l, n
+    log-uniform in [64, 2048]); every product equals its single launch, a sample equals
+    the oracle."""
+    g = gfq_gpu
+    specs = inputs.batch_specs(512, cfg=4)
+    probs, host = make_batch(g, specs, 4)
+    g.matmul_batched(probs)
+    g.sync()
+    for i, (q, m, l, n, Ap, Bp, C) in enumerate(probs):
+        alone = g.matmul(q, Ap, Bp, m, l, n)
+        nb = g.packed_bytes(q, m, n)
+        assert np.array_equal(alone.cpu().numpy()[:nb], C.cpu().numpy()[:nb]), i
+    check_against_oracle_and_alone(g, probs, host, range(0, 512, 37))
