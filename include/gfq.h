@@ -135,6 +135,30 @@ int gfq_batch_launch(gfq_batch *batch);
 int gfq_batch_times(gfq_batch *batch, double *completion_us);
 int gfq_batch_destroy(gfq_batch *batch);
 
+/* Autotuning.  gfq_tune times candidate configurations on scratch operands of the given
+ * shape (pseudo-random contents) on the current device and stores the fastest in a cache
+ * keyed by (device architecture, mode, field, size class); it synchronises and returns the
+ * chosen configuration.  Modes: 0 = single products (k, tile height and split for this
+ * shape's size class, where the class rounds m, l, n up to powers of two from 64 to 16384);
+ * GFQ_TUNE_BATCH = products inside batches (k and tile height for the class of (m, l); n is
+ * ignored).  gfq_choose_config and gfq_batch_create use cached entries when they exist.
+ * gfq_tune_lookup returns GFQ_OK and the entry if the class is cached, GFQ_EAGAIN if not.
+ * gfq_tune_save / gfq_tune_load write / merge the cache as text, one entry per line.
+ * gfq_tune_clear empties it.
+ * gfq_tune: each of m, l, n in 1 .. 65536 (else GFQ_EDIM); q in {3,4,5,7} (GFQ_EFIELD);
+ * mode 0 or GFQ_TUNE_BATCH (GFQ_EINVAL).  It runs on the calling thread's stream, waits for
+ * its own launches, and keeps its scratch operands (one device buffer, filled with
+ * pseudo-random words) until the process ends; GFQ_ENOMEM if that buffer cannot be had.
+ * Concurrent calls on one device measure each other: tune from one thread at a time.
+ * gfq_tune_load returns GFQ_EINVAL if the file cannot be read or holds a malformed or
+ * out-of-range entry (the valid entries are merged all the same). */
+#define GFQ_TUNE_BATCH 1
+int gfq_tune(int q, int64_t m, int64_t l, int64_t n, int mode, gfq_config *out);
+int gfq_tune_lookup(int q, int64_t m, int64_t l, int64_t n, int mode, gfq_config *out);
+int gfq_tune_save(const char *path);
+int gfq_tune_load(const char *path);
+int gfq_tune_clear(void);
+
 /* Stream for subsequent calls made by this host thread (a hipStream_t; NULL = default). */
 int gfq_set_stream(void *hip_stream);
 

@@ -236,6 +236,7 @@ int gfq_choose_config(int q, int64_t m, int64_t l, int64_t n, gfq_config *out) {
     if (!valid_field(q)) return GFQ_EFIELD;
     if (!out) return GFQ_ENULL;
     if (m < 0 || l < 0 || n < 0) return GFQ_EDIM;
+    if (m > 0 && n > 0 && l > 0 && gfq_tune_lookup(q, m, l, n, 0, out) == GFQ_OK) return GFQ_OK;
     gfq_config best = {};
     double best_cost = 0.0;
     // k = 7: the widest slab whose two tables fit LDS with 128-bit reads that conflict at

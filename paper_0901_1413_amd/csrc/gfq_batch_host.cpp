@@ -50,9 +50,9 @@ static void batch_release(gfq_batch *b) {
     delete b;
 }
 
-extern "C" {
-
-int gfq_batch_create(int count, const gfq_problem *problems, gfq_batch **out) {
+// Build a batch; cfgs (optional, one per product) overrides the per-product choice of slab
+// width and tile height (the tuner uses it to time candidates).
+int gfq::batch_create_with(int count, const gfq_problem *problems, const gfq_config *cfgs, gfq_batch **out) {
     if (!out) return GFQ_ENULL;
     *out = nullptr;
     if (count < 0) return GFQ_EINVAL;
@@ -75,7 +75,9 @@ int gfq_batch_create(int count, const gfq_problem *problems, gfq_batch **out) {
         BatchProd &bp = prods[i];
         std::memset(&bp, 0, sizeof bp);
         gfq_config c;
-        gfq_choose_config(p.q, p.m, p.l, p.n, &c);
+        if (cfgs) c = cfgs[i];
+        else if (gfq_tune_lookup(p.q, p.m, p.l, p.n, GFQ_TUNE_BATCH, &c) != GFQ_OK)
+            gfq_choose_config(p.q, p.m, p.l, p.n, &c);
         const int P = planes_of(p.q);
         // the batched kernels use 256-byte super-rows: k <= 7 (two planes) or 6 (three)
         const int kcap = P == 2 ? 7 : 6;
@@ -154,6 +156,12 @@ int gfq_batch_create(int count, const gfq_problem *problems, gfq_batch **out) {
     b->times = (unsigned long long *)(base + off_time);
     *out = b;
     return GFQ_OK;
+}
+
+extern "C" {
+
+int gfq_batch_create(int count, const gfq_problem *problems, gfq_batch **out) {
+    return batch_create_with(count, problems, nullptr, out);
 }
 
 int gfq_batch_launch(gfq_batch *b) {

@@ -169,6 +169,21 @@ __global__ __launch_bounds__(256) void unpack_kernel(const u32 *src, uint8_t *ds
     }
 }
 
+// Pseudo-random words for the tuner's scratch operands (timing only): a 32-bit mix of the
+// word index and a seed.
+__global__ __launch_bounds__(256) void fill_random_kernel(u32 *p, size_t n, u32 seed) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        u32 x = (u32)i * 0x9e3779b9u ^ seed ^ (u32)(i >> 32);
+        x ^= x >> 16; x *= 0x7feb352du; x ^= x >> 15; x *= 0x846ca68bu; x ^= x >> 16;
+        p[i] = x;
+    }
+}
+
+hipError_t launch_fill_random(u32 *p, size_t n, u32 seed, hipStream_t st) {
+    hipLaunchKernelGGL(fill_random_kernel, dim3(1024), dim3(256), 0, st, p, n, seed);
+    return hipGetLastError();
+}
+
 hipError_t launch_reduce(int q, const u32 *part, u32 *C, int m, int n, int Wn, int splits, size_t stride, hipStream_t st) {
     const size_t threads = (size_t)m * (Wn / 4);
     dim3 grid((unsigned)((threads + 255) / 256));

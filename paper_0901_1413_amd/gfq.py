@@ -53,6 +53,11 @@ _SIGS = {
     "gfq_batch_launch": (ctypes.c_int, [_VP]),
     "gfq_batch_times": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double)]),
     "gfq_batch_destroy": (ctypes.c_int, [_VP]),
+    "gfq_tune": (ctypes.c_int, [ctypes.c_int, _I64, _I64, _I64, ctypes.c_int, ctypes.POINTER(Config)]),
+    "gfq_tune_lookup": (ctypes.c_int, [ctypes.c_int, _I64, _I64, _I64, ctypes.c_int, ctypes.POINTER(Config)]),
+    "gfq_tune_save": (ctypes.c_int, [ctypes.c_char_p]),
+    "gfq_tune_load": (ctypes.c_int, [ctypes.c_char_p]),
+    "gfq_tune_clear": (ctypes.c_int, []),
     "gfq_set_stream": (ctypes.c_int, [_VP]),
     "gfq_sync": (ctypes.c_int, []),
     "gfq_set_timing": (ctypes.c_int, [ctypes.c_int]),
@@ -205,6 +210,35 @@ class Batch:
             self.destroy()
         except Exception:
             pass
+
+
+TUNE_BATCH = 1
+
+
+def tune(q: int, m: int, l: int, n: int, batch: bool = False) -> dict:
+    """Time candidate configurations for this shape's size class and cache the fastest."""
+    c = Config()
+    _bind_stream()
+    _check(load().gfq_tune(q, m, l, n, TUNE_BATCH if batch else 0, ctypes.byref(c)), "gfq_tune")
+    return c.as_dict()
+
+
+def tune_lookup(q: int, m: int, l: int, n: int, batch: bool = False):
+    c = Config()
+    st = load().gfq_tune_lookup(q, m, l, n, TUNE_BATCH if batch else 0, ctypes.byref(c))
+    return c.as_dict() if st == GFQ_OK else None
+
+
+def tune_save(path: str):
+    _check(load().gfq_tune_save(path.encode()), "gfq_tune_save")
+
+
+def tune_load(path: str):
+    _check(load().gfq_tune_load(path.encode()), "gfq_tune_load")
+
+
+def tune_clear():
+    load().gfq_tune_clear()
 
 
 def set_timing(on: bool):

@@ -76,3 +76,26 @@ def test_choose_config_degenerate_shapes():
         for m, l, n in ((0, 4, 4), (4, 4, 0), (0, 0, 0), (5, 0, 7), (1, 1, 1)):
             c = gfq.choose_config(q, m, l, n)
             assert 1 <= c["k"] <= 10 and c["split"] >= 1
+
+
+def test_tune_cache_text_roundtrip(tmp_path):
+    """The tuning cache file is plain text; loading validates each entry (host logic only)."""
+    f = tmp_path / "tune.txt"
+    f.write_text("# arch mode q m_class l_class n_class k rows split\n"
+                 "gfx950 0 3 13 13 13 7 2048 2\n"
+                 "gfx950 1 5 9 10 0 6 256 1\n")
+    gfq.tune_clear()
+    gfq.tune_load(str(f))
+    out = tmp_path / "out.txt"
+    gfq.tune_save(str(out))
+    lines = [l.split() for l in out.read_text().splitlines() if not l.startswith("#")]
+    assert sorted(lines) == sorted([["gfx950", "0", "3", "13", "13", "13", "7", "2048", "2"],
+                                    ["gfx950", "1", "5", "9", "10", "0", "6", "256", "1"]])
+    bad = tmp_path / "bad.txt"
+    bad.write_text("gfx950 0 3 13 13 13 11 2048 2\n")          # k = 11 is out of range
+    with pytest.raises(gfq.GfqError):
+        gfq.tune_load(str(bad))
+    gfq.tune_clear()
+    out2 = tmp_path / "empty.txt"
+    gfq.tune_save(str(out2))
+    assert [l for l in out2.read_text().splitlines() if not l.startswith("#")] == []
