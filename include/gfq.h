@@ -159,6 +159,100 @@ int gfq_tune_save(const char *path);
 int gfq_tune_load(const char *path);
 int gfq_tune_clear(void);
 
+/* Product server: continuous batching of products as they arrive (the batched products
+ * above, fed by a request queue).  A server owns a worker thread, its own HIP streams (one
+ * per in-flight batch, default priority), an arena of device memory for packed operands
+ * bounded by a byte budget, and per-slot descriptor buffers; it runs on the device that is
+ * current when it is created.
+ *
+ * Each request is one product C = A B over field q with A m x l, B l x n.  Operands are
+ * device pointers owned by the caller and must stay valid, and C untouched by others, until
+ * the request's completion has been returned by gfq_server_poll.  By default A and B are
+ * uint8 matrices (canonical values, leading dimensions lda >= l, ldb >= n) and C receives a
+ * uint8 matrix (ldc >= n); the flags GFQ_REQ_A_PACKED, GFQ_REQ_B_PACKED, GFQ_REQ_C_PACKED
+ * mark an operand as already packed (format above, 16-byte aligned; its ld is ignored), so
+ * operands kept packed in device memory are used in place.  Every packed operand the server
+ * makes (the packed forms of uint8 A and B, and the packed product before it is unpacked) is
+ * held in the arena from admission to completion.
+ *
+ * The worker admits requests in order of arrival (not_before_us, or the submission time
+ * when that is earlier or 0) while the arena has room for a request's packed operands and a
+ * batch has room (max_batch requests, max_items tiles); the first request that does not
+ * fit waits for memory released by completing batches, so no request is overtaken.  An
+ * admitted batch is launched at once on a free slot's stream: one conversion launch packs
+ * every uint8 operand, one work-list launch per (field, tile height) computes the
+ * products, one conversion launch unpacks every uint8 product.  Batches on different slots
+ * overlap on the device; requests that arrive meanwhile form the next batch as soon as a
+ * slot is free.  In GFQ_SERVE_SERIAL mode the server instead runs one request at a time
+ * with the single-product calls (gfq_pack, gfq_matmul, gfq_unpack) - the baseline of
+ * plain launches, measured by the same clocks.
+ *
+ * Times are microseconds of the server clock (gfq_server_now_us, monotonic, 0 at creation).
+ */
+typedef struct gfq_server gfq_server;
+
+#define GFQ_SERVE_BATCHED 0
+#define GFQ_SERVE_SERIAL 1
+
+typedef struct {
+    size_t budget_bytes; /* arena limit for packed operands (0 = 1 GiB)                     */
+    int slots;           /* batches in flight, 1..8 (0 = 3; serial mode uses 1)             */
+    int max_batch;       /* requests per batch, 1..4096 (0 = 256; serial mode uses 1)       */
+    int max_items;       /* tiles per batch, 32768..1048576 (0 = 65536)                     */
+    int mode;            /* GFQ_SERVE_BATCHED or GFQ_SERVE_SERIAL                           */
+} gfq_server_opts;
+
+#define GFQ_REQ_A_PACKED 1
+#define GFQ_REQ_B_PACKED 2
+#define GFQ_REQ_C_PACKED 4
+
+typedef struct {
+    int q;
+    int64_t m, l, n;        /* each in 0 .. 65535 (m == 0, n == 0 or l == 0 are allowed)  */
+    const void *A;
+    int64_t lda;
+    const void *B;
+    int64_t ldb;
+    void *C;
+    int64_t ldc;
+    int flags;              /* GFQ_REQ_* bits                                             */
+    uint64_t tag;           /* returned with the completion                               */
+    double not_before_us;   /* arrival time on the server clock; 0 = at submission        */
+} gfq_request;
+
+typedef struct {
+    uint64_t tag;
+    int status;             /* GFQ_OK, or GFQ_EHIP if the device work failed              */
+    int batch_size;         /* requests in the batch that carried this one                */
+    double arrival_us;      /* max(submission, not_before_us)                             */
+    double launch_us;       /* batch launched                                             */
+    double done_us;         /* completion observed by the worker                          */
+} gfq_completion;
+
+typedef struct {
+    int64_t submitted, completed, batches;
+    int64_t queued;              /* submitted, not yet admitted                             */
+    int64_t max_batch_seen;
+    size_t arena_in_use, arena_held, arena_peak_in_use;
+} gfq_server_stats;
+
+/* Create a server (opts may be NULL for defaults).  GFQ_EINVAL for options out of range,
+ * GFQ_ENOMEM / GFQ_EHIP if its streams or descriptor buffers cannot be had. */
+int gfq_server_create(const gfq_server_opts *opts, gfq_server **out);
+/* Queue count requests (host array, copied).  All are validated first (field, dimensions,
+ * null or misaligned pointers, leading dimensions, C overlapping A or B); the first error
+ * rejects them all.  GFQ_EBUDGET if a request's packed operands alone exceed the budget;
+ * GFQ_EHIP if the server has failed.  Returns without waiting. */
+int gfq_server_submit(gfq_server *srv, const gfq_request *reqs, int count);
+/* Move up to max completions into out (*got of them), waiting up to timeout_us for the
+ * first (0 = do not wait, negative = wait indefinitely).  GFQ_OK even when *got is 0. */
+int gfq_server_poll(gfq_server *srv, gfq_completion *out, int max, int *got, double timeout_us);
+double gfq_server_now_us(const gfq_server *srv);
+int gfq_server_stats_read(const gfq_server *srv, gfq_server_stats *out);
+/* Wait for the batches in flight, drop requests not yet admitted (their completions are
+ * never reported), stop the worker and free everything. */
+int gfq_server_destroy(gfq_server *srv);
+
 /* Stream for subsequent calls made by this host thread (a hipStream_t; NULL = default). */
 int gfq_set_stream(void *hip_stream);
 

@@ -9,12 +9,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgfq.so")
-SOURCES = ["gfq_m4rm.hip", "gfq_batch.hip", "gfq_pack.hip", "gfq_api.cpp", "gfq_batch_host.cpp", "gfq_tune.cpp"]
+SOURCES = ["gfq_m4rm.hip", "gfq_batch.hip", "gfq_pack.hip", "gfq_api.cpp", "gfq_batch_host.cpp", "gfq_tune.cpp",
+           "gfq_server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # packed-fp32 forms are kept out of every HIP build
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Wall", "-Wno-unused-command-line-argument",
+         "-Wall", "-Wno-unused-command-line-argument", "-pthread",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 

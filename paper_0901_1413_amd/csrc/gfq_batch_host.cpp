@@ -17,15 +17,6 @@ using namespace gfq;
 
 namespace {
 
-struct Group {
-    int q = 0, R = 0;
-    std::vector<BatchItem> items;
-    std::vector<double> cost;
-    int kmax = 1;
-    size_t lds = 0;
-    size_t item_off = 0;   // index of the group's first item in the device item array
-};
-
 int group_index(int q, int R) {
     const int qi = q == 3 ? 0 : (q == 4 ? 1 : (q == 5 ? 2 : 3));
     return qi * 2 + (R == 2 ? 0 : 1);
@@ -33,43 +24,11 @@ int group_index(int q, int R) {
 
 }  // namespace
 
-struct gfq_batch {
-    int count = 0;
-    int device = 0;
-    std::vector<Group> groups;
-    void *mem = nullptr;
-    BatchProd *prods = nullptr;
-    BatchItem *items = nullptr;
-    u32 *prod_done = nullptr;
-    unsigned long long *times = nullptr;   // [0] start, [1 + p] completion of product p
-};
-
-static void batch_release(gfq_batch *b) {
-    if (!b) return;
-    if (b->mem) (void)hipFree(b->mem);
-    delete b;
-}
-
-// Build a batch; cfgs (optional, one per product) overrides the per-product choice of slab
-// width and tile height (the tuner uses it to time candidates).
-int gfq::batch_create_with(int count, const gfq_problem *problems, const gfq_config *cfgs, gfq_batch **out) {
-    if (!out) return GFQ_ENULL;
-    *out = nullptr;
-    if (count < 0) return GFQ_EINVAL;
-    if (count > 0 && !problems) return GFQ_ENULL;
-    for (int i = 0; i < count; i++) {
-        const gfq_problem &p = problems[i];
-        int st = validate_mm(p.q, p.m, p.l, p.n, p.A, p.B, p.C);
-        if (st != GFQ_OK) return st;
-        if (p.m >= (1 << 16) * 256 || p.n >= (int64_t)(1 << 16) * 512) return GFQ_EDIM;   // tile index fits 16 bits
-    }
-    gfq_batch *b = new gfq_batch();
-    b->count = count;
-    hipError_t e = hipGetDevice(&b->device);
-    if (e != hipSuccess) { batch_release(b); return hip_fail(e, "hipGetDevice"); }
-
-    std::vector<BatchProd> prods(count);
-    std::vector<Group> g(8);
+// Launch parameters of every product and its tiles, grouped by (field, rows per lane) and
+// ordered longest first within a group.
+void gfq::plan_batch(int count, const gfq_problem *problems, const gfq_config *cfgs, BatchProd *prods,
+                     std::vector<BatchGroup> *groups, size_t *nitems) {
+    std::vector<BatchGroup> g(8);
     for (int i = 0; i < count; i++) {
         const gfq_problem &p = problems[i];
         BatchProd &bp = prods[i];
@@ -103,7 +62,7 @@ int gfq::batch_create_with(int count, const gfq_problem *problems, const gfq_con
         if (p.m == 0 || p.n == 0) continue;
         const int tx = (a.Wn + 15) / 16, ty = (a.m + TM - 1) / TM;
         bp.tiles = (u32)(tx * ty);
-        Group &gr = g[group_index(p.q, R)];
+        BatchGroup &gr = g[group_index(p.q, R)];
         gr.q = p.q;
         gr.R = R;
         gr.kmax = std::max(gr.kmax, k);
@@ -116,9 +75,9 @@ int gfq::batch_create_with(int count, const gfq_problem *problems, const gfq_con
                 gr.cost.push_back((rows + (double)(1 << k)) * words * std::max(a.S, 1) * (P == 2 ? 1.0 : 3.0));
             }
     }
-    // order every queue longest first
-    size_t nitems = 0;
-    for (Group &gr : g) {
+    groups->clear();
+    size_t n = 0;
+    for (BatchGroup &gr : g) {
         if (gr.items.empty()) continue;
         std::vector<size_t> idx(gr.items.size());
         for (size_t j = 0; j < idx.size(); j++) idx[j] = j;
@@ -126,11 +85,69 @@ int gfq::batch_create_with(int count, const gfq_problem *problems, const gfq_con
         std::vector<BatchItem> sorted(idx.size());
         for (size_t j = 0; j < idx.size(); j++) sorted[j] = gr.items[idx[j]];
         gr.items.swap(sorted);
-        gr.item_off = nitems;
-        nitems += gr.items.size();
+        gr.cost.clear();
+        gr.item_off = n;
+        n += gr.items.size();
         gr.lds = mm_lds_bytes(gr.q, gr.kmax, 256, NT_MM / 4 * gr.R, nullptr);
-        b->groups.push_back(gr);
+        groups->push_back(std::move(gr));
     }
+    *nitems = n;
+}
+
+size_t gfq::batch_tiles_bound(int64_t m, int64_t n) {
+    if (m <= 0 || n <= 0) return 0;
+    return (size_t)((m + 255) / 256) * (size_t)((words_of(n) + 15) / 16);
+}
+
+hipError_t gfq::set_batched_lds_limits() {
+    for (int q : {3, 4, 5, 7})
+        for (int R : {2, max_rows_per_lane(q)}) {
+            if (q == 5 && R != 2) continue;       // F_5 batches use two rows per lane only
+            const size_t lds = mm_lds_bytes(q, planes_of(q) == 2 ? 7 : 6, 256, NT_MM / 4 * R, nullptr);
+            hipError_t e = hipFuncSetAttribute(batched_kernel(q, R), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+        }
+    return hipSuccess;
+}
+
+struct gfq_batch {
+    int count = 0;
+    int device = 0;
+    std::vector<BatchGroup> groups;
+    void *mem = nullptr;
+    BatchProd *prods = nullptr;
+    BatchItem *items = nullptr;
+    u32 *prod_done = nullptr;
+    unsigned long long *times = nullptr;   // [0] start, [1 + p] completion of product p
+};
+
+static void batch_release(gfq_batch *b) {
+    if (!b) return;
+    if (b->mem) (void)hipFree(b->mem);
+    delete b;
+}
+
+// Build a batch; cfgs (optional, one per product) overrides the per-product choice of slab
+// width and tile height (the tuner uses it to time candidates).
+int gfq::batch_create_with(int count, const gfq_problem *problems, const gfq_config *cfgs, gfq_batch **out) {
+    if (!out) return GFQ_ENULL;
+    *out = nullptr;
+    if (count < 0) return GFQ_EINVAL;
+    if (count > 0 && !problems) return GFQ_ENULL;
+    for (int i = 0; i < count; i++) {
+        const gfq_problem &p = problems[i];
+        int st = validate_mm(p.q, p.m, p.l, p.n, p.A, p.B, p.C);
+        if (st != GFQ_OK) return st;
+        if (p.m >= (1 << 16) * 256 || p.n >= (int64_t)(1 << 16) * 512) return GFQ_EDIM;   // tile index fits 16 bits
+    }
+    gfq_batch *b = new gfq_batch();
+    b->count = count;
+    hipError_t e = hipGetDevice(&b->device);
+    if (e != hipSuccess) { batch_release(b); return hip_fail(e, "hipGetDevice"); }
+
+    std::vector<BatchProd> prods(std::max(count, 1));
+    size_t nitems = 0;
+    plan_batch(count, problems, cfgs, prods.data(), &b->groups, &nitems);
 
     // one allocation: products | items | tile counts | times
     auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
@@ -142,13 +159,11 @@ int gfq::batch_create_with(int count, const gfq_problem *problems, const gfq_con
     if (e != hipSuccess) { batch_release(b); hip_fail(e, "hipMalloc(batch)"); return GFQ_ENOMEM; }
     char *base = (char *)b->mem;
     std::vector<BatchItem> all(std::max<size_t>(nitems, 1));
-    for (const Group &gr : b->groups) std::copy(gr.items.begin(), gr.items.end(), all.begin() + gr.item_off);
+    for (const BatchGroup &gr : b->groups) std::copy(gr.items.begin(), gr.items.end(), all.begin() + gr.item_off);
     e = hipMemset(b->mem, 0, total);
     if (e == hipSuccess && count > 0) e = hipMemcpy(base, prods.data(), sizeof(BatchProd) * count, hipMemcpyHostToDevice);
     if (e == hipSuccess && nitems > 0) e = hipMemcpy(base + off_items, all.data(), sizeof(BatchItem) * nitems, hipMemcpyHostToDevice);
-    for (size_t j = 0; e == hipSuccess && j < b->groups.size(); j++)
-        e = hipFuncSetAttribute(batched_kernel(b->groups[j].q, b->groups[j].R),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->groups[j].lds);
+    if (e == hipSuccess) e = set_batched_lds_limits();
     if (e != hipSuccess) { batch_release(b); return hip_fail(e, "batch upload"); }
     b->prods = (BatchProd *)base;
     b->items = (BatchItem *)(base + off_items);
@@ -169,7 +184,7 @@ int gfq_batch_launch(gfq_batch *b) {
     hipStream_t st = current_stream();
     hipError_t e = launch_batch_stamp(b->times, st);
     for (size_t j = 0; e == hipSuccess && j < b->groups.size(); j++) {
-        const Group &gr = b->groups[j];
+        const BatchGroup &gr = b->groups[j];
         BatchList l;
         l.prods = b->prods;
         l.items = b->items + gr.item_off;

@@ -3,7 +3,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "gfq.h"
+#include "gfq_batch.h"
 #include "gfq_internal.h"
 
 namespace gfq {
@@ -14,6 +17,22 @@ int hip_fail(hipError_t e, const char *what);
 hipStream_t current_stream();
 // Build a batch; cfgs (optional, one per product) overrides the per-product configuration.
 int batch_create_with(int count, const gfq_problem *problems, const gfq_config *cfgs, gfq_batch **out);
+// The tiles of one (field, rows per lane) work list of a batch.
+struct BatchGroup {
+    int q = 0, R = 0, kmax = 1;
+    size_t lds = 0;                  // dynamic LDS of the list's launch
+    size_t item_off = 0;             // index of the group's first item in the batch's item array
+    std::vector<BatchItem> items;    // longest first
+    std::vector<double> cost;        // planning only
+};
+// Per-product launch parameters (prods[0 .. count)) and the non-empty work lists, with
+// consecutive item offsets; *nitems = total tiles.  The problems must be valid.
+void plan_batch(int count, const gfq_problem *problems, const gfq_config *cfgs, BatchProd *prods,
+                std::vector<BatchGroup> *groups, size_t *nitems);
+// Upper bound of the tiles of an m x n product in any batch (the smallest tile height).
+size_t batch_tiles_bound(int64_t m, int64_t n);
+// Allow every batched work-list kernel the dynamic LDS of its largest slab width.
+hipError_t set_batched_lds_limits();
 // Fill n words with pseudo-random bits (a hash of the index and the seed); timing data only.
 hipError_t launch_fill_random(u32 *p, size_t n, u32 seed, hipStream_t st);
 // Field, dimension, pointer, alignment and aliasing checks of one product.

@@ -85,6 +85,22 @@ inline MMPlan mm_plan(int q, int k, int rowsTile) {
 
 hipError_t launch_matmul(int q, const MMArgs &a, const MMPlan &plan, hipStream_t st);
 hipError_t launch_reduce(int q, const u32 *part, u32 *C, int m, int n, int Wn, int splits, size_t stride, hipStream_t st);
+// One pack (uint8 -> planes) or unpack (planes -> uint8) job of a conversion list.  The
+// uint8 side has leading dimension ld; the packed side has W words per plane row.  Jobs are
+// ordered by first_block, the first workgroup of the job in the launch (the first job's is
+// 0); a job covers ceil(rows * units per row / 256) workgroups.
+struct ConvJob {
+    const void *src;
+    void *dst;
+    int64_t ld;
+    int rows, cols, W;
+    int q, pack, aligned;
+    u32 first_block;
+    u32 pad;
+};
+u32 conv_job_blocks(const ConvJob &j);
+hipError_t launch_conv_list(const ConvJob *jobs, int njobs, u32 blocks, hipStream_t st);
+
 hipError_t launch_pack(int q, const uint8_t *src, int64_t ld, u32 *dst, int rows, int cols, int W, hipStream_t st);
 hipError_t launch_unpack(int q, const u32 *src, uint8_t *dst, int64_t ld, int rows, int cols, int W, hipStream_t st);
 

@@ -37,6 +37,29 @@ class Problem(ctypes.Structure):
                 ("C", ctypes.c_void_p)]
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_size_t), ("slots", ctypes.c_int), ("max_batch", ctypes.c_int),
+                ("max_items", ctypes.c_int), ("mode", ctypes.c_int)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_int), ("m", ctypes.c_int64), ("l", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("A", ctypes.c_void_p), ("lda", ctypes.c_int64), ("B", ctypes.c_void_p), ("ldb", ctypes.c_int64),
+                ("C", ctypes.c_void_p), ("ldc", ctypes.c_int64), ("flags", ctypes.c_int),
+                ("tag", ctypes.c_uint64), ("not_before_us", ctypes.c_double)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int), ("batch_size", ctypes.c_int),
+                ("arrival_us", ctypes.c_double), ("launch_us", ctypes.c_double), ("done_us", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("batches", ctypes.c_int64),
+                ("queued", ctypes.c_int64), ("max_batch_seen", ctypes.c_int64), ("arena_in_use", ctypes.c_size_t),
+                ("arena_held", ctypes.c_size_t), ("arena_peak_in_use", ctypes.c_size_t)]
+
+
 _lib = None
 _I64 = ctypes.c_int64
 _VP = ctypes.c_void_p
@@ -58,6 +81,13 @@ _SIGS = {
     "gfq_tune_save": (ctypes.c_int, [ctypes.c_char_p]),
     "gfq_tune_load": (ctypes.c_int, [ctypes.c_char_p]),
     "gfq_tune_clear": (ctypes.c_int, []),
+    "gfq_server_create": (ctypes.c_int, [ctypes.POINTER(ServerOpts), ctypes.POINTER(_VP)]),
+    "gfq_server_submit": (ctypes.c_int, [_VP, ctypes.POINTER(Request), ctypes.c_int]),
+    "gfq_server_poll": (ctypes.c_int, [_VP, ctypes.POINTER(Completion), ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                       ctypes.c_double]),
+    "gfq_server_now_us": (ctypes.c_double, [_VP]),
+    "gfq_server_stats_read": (ctypes.c_int, [_VP, ctypes.POINTER(ServerStats)]),
+    "gfq_server_destroy": (ctypes.c_int, [_VP]),
     "gfq_set_stream": (ctypes.c_int, [_VP]),
     "gfq_sync": (ctypes.c_int, []),
     "gfq_set_timing": (ctypes.c_int, [ctypes.c_int]),
@@ -268,3 +298,89 @@ def matmul_unpacked(q: int, A_u8, B_u8, **kw):
     Bp = pack(q, B_u8)
     Cp = matmul(q, Ap, Bp, m, l, n, **kw)
     return unpack(q, Cp, m, n)
+
+
+REQ_A_PACKED, REQ_B_PACKED, REQ_C_PACKED = 1, 2, 4
+
+
+def _operand(X, rows: int, cols: int, packed: bool):
+    """(pointer, leading dimension) of a device operand: a 2-D uint8 tensor (rows may be
+    strided, columns contiguous) or, when packed, any tensor holding the packed matrix."""
+    if X is None:
+        return None, 0
+    if packed:
+        return X.data_ptr(), 0
+    assert X.dim() == 2 and tuple(X.shape) == (rows, cols) and (cols <= 1 or X.stride(1) == 1), \
+        (tuple(X.shape), (rows, cols))
+    return X.data_ptr(), max(X.stride(0), cols)
+
+
+class Server:
+    """Continuous-batching product server (gfq_server_*).  submit() queues requests and
+    keeps their tensors alive until poll() has returned their completions."""
+
+    def __init__(self, budget_bytes: int = 0, slots: int = 0, max_batch: int = 0, max_items: int = 0,
+                 serial: bool = False):
+        o = ServerOpts(budget_bytes, slots, max_batch, max_items, 1 if serial else 0)
+        h = _VP()
+        _check(load().gfq_server_create(ctypes.byref(o), ctypes.byref(h)), "gfq_server_create")
+        self.handle = h
+        self._keep = {}
+
+    @staticmethod
+    def request(q, m, l, n, A, B, C, tag, not_before_us=0.0, flags=0) -> Request:
+        a, lda = _operand(A, m, l, flags & REQ_A_PACKED)
+        b, ldb = _operand(B, l, n, flags & REQ_B_PACKED)
+        c, ldc = _operand(C, m, n, flags & REQ_C_PACKED)
+        return Request(q, m, l, n, a, lda, b, ldb, c, ldc, flags, tag, not_before_us)
+
+    def submit(self, reqs: Sequence[Request], keep: Sequence = ()):
+        """Queue requests (Request structures); keep[i] (optional) is held until request i
+        completes."""
+        arr = (Request * len(reqs))(*reqs)
+        _check(load().gfq_server_submit(self.handle, arr, len(reqs)), "gfq_server_submit")
+        for i, r in enumerate(reqs):
+            if i < len(keep):
+                self._keep[r.tag] = keep[i]
+
+    def poll(self, max_count: int = 4096, timeout_us: float = 0.0):
+        buf = (Completion * max_count)()
+        got = ctypes.c_int()
+        _check(load().gfq_server_poll(self.handle, buf, max_count, ctypes.byref(got), timeout_us), "gfq_server_poll")
+        out = []
+        for i in range(got.value):
+            c = buf[i]
+            self._keep.pop(c.tag, None)
+            out.append({"tag": c.tag, "status": c.status, "batch_size": c.batch_size,
+                        "arrival_us": c.arrival_us, "launch_us": c.launch_us, "done_us": c.done_us})
+        return out
+
+    def wait_all(self, count: int, timeout_s: float = 60.0):
+        """Poll until count completions have arrived (raises on timeout)."""
+        import time
+        out, t_end = [], time.monotonic() + timeout_s
+        while len(out) < count:
+            if time.monotonic() > t_end:
+                raise TimeoutError(f"{len(out)} of {count} completions after {timeout_s} s")
+            out += self.poll(timeout_us=20000.0)
+        return out
+
+    def now_us(self) -> float:
+        return load().gfq_server_now_us(self.handle)
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(load().gfq_server_stats_read(self.handle, ctypes.byref(st)), "gfq_server_stats_read")
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def destroy(self):
+        if self.handle:
+            _check(load().gfq_server_destroy(self.handle), "gfq_server_destroy")
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
