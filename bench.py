@@ -1,16 +1,24 @@
 """Benchmark of the bitsliced Four-Russians product on one MI355X.
 
-Workload: the plain single products over F_3 and F_5, A and B 8192 x 8192 with i.i.d.
-uniform entries (seeded).  One step is the whole path for both products: pack A and B
-(uint8 -> bit-planes), the Four-Russians product (and the partial-sum kernel when the
-inner dimension is split), unpack C.  Inputs are resident in HBM before timing starts.
+Headline workload (the `value`): the plain single products over F_3 and F_5, A and B
+8192 x 8192 with i.i.d. uniform entries (seeded).  One step is the whole path for both
+products: pack A and B (uint8 -> bit-planes), the Four-Russians product (and the
+partial-sum kernel when the inner dimension is split), unpack C.  Inputs are resident in
+HBM before timing starts.
 
 Printed: one JSON line with field-ops/s (2 m l n / t) for the whole step, the roofline of
-the dominant kernel (the product kernel of the field that takes longest), and the CPU
-oracle timed on a bounded row sample of the same products (its rows are also compared
-bit-exactly with the GPU product).
+the dominant kernel (the product kernel of the field that takes longest), the CPU oracle
+timed on a bounded row sample of the same products (its rows are also compared bit-exactly
+with the GPU product), and sections for the other workloads:
+  c1       F_3 512^3: per-product latency p50/p99 and the oracle's time for the product
+  c2_k     the 8192^3 products with the slab width k swept 4..10 (each bit-exact)
+  c3       F_7 and GF(4), A 16384 x 2048 times B 2048 x 16384, dense and 10% density
+  c4       4096 products of mixed fields and log-uniform shapes: one batched launch
+           (captured in a HIP graph) against one plain launch per product
+  c5       served requests with Poisson arrivals: continuous batching against serial
+           plain launches over the same trace, latency p50/p99 and throughput
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--only c1,c5] [--c5-requests N]
 """
 from __future__ import annotations
 
@@ -27,6 +35,7 @@ M = L = N = 8192
 FIELDS = (3, 5)
 PEAK_VALU_OPS = 256 * 64 * 2.4e9          # 32-bit VALU lane-operations per second
 PEAK_HBM = 8.0e12
+SECTIONS = ("c1", "c2_k", "c3", "c4", "c5")
 
 # Per-unit operation counts of the method on gfx950 (three-input bitwise instructions).
 # A unit is (row of C, slab of k rows of B, 32-column word).  Accumulate: carry-save
@@ -43,10 +52,10 @@ C_ADD_PAPER = {3: 6, 4: 2, 5: 20, 7: 17}
 # HBM traffic of the product kernels from rocprofv3 FETCH_SIZE / WRITE_SIZE passes on this
 # workload, scaled by the same counters on a 1 GiB device copy (reads x 2.0, writes x 1.0);
 # valid only while the kernel sources hash to `src` (otherwise the roofline reports null).
-KERNEL_SOURCES = ("gfq_m4rm.hip", "gfq_device.h", "gfq_field.h", "gfq_internal.h")
+KERNEL_SOURCES = ("gfq_m4rm.hip", "gfq_m4rm_tile.h", "gfq_device.h", "gfq_field.h", "gfq_internal.h")
 MEASURED_TRAFFIC = {
-    3: {"src": "928ca375c42b3e04", "read_mib": 643.1, "write_mib": 32.0},
-    5: {"src": "928ca375c42b3e04", "read_mib": 248.2, "write_mib": 24.0},
+    3: {"src": "4033fe525fd500ec", "read_mib": 652.1, "write_mib": 32.0},
+    5: {"src": "4033fe525fd500ec", "read_mib": 295.9, "write_mib": 24.0},
 }
 
 
@@ -70,14 +79,34 @@ def algorithmic_ops(q, m, l, n, k, acc, add, fin=None):
 
 def percentile(xs, p):
     xs = sorted(xs)
+    if not xs:
+        return None
     i = min(len(xs) - 1, max(0, int(round(p / 100.0 * (len(xs) - 1)))))
     return xs[i]
 
 
-def cpu_baseline(torch, gfq, oracle, data, seconds=10.0):
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+class Ctx:
+    def __init__(self, torch, gfq, inputs, oracle_mod):
+        self.torch, self.gfq, self.inputs, self.oracle = torch, gfq, inputs, oracle_mod
+        self.dev = torch.device("cuda", 0)
+
+    def up(self, x):
+        import numpy as np
+        return self.torch.from_numpy(np.ascontiguousarray(x)).to(self.dev)
+
+    def events(self, n):
+        return [self.torch.cuda.Event(enable_timing=True) for _ in range(n)]
+
+
+def cpu_baseline(ctx, data, seconds=10.0):
     """Time the oracle on the first rows of A for each field (about `seconds` in total) and
     compare those rows with the GPU product."""
     import numpy as np
+    oracle = ctx.oracle
     per_field = seconds / len(FIELDS)
     total_ops, total_t, rows_done, match = 0.0, 0.0, {}, True
     for q in FIELDS:
@@ -107,54 +136,28 @@ def cpu_baseline(torch, gfq, oracle, data, seconds=10.0):
     }
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--copy-mb", type=int, default=0,
-                    help="first run one device-to-device copy of this many MiB (a kernel of known "
-                         "traffic that calibrates hardware memory counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the library drives one "
-              f"MI355X and reports that GPU's throughput", file=sys.stderr)
-        sys.exit(2)
+# ------------------------------------------------------------------------------------
+# headline: F_3 and F_5 8192^3, whole path
+# ------------------------------------------------------------------------------------
 
-    import numpy as np
-    import torch
-
-    from paper_0901_1413_amd import gfq, inputs
-
-    torch.cuda.set_device(0)
-    dev = torch.device("cuda", 0)
-    gfq.load()
-
-    if args.copy_mb:
-        src = torch.ones(args.copy_mb << 20, dtype=torch.uint8, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-
+def headline(ctx, args):
+    torch, gfq, inputs = ctx.torch, ctx.gfq, ctx.inputs
     data = {}
     for q in FIELDS:
         A, B = inputs.pair(q, M, L, N, cfg=2, idx=q)
         cfg = gfq.choose_config(q, M, L, N)
         data[q] = {
             "A": A, "B": B, "cfg": cfg,
-            "Ad": torch.from_numpy(A).to(dev), "Bd": torch.from_numpy(B).to(dev),
+            "Ad": ctx.up(A), "Bd": ctx.up(B),
             "Ap": gfq.empty_packed(q, M, L), "Bp": gfq.empty_packed(q, L, N), "Cp": gfq.empty_packed(q, M, N),
-            "Cd": torch.empty((M, N), dtype=torch.uint8, device=dev),
+            "Cd": torch.empty((M, N), dtype=torch.uint8, device=ctx.dev),
         }
     torch.cuda.synchronize()
 
     def step(record=None):
         for q in FIELDS:
             d = data[q]
-            e0 = torch.cuda.Event(enable_timing=True) if record is not None else None
-            e1 = torch.cuda.Event(enable_timing=True) if record is not None else None
+            e0, e1 = ctx.events(2) if record is not None else (None, None)
             if e0 is not None:
                 e0.record()
             gfq.pack(q, d["Ad"], out=d["Ap"])
@@ -169,11 +172,8 @@ def main():
         step()
     torch.cuda.synchronize()
 
-    # timed region: K steps, per-product events, library events around every kernel
     per_product = []
-    kernel_ms = {q: [] for q in FIELDS}
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
+    t_start, t_end = ctx.events(2)
     torch.cuda.synchronize()
     t_start.record()
     for _ in range(args.steps):
@@ -183,6 +183,7 @@ def main():
     total_ms = t_start.elapsed_time(t_end)
 
     # product-kernel durations, measured in separate passes with library timing on
+    kernel_ms = {}
     gfq.set_timing(True)
     for q in FIELDS:
         d = data[q]
@@ -195,9 +196,8 @@ def main():
                         "reduce_ms": (t["reduce_ms"] / t["reduce_launches"]) if t["reduce_launches"] else 0.0}
     gfq.set_timing(False)
 
-    ops_per_step = sum(2.0 * M * L * N for _ in FIELDS)
     ms_per_step = total_ms / args.steps
-    value = ops_per_step / (ms_per_step * 1e-3)
+    value = sum(2.0 * M * L * N for _ in FIELDS) / (ms_per_step * 1e-3)
     lat = {}
     for q in FIELDS:
         xs = [e0.elapsed_time(e1) for (qq, e0, e1) in per_product if qq == q]
@@ -211,19 +211,18 @@ def main():
         ops = algorithmic_ops(q, M, L, N, c["k"], C_ACC, C_ADD)
         ops_paper = algorithmic_ops(q, M, L, N, c["k"], C_ACC_PAPER, C_ADD_PAPER)
         ach = ops / dur
+        tr = MEASURED_TRAFFIC.get(q, {})
         rooflines.append({
             "kernel": f"m4rm_kernel<F_{q}>", "bound": "alu",
             "achieved": round(ach / 1e12, 3), "peak": round(PEAK_VALU_OPS / 1e12, 3), "unit": "Tops/s",
             "frac": round(ach / PEAK_VALU_OPS, 4),
-            "traffic": (round((MEASURED_TRAFFIC[q]["read_mib"] + MEASURED_TRAFFIC[q]["write_mib"]) * 2 ** 20)
-                        if MEASURED_TRAFFIC.get(q, {}).get("src") == src_hash else None),
+            "traffic": (round((tr["read_mib"] + tr["write_mib"]) * 2 ** 20) if tr.get("src") == src_hash else None),
             "avg_ms": round(kernel_ms[q]["product_ms"], 4),
             "partial_sum_ms": round(kernel_ms[q]["reduce_ms"], 4),
             "paper_op_frac": round(ops_paper / dur / PEAK_VALU_OPS, 4),
             "config": c,
         })
     dominant = max(rooflines, key=lambda r: r["avg_ms"])
-
     out = {
         "metric": "GF(q) matmul field-ops/s (2mln/t) batched vs plain, 1 MI355X; p99 latency",
         "value": value,
@@ -245,11 +244,400 @@ def main():
         "roofline_kernels": rooflines,
         "latency_per_product": lat,
     }
+    return out, data
+
+
+# ------------------------------------------------------------------------------------
+# c1: F_3 512^3
+# ------------------------------------------------------------------------------------
+
+def section_c1(ctx, reps=200):
+    import numpy as np
+    torch, gfq, inputs = ctx.torch, ctx.gfq, ctx.inputs
+    n = 512
+    A, B = inputs.pair(3, n, n, n, cfg=1, idx=0)
+    Ad, Bd = ctx.up(A), ctx.up(B)
+    Ap, Bp, Cp = gfq.empty_packed(3, n, n), gfq.empty_packed(3, n, n), gfq.empty_packed(3, n, n)
+    Cd = torch.empty((n, n), dtype=torch.uint8, device=ctx.dev)
+
+    def path():
+        gfq.pack(3, Ad, out=Ap)
+        gfq.pack(3, Bd, out=Bp)
+        gfq.matmul(3, Ap, Bp, n, n, n, out=Cp)
+        gfq.unpack(3, Cp, n, n, out=Cd)
+
+    for _ in range(10):
+        path()
+    torch.cuda.synchronize()
+    res = {}
+    for name, fn in (("path", path), ("product", lambda: gfq.matmul(3, Ap, Bp, n, n, n, out=Cp))):
+        ev = ctx.events(2 * reps)
+        for i in range(reps):
+            ev[2 * i].record()
+            fn()
+            ev[2 * i + 1].record()
+        torch.cuda.synchronize()
+        xs = [ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(reps)]
+        res[name] = {"p50_us": round(percentile(xs, 50) * 1e3, 2), "p99_us": round(percentile(xs, 99) * 1e3, 2),
+                     "field_ops_per_s_at_p50": 2.0 * n ** 3 / (percentile(xs, 50) * 1e-3)}
+    path()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    want = ctx.oracle.matmul(3, A, B)
+    t_or = time.perf_counter() - t0
+    return {"workload": "F_3 A, B 512x512 uniform", "reps": reps, **res,
+            "bit_exact_vs_oracle": bool(np.array_equal(Cd.cpu().numpy(), want)),
+            "oracle_ms": round(t_or * 1e3, 2), "oracle_cores": ctx.oracle.max_threads(),
+            "config": gfq.choose_config(3, n, n, n)}
+
+
+# ------------------------------------------------------------------------------------
+# c2_k: slab width sweep on the headline products
+# ------------------------------------------------------------------------------------
+
+def section_c2_k(ctx, data, reps=3):
+    torch, gfq = ctx.torch, ctx.gfq
+    out = {}
+    for q in FIELDS:
+        d = data[q]
+        ref = d["Cp"]
+        nb = gfq.packed_bytes(q, M, N)
+        Ck = gfq.empty_packed(q, M, N)
+        rows = []
+        for k in range(4, 11):
+            gfq.matmul(q, d["Ap"], d["Bp"], M, L, N, out=Ck, k=k)
+            torch.cuda.synchronize()
+            same = bool(torch.equal(Ck[:nb], ref[:nb]))
+            gfq.set_timing(True)
+            gfq.timing_read()
+            for _ in range(reps):
+                gfq.matmul(q, d["Ap"], d["Bp"], M, L, N, out=Ck, k=k)
+            torch.cuda.synchronize()
+            t = gfq.timing_read()
+            gfq.set_timing(False)
+            pm = t["product_ms"] / t["product_launches"]
+            rm = (t["reduce_ms"] / t["reduce_launches"]) if t["reduce_launches"] else 0.0
+            ops = algorithmic_ops(q, M, L, N, k, C_ACC, C_ADD)
+            rows.append({"k": k, "product_ms": round(pm, 4), "partial_sum_ms": round(rm, 4),
+                         "field_ops_per_s": 2.0 * M * L * N / ((pm + rm) * 1e-3),
+                         "alu_frac": round(ops / (pm * 1e-3) / PEAK_VALU_OPS, 4), "bit_exact": same})
+        out[f"F_{q}"] = rows
+    return out
+
+
+# ------------------------------------------------------------------------------------
+# c3: F_7 and GF(4), 16384 x 2048 times 2048 x 16384, dense and 10% density
+# ------------------------------------------------------------------------------------
+
+def section_c3(ctx, reps=3, sample_rows=32):
+    import numpy as np
+    torch, gfq, inputs = ctx.torch, ctx.gfq, ctx.inputs
+    m, l, n = 16384, 2048, 16384
+    res = {}
+    for q in (7, 4):
+        for density in (1.0, 0.1):
+            A, B = inputs.pair(q, m, l, n, cfg=3, idx=q, density=density)
+            Ad, Bd = ctx.up(A), ctx.up(B)
+            Ap, Bp, Cp = gfq.empty_packed(q, m, l), gfq.empty_packed(q, l, n), gfq.empty_packed(q, m, n)
+            Cd = torch.empty((m, n), dtype=torch.uint8, device=ctx.dev)
+
+            def path():
+                gfq.pack(q, Ad, out=Ap)
+                gfq.pack(q, Bd, out=Bp)
+                gfq.matmul(q, Ap, Bp, m, l, n, out=Cp)
+                gfq.unpack(q, Cp, m, n, out=Cd)
+
+            path()
+            torch.cuda.synchronize()
+            ev = ctx.events(2)
+            ev[0].record()
+            for _ in range(reps):
+                path()
+            ev[1].record()
+            torch.cuda.synchronize()
+            path_ms = ev[0].elapsed_time(ev[1]) / reps
+            gfq.set_timing(True)
+            gfq.timing_read()
+            for _ in range(reps):
+                gfq.matmul(q, Ap, Bp, m, l, n, out=Cp)
+            torch.cuda.synchronize()
+            t = gfq.timing_read()
+            gfq.set_timing(False)
+            pm = t["product_ms"] / t["product_launches"]
+            rm = (t["reduce_ms"] / t["reduce_launches"]) if t["reduce_launches"] else 0.0
+            cfg = gfq.choose_config(q, m, l, n)
+            rows = np.sort(inputs.rng(3, q, 3).choice(m, size=sample_rows, replace=False))
+            got = Cd[torch.from_numpy(rows).to(ctx.dev)].cpu().numpy()
+            ok = bool(np.array_equal(got, ctx.oracle.matmul(q, A[rows], B)))
+            ops = algorithmic_ops(q, m, l, n, cfg["k"], C_ACC, C_ADD)
+            name = ("GF4" if q == 4 else f"F_{q}") + ("" if density == 1.0 else "_density0.1")
+            res[name] = {"path_ms": round(path_ms, 4), "product_ms": round(pm, 4), "partial_sum_ms": round(rm, 4),
+                         "field_ops_per_s_path": 2.0 * m * l * n / (path_ms * 1e-3),
+                         "field_ops_per_s_product": 2.0 * m * l * n / ((pm + rm) * 1e-3),
+                         "alu_frac": round(ops / (pm * 1e-3) / PEAK_VALU_OPS, 4), "config": cfg,
+                         "sampled_rows_bit_exact": ok, "sampled_rows": sample_rows}
+            del Ad, Bd, Ap, Bp, Cp, Cd
+    return {"workload": "A 16384x2048, B 2048x16384; uniform and 10% density", **res}
+
+
+# ------------------------------------------------------------------------------------
+# c4: 4096 products of mixed fields and shapes, batched vs plain
+# ------------------------------------------------------------------------------------
+
+def section_c4(ctx, count=4096, reps=5, pool=2048):
+    import numpy as np
+    torch, gfq, inputs = ctx.torch, ctx.gfq, ctx.inputs
+    specs = inputs.batch_specs(count, cfg=4)
+    offs = inputs.window_offsets(4, [(m, l, n) for (_, m, l, n) in specs], pool)
+    pools_h = {q: (inputs.matrix(q, pool, pool, cfg=4, idx=q, which=0),
+                   inputs.matrix(q, pool, pool, cfg=4, idx=q, which=1)) for q in (3, 5, 7)}
+    pools = {q: (ctx.up(a), ctx.up(b)) for q, (a, b) in pools_h.items()}
+    probs, plain_out = [], []
+    for (q, m, l, n), (ra, ca, rb, cb) in zip(specs, offs):
+        Pa, Pb = pools[q]
+        probs.append((q, m, l, n, gfq.pack(q, Pa[ra:ra + m, ca:ca + l]), gfq.pack(q, Pb[rb:rb + l, cb:cb + n]),
+                      gfq.empty_packed(q, m, n)))
+        plain_out.append(gfq.empty_packed(q, m, n))
+    torch.cuda.synchronize()
+    ops = sum(2.0 * m * l * n for (_, m, l, n) in specs)
+
+    b = gfq.Batch(probs)
+    b.launch()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(graph, stream=side):
+            b.launch()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph.replay()
+    torch.cuda.synchronize()
+    ev = ctx.events(2)
+    ev[0].record()
+    for _ in range(reps):
+        graph.replay()
+    ev[1].record()
+    torch.cuda.synchronize()
+    batched_ms = ev[0].elapsed_time(ev[1]) / reps
+    graph.replay()
+    torch.cuda.synchronize()
+    done_us = sorted(b.times_us())
+
+    def plain():
+        for (q, m, l, n, A, B, _), C in zip(probs, plain_out):
+            gfq.matmul(q, A, B, m, l, n, out=C)
+
+    plain()
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(reps):
+        plain()
+    ev[1].record()
+    torch.cuda.synchronize()
+    plain_ms = ev[0].elapsed_time(ev[1]) / reps
+    same = all(torch.equal(C[:gfq.packed_bytes(q, m, n)], C2[:gfq.packed_bytes(q, m, n)])
+               for (q, m, l, n, _, _, C), C2 in zip(probs, plain_out))
+    # oracle on a seeded sample of the products
+    pick = inputs.rng(4, 2, 2).choice(count, size=8, replace=False)
+    ok = True
+    for i in pick:
+        q, m, l, n = specs[i]
+        ra, ca, rb, cb = offs[i]
+        want = ctx.oracle.matmul(q, pools_h[q][0][ra:ra + m, ca:ca + l], pools_h[q][1][rb:rb + l, cb:cb + n])
+        ok = ok and bool(np.array_equal(gfq.unpack(q, probs[i][6], m, n).cpu().numpy(), want))
+    del graph
+    b.destroy()
+    return {"workload": f"{count} products, field uniform over F_3/F_5/F_7, m, l, n log-uniform in [64, 2048], "
+                        f"operands uniform windows of seeded {pool}x{pool} pools",
+            "field_ops": ops,
+            "batched_ms": round(batched_ms, 4), "batched_field_ops_per_s": ops / (batched_ms * 1e-3),
+            "batched_launch": "work lists per (field, tile height), captured in one HIP graph",
+            "plain_ms": round(plain_ms, 4), "plain_field_ops_per_s": ops / (plain_ms * 1e-3),
+            "speedup": round(plain_ms / batched_ms, 2),
+            "completion_p50_us": round(percentile(done_us, 50), 1),
+            "completion_p99_us": round(percentile(done_us, 99), 1),
+            "batched_equals_plain": same, "oracle_sample_bit_exact": ok,
+            "tuned_classes_used": ctx.tuned}
+
+
+# ------------------------------------------------------------------------------------
+# c5: served requests, continuous batching vs serial plain launches
+# ------------------------------------------------------------------------------------
+
+def section_c5(ctx, count=20000, budget=200 * 10 ** 9, pool=4096, load=0.8):
+    import numpy as np
+    torch, gfq, inputs = ctx.torch, ctx.gfq, ctx.inputs
+    trace = inputs.request_trace(count, cfg=5)                 # unit-rate arrivals, rescaled below
+    shapes = [(n, n, n) for (_, _, n) in trace]
+    offs = inputs.window_offsets(5, shapes, pool)
+    qs = sorted({q for (_, q, _) in trace})
+    pools_h = {q: (inputs.matrix(q, pool, pool, cfg=5, idx=q, which=0),
+                   inputs.matrix(q, pool, pool, cfg=5, idx=q, which=1)) for q in qs}
+    pools = {q: (ctx.up(a), ctx.up(b)) for q, (a, b) in pools_h.items()}
+    sizes = np.array([n * n for (_, _, n) in trace], dtype=np.int64)
+    starts = np.concatenate([[0], np.cumsum(((sizes + 255) // 256) * 256)[:-1]])
+    total = int(starts[-1] + sizes[-1] + 256)
+    outs = [torch.empty(total, dtype=torch.uint8, device=ctx.dev) for _ in range(2)]
+    ops = np.array([2.0 * n ** 3 for (_, _, n) in trace])
+
+    def requests(out, idx, t0_us, us_per_unit):
+        rs = []
+        base = out.data_ptr()
+        for i in idx:
+            t, q, n = trace[i]
+            ra, ca, rb, cb = offs[i]
+            Pa, Pb = pools[q]
+            rs.append(gfq.Request(q, n, n, n, Pa.data_ptr() + ra * pool + ca, pool, Pb.data_ptr() + rb * pool + cb,
+                                  pool, base + int(starts[i]), n, 0, i, t0_us + t * us_per_unit))
+        return rs
+
+    def run(srv, idx, out, us_per_unit, timeout_s):
+        t0 = srv.now_us() + 20000.0
+        rs = requests(out, idx, t0 if us_per_unit else 0.0, us_per_unit)
+        srv.submit(rs)
+        comps, t_end, t_log = [], time.monotonic() + timeout_s, time.monotonic() + 10.0
+        while len(comps) < len(rs):
+            if time.monotonic() > t_end:
+                raise TimeoutError(f"c5: {len(comps)} of {len(rs)} requests done after {timeout_s} s")
+            comps += srv.poll(timeout_us=20000.0)
+            if time.monotonic() > t_log:
+                log(f"c5: {len(comps)} of {len(rs)} requests done")
+                t_log += 10.0
+        assert all(c["status"] == 0 for c in comps), [c for c in comps if c["status"]][:3]
+        return comps
+
+    def summary(comps, srv):
+        lat = [(c["done_us"] - c["arrival_us"]) * 1e-3 for c in comps]
+        first = min(c["arrival_us"] for c in comps)
+        last = max(c["done_us"] for c in comps)
+        tot = sum(ops[c["tag"]] for c in comps)
+        st = srv.stats()
+        return {"requests": len(comps), "span_s": round((last - first) * 1e-6, 4),
+                "field_ops_per_s": tot / ((last - first) * 1e-6),
+                "requests_per_s": len(comps) / ((last - first) * 1e-6),
+                "latency_p50_ms": round(percentile(lat, 50), 3), "latency_p99_ms": round(percentile(lat, 99), 3),
+                "latency_max_ms": round(max(lat), 3),
+                "batches": st["batches"], "mean_batch": round(st["completed"] / max(1, st["batches"]), 2),
+                "max_batch": st["max_batch_seen"], "arena_peak_bytes": st["arena_peak_in_use"]}
+
+    torch.cuda.synchronize()
+    srv = gfq.Server(budget_bytes=budget, slots=3, max_batch=256)
+    # capacity: a prefix of the trace submitted at once, drained as fast as possible
+    cal = list(range(min(2000, count)))
+    comps = run(srv, cal, outs[0], 0.0, 300.0)
+    span = (max(c["done_us"] for c in comps) - min(c["arrival_us"] for c in comps)) * 1e-6
+    mu = len(cal) / span
+    lam = load * mu
+    us_per_unit = 1e6 / lam
+    log(f"c5: capacity {mu:.0f} req/s, offered {lam:.0f} req/s")
+    comps_b = run(srv, range(count), outs[0], us_per_unit, 600.0)
+    served = summary(comps_b, srv)
+    srv.destroy()
+    log("c5: continuous batching done; serial plain launches")
+    srv = gfq.Server(budget_bytes=budget, serial=True)
+    comps_s = run(srv, range(count), outs[1], us_per_unit, 900.0)
+    serial = summary(comps_s, srv)
+    srv.destroy()
+    torch.cuda.synchronize()
+    identical = bool(torch.equal(outs[0], outs[1]))
+    # oracle on a seeded sample of the smaller requests
+    small = [i for i, (_, _, n) in enumerate(trace) if n <= 512]
+    pick = inputs.rng(5, 2, 2).choice(len(small), size=min(16, len(small)), replace=False)
+    ok = True
+    for j in pick:
+        i = small[j]
+        _, q, n = trace[i]
+        ra, ca, rb, cb = offs[i]
+        want = ctx.oracle.matmul(q, pools_h[q][0][ra:ra + n, ca:ca + n], pools_h[q][1][rb:rb + n, cb:cb + n])
+        got = outs[0][int(starts[i]):int(starts[i]) + n * n].view(n, n).cpu().numpy()
+        ok = ok and bool(np.array_equal(got, want))
+    del outs
+    return {"workload": f"{count} requests, field uniform over {{3,4,5,7}}, square n log-uniform in [128, 4096], "
+                        f"Poisson arrivals at {load} x the measured capacity; operands uniform windows of seeded "
+                        f"{pool}x{pool} pools; result = unpacked uint8 C in device memory",
+            "budget_bytes": budget, "capacity_req_per_s": round(mu, 1), "offered_req_per_s": round(lam, 1),
+            "continuous_batching": served, "serial_plain": serial,
+            "p99_ratio_serial_over_batched": round(serial["latency_p99_ms"] / served["latency_p99_ms"], 2),
+            "results_identical_batched_vs_serial": identical, "oracle_sample_bit_exact": ok}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--only", default=",".join(SECTIONS),
+                    help="comma-separated sections after the headline (" + ",".join(SECTIONS) + "; empty = none)")
+    ap.add_argument("--c5-requests", type=int, default=20000)
+    ap.add_argument("--tune-file", default=os.path.join(ROOT, "paper_0901_1413_amd", "tuning", "gfx950.txt"),
+                    help="tuning cache to load (skipped if missing)")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="first run one device-to-device copy of this many MiB (a kernel of known "
+                         "traffic that calibrates hardware memory counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the library drives one "
+              f"MI355X and reports that GPU's throughput", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_0901_1413_amd import gfq, inputs
+    import oracle
+
+    torch.cuda.set_device(0)
+    gfq.load()
+    ctx = Ctx(torch, gfq, inputs, oracle)
+    ctx.tuned = False
+    if args.tune_file and os.path.exists(args.tune_file):
+        gfq.tune_load(args.tune_file)
+        ctx.tuned = True
+
+    if args.copy_mb:
+        src = torch.ones(args.copy_mb << 20, dtype=torch.uint8, device=ctx.dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    log("headline")
+    out, data = headline(ctx, args)
+    out["tuning_cache_loaded"] = ctx.tuned
+    sections = [s for s in args.only.split(",") if s]
+    res = {}
+    for s in sections:
+        if s not in SECTIONS:
+            raise SystemExit(f"unknown section {s}")
+    if "c2_k" in sections:
+        log("c2_k")
+        res["c2_k"] = section_c2_k(ctx, data)
     if not args.no_cpu:
         for q in FIELDS:
             data[q]["C_host"] = data[q]["Cd"].cpu().numpy()
-        import oracle
-        out["cpu_baseline"] = cpu_baseline(torch, gfq, oracle, data)
+        log("cpu baseline")
+        out["cpu_baseline"] = cpu_baseline(ctx, data)
+    del data
+    torch.cuda.empty_cache()
+    if "c1" in sections:
+        log("c1")
+        res["c1"] = section_c1(ctx)
+    if "c3" in sections:
+        log("c3")
+        res["c3"] = section_c3(ctx)
+        torch.cuda.empty_cache()
+    if "c4" in sections:
+        log("c4")
+        res["c4"] = section_c4(ctx)
+        torch.cuda.empty_cache()
+    if "c5" in sections:
+        log("c5")
+        res["c5"] = section_c5(ctx, count=args.c5_requests)
+        torch.cuda.empty_cache()
+    if res:
+        out["sections"] = res
     print(json.dumps(out), flush=True)
 
 

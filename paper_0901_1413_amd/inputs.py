@@ -59,3 +59,18 @@ def request_trace(count: int, cfg: int, fields=(3, 5, 7, 4), lo: int = 128, hi: 
     gaps = g.exponential(1.0 / rate, size=count)
     t = np.cumsum(gaps)
     return [(float(t[i]), int(qs[i]), int(ns[i])) for i in range(count)]
+
+
+def window_offsets(cfg: int, shapes, pool: int):
+    """Seeded top-left corners for operand windows of pool x pool matrices: for each
+    (m, l, n) in shapes, (ra, ca) for an m x l window of the A pool and (rb, cb) for an
+    l x n window of the B pool, each uniform over the positions where the window fits.
+    Every window of a uniform i.i.d. pool is itself uniform i.i.d."""
+    g = rng(cfg, 1, META)
+    out = []
+    for (m, l, n) in shapes:
+        assert max(m, l, n) <= pool
+        ra, ca = g.integers(0, pool - m + 1), g.integers(0, pool - l + 1)
+        rb, cb = g.integers(0, pool - l + 1), g.integers(0, pool - n + 1)
+        out.append((int(ra), int(ca), int(rb), int(cb)))
+    return out

@@ -97,3 +97,42 @@ def test_c4_shaped_batch_sampled(gfq_gpu):
         nb = g.packed_bytes(q, m, n)
         assert np.array_equal(alone.cpu().numpy()[:nb], C.cpu().numpy()[:nb]), i
     check_against_oracle_and_alone(g, probs, host, range(0, 512, 37))
+
+
+def test_batch_graph_capture_replays(gfq_gpu):
+    """gfq_batch_launch allocates nothing and makes no synchronising call, so it can be
+    captured into a HIP graph; every replay (with eager work in between) equals the eager
+    launch bit for bit."""
+    import torch
+    g = gfq_gpu
+    specs = [(3, 300, 200, 100), (5, 64, 64, 64), (7, 1000, 900, 130), (4, 513, 127, 511), (5, 700, 1500, 900)]
+    probs, host = make_batch(g, specs, 311)
+    b = g.Batch(probs)
+    b.launch()
+    g.sync()
+    want = [C.clone() for (*_, C) in probs]
+    for i, (q, m, l, n, _, _, C) in enumerate(probs):
+        assert np.array_equal(g.unpack(q, C, m, n).cpu().numpy(), oracle.matmul(q, *host[i])), i
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(graph, stream=side):
+            b.launch()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    Ao, Bo = inputs.pair(3, 64, 64, 64, cfg=311, idx=99)
+    Aop, Bop = g.pack(3, dev(Ao)), g.pack(3, dev(Bo))
+    other = g.empty_packed(3, 64, 64)
+    for rep in range(4):
+        for (*_, C) in probs:
+            C.zero_()
+        g.matmul(3, Aop, Bop, 64, 64, 64, out=other)            # eager work between replays
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for i, (w, (*_, C)) in enumerate(zip(want, probs)):
+            assert torch.equal(w, C), (rep, i)
+        times = b.times_us()
+        assert all(t > 0 for t in times), (rep, times)
+    del graph
