@@ -285,8 +285,8 @@ int gfq_matmul_config(int q, int64_t m, int64_t l, int64_t n, const void *A, con
     const int P = planes_of(q);
     const int Wn = words_of(n);
     if (l == 0) {
-        hipError_t e = hipMemsetAsync(C, 0, gfq_packed_bytes(q, m, n), t_stream);
-        return e == hipSuccess ? GFQ_OK : hip_fail(e, "hipMemsetAsync");
+        hipError_t e = launch_fill_zero(C, gfq_packed_bytes(q, m, n), t_stream);
+        return e == hipSuccess ? GFQ_OK : hip_fail(e, "zero fill");
     }
     MMArgs a;
     a.A = (const u32 *)A;

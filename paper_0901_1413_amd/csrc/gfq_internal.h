@@ -101,6 +101,7 @@ struct ConvJob {
 u32 conv_job_blocks(const ConvJob &j);
 hipError_t launch_conv_list(const ConvJob *jobs, int njobs, u32 blocks, hipStream_t st);
 
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st);
 hipError_t launch_pack(int q, const uint8_t *src, int64_t ld, u32 *dst, int rows, int cols, int W, hipStream_t st);
 hipError_t launch_unpack(int q, const u32 *src, uint8_t *dst, int64_t ld, int rows, int cols, int W, hipStream_t st);
 

@@ -244,6 +244,8 @@ hipError_t launch_conv_list(const ConvJob *jobs, int njobs, u32 blocks, hipStrea
     return hipGetLastError();
 }
 
+static unsigned grid_for(int64_t work, int per_block);
+
 // Pseudo-random words for the tuner's scratch operands (timing only): a 32-bit mix of the
 // word index and a seed.
 __global__ __launch_bounds__(256) void fill_random_kernel(u32 *p, size_t n, u32 seed) {
@@ -252,6 +254,19 @@ __global__ __launch_bounds__(256) void fill_random_kernel(u32 *p, size_t n, u32 
         x ^= x >> 16; x *= 0x7feb352du; x ^= x >> 15; x *= 0x846ca68bu; x ^= x >> 16;
         p[i] = x;
     }
+}
+
+// Zero n words (a kernel rather than a memset node, so that captured graphs replay it).
+__global__ __launch_bounds__(256) void fill_zero_kernel(uint4 *p, size_t n16) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st) {
+    const size_t n16 = bytes / 16;             // packed buffers are whole 16-byte groups
+    if (n16 == 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for((int64_t)n16, 256)), dim3(256), 0, st, (uint4 *)p, n16);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill_random(u32 *p, size_t n, u32 seed, hipStream_t st) {
