@@ -26,7 +26,7 @@ template <> struct FT<3> {
     __device__ static void to_table(const u32 *x, u32 *t) { f3_to_bin(x[0], x[1], t); }
     __device__ static void tadd(const u32 *a, const u32 *b, u32 *r) { f3b_add(a, b, r); }
     __device__ static void tsub(const u32 *a, const u32 *b, u32 *r) { f3b_sub(a, b, r); }
-    __device__ static void acc_zero(u32 *c) { for (int i = 0; i < PA; i++) c[i] = 0u; }
+    __device__ static void acc_init(u32 *c, int) { for (int i = 0; i < PA; i++) c[i] = 0u; }
     __device__ static void accumulate(u32 *c, const u32 (*t)[P]) {
         u32 *S = c, *K = c + 2;
         csa_step<2>(S, K, t[0]);
@@ -58,7 +58,7 @@ template <> struct FT<7> {
         const u32 nb[3] = {~b[0], ~b[1], ~b[2]};
         tadd(a, nb, r);
     }
-    __device__ static void acc_zero(u32 *c) { for (int i = 0; i < PA; i++) c[i] = 0u; }
+    __device__ static void acc_init(u32 *c, int) { for (int i = 0; i < PA; i++) c[i] = 0u; }
     __device__ static void accumulate(u32 *c, const u32 (*t)[P]) {
         u32 *S = c, *K = c + 3;
         csa_step<3>(S, K, t[0]);
@@ -80,7 +80,8 @@ template <> struct FT<7> {
 
 // F_5 (Section 4.2).  Basis {1, 2, 4}, phi_d = plane d; table entries are 3-bit
 // representatives (4-bit sum, then fold5).  The accumulator works modulo 15 (4 planes per
-// half of the carry-save pair) and is reduced mod 5 once, at the end.
+// half of the carry-save pair) and is reduced mod 5 once, at the end; a slab's three
+// scaled rows enter it together (f5_csa_slab).
 template <> struct FT<5> {
     static constexpr int P = 3, D = 3, PA = 8;
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; f[2] = x[2]; }
@@ -94,16 +95,9 @@ template <> struct FT<5> {
         const u32 n[3] = {nb.b0, nb.b1, nb.b2};
         tadd(a, n, r);
     }
-    __device__ static void acc_zero(u32 *c) { for (int i = 0; i < PA; i++) c[i] = 0u; }
-    __device__ static void accumulate(u32 *c, const u32 (*t)[P]) {
-        u32 *S = c, *K = c + 4, x[4];
-        f5w_scaled(t[0], 1, x);
-        csa_step<4>(S, K, x);
-        f5w_scaled(t[1], 2, x);
-        csa_step<4>(S, K, x);
-        f5w_scaled(t[2], 4, x);
-        csa_step<4>(S, K, x);
-    }
+    // the accumulator starts at -7 x slabs (mod 15): each slab adds 4 T[phi_2] as 7 - T[phi_2]
+    __device__ static void acc_init(u32 *c, int slabs) { f5_csa_init(c, c + 4, slabs); }
+    __device__ static void accumulate(u32 *c, const u32 (*t)[P]) { f5_csa_slab(c, c + 4, t[0], t[1], t[2]); }
     __device__ static void finish(const u32 *c, u32 *out) {
         P3v s = fold5(c[0], c[1], c[2], c[3]);
         P3v k = fold5(c[4], c[5], c[6], c[7]);
@@ -125,7 +119,7 @@ template <> struct FT<4> {
     __device__ static void to_table(const u32 *x, u32 *t) { t[0] = x[0]; t[1] = x[1]; }
     __device__ static void tadd(const u32 *a, const u32 *b, u32 *r) { r[0] = a[0] ^ b[0]; r[1] = a[1] ^ b[1]; }
     __device__ static void tsub(const u32 *a, const u32 *b, u32 *r) { tadd(a, b, r); }
-    __device__ static void acc_zero(u32 *c) { c[0] = c[1] = 0u; }
+    __device__ static void acc_init(u32 *c, int) { c[0] = c[1] = 0u; }
     __device__ static void accumulate(u32 *c, const u32 (*t)[P]) {
         c[0] = xor3(c[0], t[0][0], t[1][1]);
         c[1] = xor3(c[1], t[0][1], t[1][0]) ^ t[1][1];

@@ -219,10 +219,37 @@ GFQ_HD void f3_from_bin(const u32 *b, u32 *x0, u32 *x1) { *x0 = b[0] ^ b[1]; *x1
 
 // F_5 addends in the modulo-15 working form: alpha * t for a 3-bit representative t and
 // alpha in {1, 2, 4}.  Doubling modulo 15 is a rotation of the four planes.
-GFQ_HD void f5w_scaled(const u32 *t, int alpha, u32 *x) {
-    if (alpha == 1) { x[0] = t[0]; x[1] = t[1]; x[2] = t[2]; x[3] = 0u; }
-    else if (alpha == 2) { x[0] = 0u; x[1] = t[0]; x[2] = t[1]; x[3] = t[2]; }
-    else { x[0] = t[2]; x[1] = 0u; x[2] = t[0]; x[3] = t[1]; }   // 4 t = t2 + 4 t0 + 8 t1 (mod 15)
+// One F_5 slab into a carry-save accumulator modulo 15 (S + K, both in 4 planes, bit j of
+// either weighing 2^j; 5 divides 15, so the value is reduced mod 5 at the end).  The slab's
+// three table rows are t = T[phi_0] (scale 1), v = T[phi_1] (scale 2) and w = T[phi_2]
+// (scale 4 = -1 mod 5, added as the complement ~w = 7 - w, so every slab also adds 7; the
+// caller starts the accumulator at -7 x slabs).  Nine addend bits sit in the columns as
+//   col 0: t0, ~w0    col 1: t1, v0, ~w1    col 2: t2, v1, ~w2    col 3: v2
+// and nine full adders plus one half adder bring every column back to two bits (carries out
+// of column 3 re-enter column 0 because 16 = 1 mod 15): 20 instructions, where adding the
+// three scaled rows one at a time costs 24.
+GFQ_HD void f5_csa_slab(u32 *S, u32 *K, const u32 *t, const u32 *v, const u32 *w) {
+    const u32 s3a = xor3(S[3], K[3], v[2]), c3a = maj3(S[3], K[3], v[2]);     // -> col 0
+    const u32 s0a = xor3(S[0], K[0], t[0]), c0a = maj3(S[0], K[0], t[0]);     // -> col 1
+    const u32 s0b = xor3n(s0a, c3a, w[0]), c0b = maj3n(s0a, c3a, w[0]);
+    const u32 s1a = xor3(S[1], K[1], t[1]), c1a = maj3(S[1], K[1], t[1]);     // -> col 2
+    const u32 s1b = xor3n(v[0], c0a, w[1]), c1b = maj3n(v[0], c0a, w[1]);
+    const u32 s1c = s1a ^ s1b, c1c = s1a & s1b;
+    const u32 s2a = xor3(S[2], K[2], t[2]), c2a = maj3(S[2], K[2], t[2]);     // -> col 3
+    const u32 s2b = xor3n(v[1], c1a, w[2]), c2b = maj3n(v[1], c1a, w[2]);
+    const u32 s2c = xor3(s2a, s2b, c1b), c2c = maj3(s2a, s2b, c1b);
+    const u32 s3b = xor3(s3a, c2a, c2b), c3b = maj3(s3a, c2a, c2b);          // -> col 0
+    S[0] = s0b; S[1] = s1c; S[2] = s2c; S[3] = s3b;
+    K[0] = c3b; K[1] = c0b; K[2] = c1c; K[3] = c2c;
+}
+
+// Starting value of that accumulator for `slabs` slabs: -7 x slabs mod 15 in S, zero K.
+GFQ_HD void f5_csa_init(u32 *S, u32 *K, int slabs) {
+    const int c = (8 * (slabs > 0 ? slabs : 0)) % 15;
+    for (int j = 0; j < 4; j++) {
+        S[j] = ((c >> j) & 1) ? 0xffffffffu : 0u;
+        K[j] = 0u;
+    }
 }
 
 }  // namespace gfq

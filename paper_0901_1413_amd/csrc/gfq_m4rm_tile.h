@@ -203,7 +203,7 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
 #pragma unroll
     for (int r = 0; r < R; r++)
 #pragma unroll
-        for (int i = 0; i < 4; i++) F::acc_zero(acc[r][i]);
+        for (int i = 0; i < 4; i++) F::acc_init(acc[r][i], s_end - s_begin);
 
     const int rs = tid / LPR, cg = tid % LPR;
     const u32 laneoff = (u32)(tid % (REP * LPR)) * 16u;

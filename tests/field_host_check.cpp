@@ -52,10 +52,24 @@ int main() {
         unsigned vns = bit(n2s[0]) | bit(n2s[1]) << 1, vnk = bit(n2k[0]) | bit(n2k[1]) << 1;
         printf("csa %u %u %u  %u %u  %u %u  %u %u  %u %u\n", S, K, X, v4s, v4k, v3s, v3k, v2s, v2k, vns, vnk);
     }
-    for (unsigned t = 0; t < 8; t++) for (int al = 1; al <= 4; al *= 2) {
-        u32 tt[3] = {t & 1, (t >> 1) & 1, (t >> 2) & 1}, x[4];
-        f5w_scaled(tt, al, x);
-        printf("f5w %u %d %u\n", t, al, bit(x[0]) | bit(x[1]) << 1 | bit(x[2]) << 2 | bit(x[3]) << 3);
+    // F_5 slab step of the mod-15 carry-save accumulator: every (S, K, t, v, w)
+    for (unsigned S = 0; S < 16; S++) for (unsigned K = 0; K < 16; K++)
+        for (unsigned t = 0; t < 8; t++) for (unsigned v = 0; v < 8; v++) for (unsigned w = 0; w < 8; w++) {
+            u32 s4[4], k4[4], t3[3], v3[3], w3[3];
+            for (int i = 0; i < 4; i++) { s4[i] = (S >> i) & 1; k4[i] = (K >> i) & 1; }
+            for (int i = 0; i < 3; i++) { t3[i] = (t >> i) & 1; v3[i] = (v >> i) & 1; w3[i] = (w >> i) & 1; }
+            f5_csa_slab(s4, k4, t3, v3, w3);
+            unsigned so = 0, ko = 0;
+            for (int i = 0; i < 4; i++) { so |= bit(s4[i]) << i; ko |= bit(k4[i]) << i; }
+            printf("f5slab %u %u %u %u %u %u %u\n", S, K, t, v, w, so, ko);
+        }
+    for (int slabs = 0; slabs < 40; slabs++) {
+        u32 s4[4], k4[4];
+        f5_csa_init(s4, k4, slabs);
+        unsigned so = 0, ko = 0;
+        for (int i = 0; i < 4; i++) { so |= (s4[i] & 1u) << i; ko |= (k4[i] & 1u) << i; }
+        const bool full = (s4[0] == 0u || s4[0] == 0xffffffffu) && (s4[3] == 0u || s4[3] == 0xffffffffu);
+        printf("f5init %d %u %u %d\n", slabs, so, ko, full ? 1 : 0);
     }
     return 0;
 }

@@ -92,7 +92,18 @@ def test_carry_save_steps(table):
         assert (n2 + m2) % 3 == ((S & 3) + (K & 3) - (X & 3)) % 3
 
 
-def test_f5_scaled_addends(table):
-    for r in (r for r in table if r[0] == "f5w"):
-        t, al, x = int(r[1]), int(r[2]), int(r[3])
-        assert x % 15 == (al * t) % 15
+def test_f5_slab_step(table):
+    """One slab of the F_5 accumulator: S' + K' = S + K + t + 2 v + (7 - w) (mod 15) for every
+    input, i.e. t + 2v + 4w (mod 5) up to the constant 7 per slab; the starting value cancels
+    that constant: init(n) + 7 n = 0 (mod 15)."""
+    rows = [r for r in table if r[0] == "f5slab"]
+    assert len(rows) == 16 * 16 * 8 * 8 * 8
+    for r in rows:
+        S, K, t, v, w, so, ko = map(int, r[1:])
+        assert (so + ko) % 15 == (S + K + t + 2 * v + (7 - w)) % 15, r
+        assert ((so + ko) - (S + K) - 7) % 5 == (t + 2 * v + 4 * w) % 5
+    inits = [r for r in table if r[0] == "f5init"]
+    assert len(inits) == 40
+    for r in inits:
+        n, so, ko, full = map(int, r[1:])
+        assert (so + ko + 7 * n) % 15 == 0 and ko == 0 and full == 1, r
