@@ -147,54 +147,75 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
     };
 
     // ---- table build: thread = (column word dw, chunk c); chunk c owns the entries whose
-    // high k-G bits equal c and walks their low G bits in Gray-code order ----
+    // high k-G bits equal c and walks their low G bits in Gray-code order.  The rows a
+    // thread needs are read from LDS in two batches (the chunk's prefix rows, then the
+    // walk's rows); the prefix is a branch-free masked sum and the walk is unrolled, so the
+    // chain of additions never waits on an LDS read. ----
+    constexpr int GMAX = KMAX > LOG_NCH ? KMAX - LOG_NCH : 0;   // longest walk: 2^GMAX entries
     const int dw = tid % TWD, ch = tid / TWD;
     const int G = k > LOG_NCH ? k - LOG_NCH : 0;
     const int nchunks = 1 << (k - G);
+    u32 rep_off[REP];                            // this chunk's copy rotation
+#pragma unroll
+    for (int i = 0; i < REP; i++) rep_off[i] = (u32)(((i + ch) % REP) * TWD * 4);
     auto build = [&](int s) {
         if (ch >= nchunks) return;
-        const u32 *bs = Bst + (s & 1) * KMAX * P * TWD;
-        unsigned char *T = smem + ((s & 1) ? TB1 : 0u);
-        auto brow = [&](int t, u32 *r) {
-            u32 x[P];
+        const u32 *bs = Bst + (s & 1) * KMAX * P * TWD + dw;
+        unsigned char *T = smem + ((s & 1) ? TB1 : 0u) + dw * 4;
+        auto store = [&](unsigned char *dst, const u32 *v) {
 #pragma unroll
-            for (int p = 0; p < P; p++) x[p] = bs[(t * P + p) * TWD + dw];
-            F::to_table(x, r);
+            for (int i = 0; i < REP; i++)
+#pragma unroll
+                for (int p = 0; p < P; p++) *reinterpret_cast<u32 *>(dst + p * SRB + rep_off[i]) = v[p];
         };
-        auto store = [&](int e, const u32 *v) {
-            unsigned char *dst = T + (u32)e * (P * SRB) + dw * 4;
+        // Every staged row index below is below KMAX, inside the staging buffer, so the
+        // reads are unconditional (rows at or beyond k hold stale data and are masked or
+        // never used) and issue back to back.
+        // prefix: the sum of the rows G + t whose bit t is set in the chunk index
+        u32 pr[LOG_NCH > 0 ? LOG_NCH : 1][P];
 #pragma unroll
-            for (int i = 0; i < REP; i++) {
-                const int rho = (i + ch) % REP;
+        for (int t = 0; t < LOG_NCH; t++)
 #pragma unroll
-                for (int p = 0; p < P; p++) *reinterpret_cast<u32 *>(dst + p * SRB + rho * TWD * 4) = v[p];
-            }
-        };
+            for (int p = 0; p < P; p++) pr[t][p] = bs[((G + t) * P + p) * TWD];
         u32 v[P];
 #pragma unroll
         for (int p = 0; p < P; p++) v[p] = 0u;
-        for (int t = 0; t < k - G; t++) {
-            if ((ch >> t) & 1) {
-                u32 r[P], z[P];
-                brow(G + t, r);
-                F::tadd(v, r, z);
 #pragma unroll
-                for (int p = 0; p < P; p++) v[p] = z[p];
-            }
-        }
-        const int eb = ch << G;
-        store(eb, v);
-        for (int j = 1; j < (1 << G); j++) {
-            const int b = __builtin_ctz(j);
-            const int g = j ^ (j >> 1);
-            u32 r[P], z[P];
-            brow(b, r);
-            // a bit switched on adds its row, a bit switched off subtracts it
-            if ((g >> b) & 1) F::tadd(v, r, z);
-            else F::tsub(v, r, z);
+        for (int t = 0; t < LOG_NCH; t++) {
+            const u32 m = (t < k - G) ? 0u - (u32)((ch >> t) & 1) : 0u;
+            u32 r[P], x[P], z[P];
+            F::to_table(pr[t], x);
+#pragma unroll
+            for (int p = 0; p < P; p++) r[p] = x[p] & m;             // the zero row adds nothing
+            F::tadd(v, r, z);
 #pragma unroll
             for (int p = 0; p < P; p++) v[p] = z[p];
-            store(eb | g, v);
+        }
+        unsigned char *eb = T + (u32)(ch << G) * (P * SRB);
+        store(eb, v);
+        if constexpr (GMAX > 0) {
+            u32 wr[GMAX > 0 ? GMAX : 1][P];
+#pragma unroll
+            for (int b = 0; b < GMAX; b++) {
+                u32 x[P];
+#pragma unroll
+                for (int p = 0; p < P; p++) x[p] = bs[(b * P + p) * TWD];
+                F::to_table(x, wr[b]);
+            }
+            // entry g of the walk follows entry g' = Gray(j - 1): bit b = ctz(j) switches,
+            // adding row b when it switches on and subtracting it when it switches off
+#pragma unroll
+            for (int j = 1; j < (1 << GMAX); j++) {
+                if (j >= (1 << G)) break;
+                const int b = __builtin_ctz(j);
+                const int g = j ^ (j >> 1);
+                u32 z[P];
+                if ((g >> b) & 1) F::tadd(v, wr[b], z);
+                else F::tsub(v, wr[b], z);
+#pragma unroll
+                for (int p = 0; p < P; p++) v[p] = z[p];
+                store(eb + g * (P * SRB), v);
+            }
         }
     };
 
