@@ -79,18 +79,25 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
     const int bt = tid / (P * CG), bp = (tid / CG) % P, bc = tid % CG;
     const bool b_active = tid < k * P * CG;
     const int bcol = colw0 + bc * 4;
+    // Global loads inside the slab loop read addresses clamped into the operand (a slab
+    // exists, so l >= 1, and the tile exists, so m, n >= 1) and the values of out-of-range
+    // positions are masked where they are used.  No load has a path that writes its
+    // destination register otherwise: such a write (a zero for an out-of-range position)
+    // would have to wait for every load in flight, including the prefetches just issued.
     auto load_b = [&](int s) -> uint4 {
-        const int brow = s * k + bt;
-        if (b_active && brow < a.l && bcol < a.Wn)
-            return *reinterpret_cast<const uint4 *>(a.B + ((size_t)brow * P + bp) * a.Wn + bcol);
-        return make_uint4(0u, 0u, 0u, 0u);
+        const int brow = min(s * k + bt, a.l - 1);
+        const int col = min(bcol, a.Wn - 4);
+        return *reinterpret_cast<const uint4 *>(a.B + ((size_t)brow * P + bp) * a.Wn + col);
     };
     auto store_b = [&](int s, const uint4 &v) {
-        if (b_active) *reinterpret_cast<uint4 *>(Bst + (((s & 1) * KMAX + bt) * P + bp) * TWD + bc * 4) = v;
+        const u32 m = (s * k + bt < a.l && bcol < a.Wn) ? 0xffffffffu : 0u;
+        if (b_active)
+            *reinterpret_cast<uint4 *>(Bst + (((s & 1) * KMAX + bt) * P + bp) * TWD + bc * 4) =
+                make_uint4(v.x & m, v.y & m, v.z & m, v.w & m);
     };
 
     // ---- staging of A: a window of words (w, w+1, w+2) per staged row and plane ----
-    u32 aw[ARPT][P][3];
+    u32 aw[ARPT][P][3], apre[ARPT][P];
     int aw_w = (s_begin * k) >> 5;
     auto a_word = [&](int j, int p, int w) -> u32 {
         const int lr = tid + j * NT;
@@ -105,7 +112,12 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
             aw[j][p][0] = a_word(j, p, aw_w);
             aw[j][p][1] = a_word(j, p, aw_w + 1);
             aw[j][p][2] = a_word(j, p, aw_w + 2);
+            apre[j][p] = a_word(j, p, aw_w + 3);
         }
+    auto apre_mask = [&](int j, int w) -> u32 {
+        const int lr = tid + j * NT;
+        return (lr < TM && row0 + lr < a.m && w < a.Wl) ? 0xffffffffu : 0u;
+    };
     // offsets (u16, entry * P * SRB) of the D table rows for slab s, for every tile row
     auto stage_idx = [&](int s) {
         const int sh = (s * k) & 31;
@@ -129,21 +141,34 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
             }
         }
     };
-    // move the window to the words of slab s (called in slab order; k < 32 so it moves by
-    // at most one word); the word two ahead is loaded now and used a slab later
-    auto advance = [&](int s) {
-        const int w = (s * k) >> 5;
-        if (w != aw_w) {
+    // the word the next move brings in: a load from a clamped address, masked when it
+    // enters the window
+    auto prefetch_a = [&]() {
+        const int w = min(aw_w + 3, a.Wl - 1);
 #pragma unroll
-            for (int j = 0; j < ARPT; j++)
+        for (int j = 0; j < ARPT; j++) {
+            const int row = min(row0 + min(tid + j * NT, TM - 1), a.m - 1);
 #pragma unroll
-                for (int p = 0; p < P; p++) {
-                    aw[j][p][0] = aw[j][p][1];
-                    aw[j][p][1] = aw[j][p][2];
-                    aw[j][p][2] = a_word(j, p, w + 2);
-                }
-            aw_w = w;
+            for (int p = 0; p < P; p++) apre[j][p] = a.A[((size_t)row * P + p) * a.Wl + w];
         }
+    };
+    // move the window to the words of slab s (called in slab order; k < 32 so it moves by
+    // at most one word); true if it moved.  The word entering the window was prefetched
+    // after the previous move (at least three slabs earlier); the caller prefetches the
+    // next one after its other loads.
+    auto advance = [&](int s) -> bool {
+        const int w = (s * k) >> 5;
+        if (w == aw_w) return false;
+#pragma unroll
+        for (int j = 0; j < ARPT; j++)
+#pragma unroll
+            for (int p = 0; p < P; p++) {
+                aw[j][p][0] = aw[j][p][1];
+                aw[j][p][1] = aw[j][p][2];
+                aw[j][p][2] = apre[j][p] & apre_mask(j, w + 2);
+            }
+        aw_w = w;
+        return true;
     };
 
     // ---- table build: thread = (column word dw, chunk c); chunk c owns the entries whose
@@ -286,25 +311,31 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
     if (s_begin < s_end) {
         store_b(s_begin, load_b(s_begin));
         stage_idx(s_begin);
-        advance(s_begin + 1);
+        if (advance(s_begin + 1)) prefetch_a();
         if (s_begin + 1 < s_end) {
             store_b(s_begin + 1, load_b(s_begin + 1));
             stage_idx(s_begin + 1);
-            advance(s_begin + 2);
+            if (advance(s_begin + 2)) prefetch_a();
         }
-        if (s_begin + 2 < s_end) bpre = load_b(s_begin + 2);
+        if (s_begin + 2 < s_end && b_active) bpre = load_b(s_begin + 2);
         __syncthreads();
         build(s_begin);
         __syncthreads();
     }
 
     for (int s = s_begin; s < s_end; s++) {
+        // Every register filled by an earlier load is consumed before this iteration's
+        // loads are issued (B rows of slab s+3, then the next A word); those are used at
+        // least an iteration later, so no wait in the loop covers a load of the same
+        // iteration.
+        bool moved = false;
         if (s + 2 < s_end) {
             store_b(s + 2, bpre);
             stage_idx(s + 2);
-            advance(s + 3);
+            moved = advance(s + 3);
         }
-        if (s + 3 < s_end) bpre = load_b(s + 3);
+        if (s + 3 < s_end && b_active) bpre = load_b(s + 3);
+        if (moved) prefetch_a();
         // The two waves sharing a SIMD (w and w + NT/256) run the independent build and
         // gather phases in opposite orders, so one wave's VALU-heavy gathers fill the other
         // wave's waits on the table build's chain of LDS round trips.
