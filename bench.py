@@ -38,10 +38,11 @@ PEAK_HBM = 8.0e12
 SECTIONS = ("c1", "c2_k", "c3", "c4", "c5")
 
 # Per-unit operation counts of the method on gfx950 (three-input bitwise instructions).
-# A unit is (row of C, slab of k rows of B, 32-column word).  Accumulate: carry-save
-# additions of the D alpha-scaled table rows (2 instructions per residue bit and addend).
+# A unit is (row of C, slab of k rows of B, 32-column word).  Accumulate: the slab's D
+# alpha-scaled table rows into a carry-save accumulator, one full adder (2 instructions)
+# per addend bit (F_3 4 bits, F_7 9; F_5 9 bits plus one half adder; GF(4) 3 XORs).
 # Table build: one field addition per table entry and word.  Finish: per output word.
-C_ACC = {3: 8, 4: 3, 5: 24, 7: 18}
+C_ACC = {3: 8, 4: 3, 5: 20, 7: 18}
 C_ADD = {3: 6, 4: 2, 5: 13, 7: 11}
 C_FIN = {3: 8, 4: 0, 5: 30, 7: 15}
 # The paper's two-input operation counts (Sections 4.1 and 4.2) for the same units.
@@ -54,8 +55,8 @@ C_ADD_PAPER = {3: 6, 4: 2, 5: 20, 7: 17}
 # valid only while the kernel sources hash to `src` (otherwise the roofline reports null).
 KERNEL_SOURCES = ("gfq_m4rm.hip", "gfq_m4rm_tile.h", "gfq_device.h", "gfq_field.h", "gfq_internal.h")
 MEASURED_TRAFFIC = {
-    3: {"src": "4033fe525fd500ec", "read_mib": 652.1, "write_mib": 32.0},
-    5: {"src": "4033fe525fd500ec", "read_mib": 295.9, "write_mib": 24.0},
+    3: {"src": "bb109ef77ad054eb", "read_mib": 597.4, "write_mib": 64.0},
+    5: {"src": "bb109ef77ad054eb", "read_mib": 243.4, "write_mib": 24.0},
 }
 
 
