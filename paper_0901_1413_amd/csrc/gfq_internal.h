@@ -57,7 +57,10 @@ inline size_t mm_lds_bytes(int q, int k, int srb, int TM, u32 *tb1_out) {
     u32 tb1 = 16;
     while (tb1 < tbytes) tb1 <<= 1;
     if (tb1_out) *tb1_out = tb1;
-    return (size_t)tb1 + tbytes + 2 * KMAX * P * twd_of(srb) * 4 + 3 * (size_t)TM * ((D + 1) / 2) * 4;
+    // two tables, B staging [3][KMAX][P][TWD], chunk prefixes [2][NT/TWD][P][TWD] (three
+    // planes only), table offsets [3][TM][(D+1)/2]
+    return (size_t)tb1 + tbytes + 3 * KMAX * P * twd_of(srb) * 4 + (P == 3 ? 2 * (size_t)NT_MM * P * 4 : 0) +
+           3 * (size_t)TM * ((D + 1) / 2) * 4;
 }
 
 // srb = 0 when k is out of range; otherwise the largest R (rows per lane) not above the

@@ -65,8 +65,9 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
     const int k = a.k;
     const u32 tbytes = (u32)(1u << k) * P * SRB;
     const u32 TB1 = a.tb1;                       // power of two >= tbytes, <= 65536
-    u32 *Bst = reinterpret_cast<u32 *>(smem + TB1 + tbytes);   // [2][KMAX][P][TWD]
-    u32 *Ib = Bst + 2 * KMAX * P * TWD;                         // [3][TM][IBW]
+    u32 *Bst = reinterpret_cast<u32 *>(smem + TB1 + tbytes);   // [3][KMAX][P][TWD]
+    u32 *PB = Bst + 3 * KMAX * P * TWD;                         // [2][NCH][P][TWD] (P = 3 only)
+    u32 *Ib = PB + (P == 3 ? 2 * NCH * P * TWD : 0);            // [3][TM][IBW]
 
     const int tid = threadIdx.x;
     const int colw0 = bx * TWD;
@@ -92,7 +93,7 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
     auto store_b = [&](int s, const uint4 &v) {
         const u32 m = (s * k + bt < a.l && bcol < a.Wn) ? 0xffffffffu : 0u;
         if (b_active)
-            *reinterpret_cast<uint4 *>(Bst + (((s & 1) * KMAX + bt) * P + bp) * TWD + bc * 4) =
+            *reinterpret_cast<uint4 *>(Bst + (((s % 3) * KMAX + bt) * P + bp) * TWD + bc * 4) =
                 make_uint4(v.x & m, v.y & m, v.z & m, v.w & m);
     };
 
@@ -171,21 +172,88 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
         return true;
     };
 
-    // ---- table build: thread = (column word dw, chunk c); chunk c owns the entries whose
-    // high k-G bits equal c and walks their low G bits in Gray-code order.  The rows a
-    // thread needs are read from LDS in two batches (the chunk's prefix rows, then the
-    // walk's rows); the prefix is a branch-free masked sum and the walk is unrolled, so the
-    // chain of additions never waits on an LDS read. ----
+    // ---- table build.  Entry e of a slab's table is split as e = (c << G) | g: chunk c
+    // (C = k - G high bits, at most NCH chunks) and walk index g.  Thread (word dw, chunk c)
+    // starts from the chunk prefix T[c << G], the sum of rows G + t over the bits t of c,
+    // and walks the G low bits in Gray-code order, adding row b when bit b switches on and
+    // subtracting it when it switches off.  For three-plane fields the prefixes come from
+    // a stage one slab earlier (prefix): NCH/4 threads per word each take four consecutive
+    // chunks (a masked sum over the bits above the lowest two, then a Gray walk over those
+    // two) and leave them in a small buffer.  For two planes, where a table addition costs
+    // only 6 (F_3) or 2 (GF(4)) instructions, each thread sums its own prefix (a masked sum).
+    // The rows a stage needs are read from LDS in one batch before its chain of additions. ----
+    constexpr bool SPLIT_PREFIX = P == 3;
     constexpr int GMAX = KMAX > LOG_NCH ? KMAX - LOG_NCH : 0;   // longest walk: 2^GMAX entries
+    constexpr int PFW = NCH / 4;                                // prefix threads per word
+    constexpr int PFB = LOG_NCH > 2 ? LOG_NCH - 2 : 0;         // masked bits per prefix thread
+    static_assert(NCH >= 4, "four chunks per prefix thread");
     const int dw = tid % TWD, ch = tid / TWD;
-    const int G = k > LOG_NCH ? k - LOG_NCH : 0;
-    const int nchunks = 1 << (k - G);
+    const int C = k > LOG_NCH ? LOG_NCH : k;     // chunk bits
+    const int G = k - C;                         // walk bits
+    const int nchunks = 1 << C;
     u32 rep_off[REP];                            // this chunk's copy rotation
 #pragma unroll
     for (int i = 0; i < REP; i++) rep_off[i] = (u32)(((i + ch) % REP) * TWD * 4);
+    auto step = [&](u32 *v, const u32 *r, bool on) {
+        u32 z[P];
+        if (on) F::tadd(v, r, z);
+        else F::tsub(v, r, z);
+#pragma unroll
+        for (int p = 0; p < P; p++) v[p] = z[p];
+    };
+    // Every staged row index read below is below KMAX, inside the staging buffer, so the
+    // reads are unconditional (rows at or beyond k hold stale data and are masked or never
+    // enter a stored value).
+    auto prefix = [&](int s) {
+        if (!SPLIT_PREFIX || ch >= PFW) return;  // thread (dw, g = ch) of the first NT/4
+        const u32 *bs = Bst + (s % 3) * KMAX * P * TWD + dw;
+        u32 *pb = PB + (s & 1) * NCH * P * TWD + dw;
+        u32 hr[PFB > 0 ? PFB : 1][P], lo0[P], lo1[P];
+#pragma unroll
+        for (int t = 0; t < PFB; t++) {
+            u32 x[P];
+#pragma unroll
+            for (int p = 0; p < P; p++) x[p] = bs[((G + 2 + t) * P + p) * TWD];
+            F::to_table(x, hr[t]);
+        }
+        {
+            u32 x[P], y[P];
+#pragma unroll
+            for (int p = 0; p < P; p++) {
+                x[p] = bs[(G * P + p) * TWD];
+                y[p] = bs[((G + 1) * P + p) * TWD];
+            }
+            F::to_table(x, lo0);
+            F::to_table(y, lo1);
+        }
+        u32 v[P];
+#pragma unroll
+        for (int p = 0; p < P; p++) v[p] = 0u;
+#pragma unroll
+        for (int t = 0; t < PFB; t++) {
+            const u32 m = (2 + t < C) ? 0u - (u32)((ch >> t) & 1) : 0u;
+            u32 r[P];
+#pragma unroll
+            for (int p = 0; p < P; p++) r[p] = hr[t][p] & m;         // the zero row adds nothing
+            step(v, r, true);
+        }
+        const int c0 = ch * 4;
+        auto put = [&](int c, const u32 *x) {
+            if (c < nchunks)
+#pragma unroll
+                for (int p = 0; p < P; p++) pb[(c * P + p) * TWD] = x[p];
+        };
+        put(c0, v);
+        step(v, lo0, true);
+        put(c0 + 1, v);
+        step(v, lo1, true);
+        put(c0 + 3, v);
+        step(v, lo0, false);
+        put(c0 + 2, v);
+    };
     auto build = [&](int s) {
         if (ch >= nchunks) return;
-        const u32 *bs = Bst + (s & 1) * KMAX * P * TWD + dw;
+        const u32 *bs = Bst + (s % 3) * KMAX * P * TWD + dw;
         unsigned char *T = smem + ((s & 1) ? TB1 : 0u) + dw * 4;
         auto store = [&](unsigned char *dst, const u32 *v) {
 #pragma unroll
@@ -193,28 +261,29 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
 #pragma unroll
                 for (int p = 0; p < P; p++) *reinterpret_cast<u32 *>(dst + p * SRB + rep_off[i]) = v[p];
         };
-        // Every staged row index below is below KMAX, inside the staging buffer, so the
-        // reads are unconditional (rows at or beyond k hold stale data and are masked or
-        // never used) and issue back to back.
-        // prefix: the sum of the rows G + t whose bit t is set in the chunk index
-        u32 pr[LOG_NCH > 0 ? LOG_NCH : 1][P];
-#pragma unroll
-        for (int t = 0; t < LOG_NCH; t++)
-#pragma unroll
-            for (int p = 0; p < P; p++) pr[t][p] = bs[((G + t) * P + p) * TWD];
         u32 v[P];
+        if constexpr (SPLIT_PREFIX) {
+            const u32 *pb = PB + (s & 1) * NCH * P * TWD + dw;
 #pragma unroll
-        for (int p = 0; p < P; p++) v[p] = 0u;
+            for (int p = 0; p < P; p++) v[p] = pb[(ch * P + p) * TWD];
+        } else {
+            // the chunk's prefix here: a masked sum of its rows G + t
+            u32 pr[LOG_NCH][P];
 #pragma unroll
-        for (int t = 0; t < LOG_NCH; t++) {
-            const u32 m = (t < k - G) ? 0u - (u32)((ch >> t) & 1) : 0u;
-            u32 r[P], x[P], z[P];
-            F::to_table(pr[t], x);
+            for (int t = 0; t < LOG_NCH; t++)
 #pragma unroll
-            for (int p = 0; p < P; p++) r[p] = x[p] & m;             // the zero row adds nothing
-            F::tadd(v, r, z);
+                for (int p = 0; p < P; p++) pr[t][p] = bs[((G + t) * P + p) * TWD];
 #pragma unroll
-            for (int p = 0; p < P; p++) v[p] = z[p];
+            for (int p = 0; p < P; p++) v[p] = 0u;
+#pragma unroll
+            for (int t = 0; t < LOG_NCH; t++) {
+                const u32 m = (t < C) ? 0u - (u32)((ch >> t) & 1) : 0u;
+                u32 r[P], x[P];
+                F::to_table(pr[t], x);
+#pragma unroll
+                for (int p = 0; p < P; p++) r[p] = x[p] & m;         // the zero row adds nothing
+                step(v, r, true);
+            }
         }
         unsigned char *eb = T + (u32)(ch << G) * (P * SRB);
         store(eb, v);
@@ -227,18 +296,12 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
                 for (int p = 0; p < P; p++) x[p] = bs[(b * P + p) * TWD];
                 F::to_table(x, wr[b]);
             }
-            // entry g of the walk follows entry g' = Gray(j - 1): bit b = ctz(j) switches,
-            // adding row b when it switches on and subtracting it when it switches off
 #pragma unroll
             for (int j = 1; j < (1 << GMAX); j++) {
                 if (j >= (1 << G)) break;
                 const int b = __builtin_ctz(j);
                 const int g = j ^ (j >> 1);
-                u32 z[P];
-                if ((g >> b) & 1) F::tadd(v, wr[b], z);
-                else F::tsub(v, wr[b], z);
-#pragma unroll
-                for (int p = 0; p < P; p++) v[p] = z[p];
+                step(v, wr[b], (g >> b) & 1);
                 store(eb + g * (P * SRB), v);
             }
         }
@@ -306,7 +369,8 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
 
     const bool build_first = (tid / 64) < (NT / 128);   // first half of the waves
 
-    // ---- prologue: stage slabs s0 and s0+1, build slab s0 ----
+    // ---- prologue: stage slabs s0 .. s0+2 (B rows) and s0, s0+1 (table offsets), the
+    // prefixes of s0 and s0+1, then the table of s0 ----
     uint4 bpre = make_uint4(0u, 0u, 0u, 0u);
     if (s_begin < s_end) {
         store_b(s_begin, load_b(s_begin));
@@ -317,31 +381,38 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
             stage_idx(s_begin + 1);
             if (advance(s_begin + 2)) prefetch_a();
         }
-        if (s_begin + 2 < s_end && b_active) bpre = load_b(s_begin + 2);
+        if (s_begin + 2 < s_end) store_b(s_begin + 2, load_b(s_begin + 2));
+        if (s_begin + 3 < s_end && b_active) bpre = load_b(s_begin + 3);
+        __syncthreads();
+        prefix(s_begin);
+        if (s_begin + 1 < s_end) prefix(s_begin + 1);
         __syncthreads();
         build(s_begin);
         __syncthreads();
     }
 
     for (int s = s_begin; s < s_end; s++) {
-        // Every register filled by an earlier load is consumed before this iteration's
-        // loads are issued (B rows of slab s+3, then the next A word); those are used at
-        // least an iteration later, so no wait in the loop covers a load of the same
-        // iteration.
+        // Iteration s stages the B rows of slab s+3 and the table offsets of slab s+2,
+        // computes the chunk prefixes of slab s+2, builds the table of slab s+1 and
+        // gathers slab s.  Every register filled by an earlier load is consumed before
+        // this iteration's loads are issued (B rows of slab s+4, then the next A word);
+        // those are used at least an iteration later, so no wait in the loop covers a load
+        // of the same iteration.
         bool moved = false;
+        if (s + 3 < s_end) store_b(s + 3, bpre);
         if (s + 2 < s_end) {
-            store_b(s + 2, bpre);
             stage_idx(s + 2);
             moved = advance(s + 3);
         }
-        if (s + 3 < s_end && b_active) bpre = load_b(s + 3);
+        if (s + 4 < s_end && b_active) bpre = load_b(s + 4);
         if (moved) prefetch_a();
         // The two waves sharing a SIMD (w and w + NT/256) run the independent build and
         // gather phases in opposite orders, so one wave's VALU-heavy gathers fill the other
-        // wave's waits on the table build's chain of LDS round trips.
+        // wave's waits on the table build's LDS round trips.
 #pragma unroll 1
         for (int phase = 0; phase < 2; phase++) {
             if ((phase == 0) == build_first) {
+                if (s + 2 < s_end) prefix(s + 2);
                 if (s + 1 < s_end) build(s + 1);
             } else {
                 gather(s);
