@@ -12,6 +12,8 @@ timed on a bounded row sample of the same products (its rows are also compared b
 with the GPU product), and sections for the other workloads:
   c1       F_3 512^3: per-product latency p50/p99 and the oracle's time for the product
   c2_k     the 8192^3 products with the slab width k swept 4..10 (each bit-exact)
+  mfma     comparison only: the same 8192^3 products as exact int8 matrix-core GEMMs
+           (torch._int_mm, int32 accumulation) reduced mod p, checked against this path
   c3       F_7 and GF(4), A 16384 x 2048 times B 2048 x 16384, dense and 10% density
   c4       4096 products of mixed fields and log-uniform shapes: one batched launch
            (captured in a HIP graph) against one plain launch per product
@@ -35,7 +37,7 @@ M = L = N = 8192
 FIELDS = (3, 5)
 PEAK_VALU_OPS = 256 * 64 * 2.4e9          # 32-bit VALU lane-operations per second
 PEAK_HBM = 8.0e12
-SECTIONS = ("c1", "c2_k", "c3", "c4", "c5")
+SECTIONS = ("c1", "c2_k", "mfma", "c3", "c4", "c5")
 
 # Per-unit operation counts of the method on gfx950 (three-input bitwise instructions).
 # A unit is (row of C, slab of k rows of B, 32-column word).  Accumulate: the slab's D
@@ -327,6 +329,52 @@ def section_c2_k(ctx, data, reps=3):
 
 
 # ------------------------------------------------------------------------------------
+# mfma: comparison only -- the headline products as int8 matrix-core GEMMs
+# ------------------------------------------------------------------------------------
+
+def int8_product(torch, q, A8, B8):
+    """C = A B over F_q from int8 GEMMs with int32 accumulation (exact while l (q-1)^2 <
+    2^31): one GEMM and a reduction mod p for F_p; for GF(4) = F_2[x]/(x^2+x+1) the
+    coefficient planes by Karatsuba, three GEMMs reduced mod 2."""
+    if q != 4:
+        return torch.remainder(torch._int_mm(A8, B8), q).to(torch.uint8)
+    a0, a1 = A8 & 1, A8 >> 1
+    b0, b1 = B8 & 1, B8 >> 1
+    p0, p1 = torch._int_mm(a0, b0), torch._int_mm(a1, b1)
+    p2 = torch._int_mm(a0 + a1, b0 + b1)
+    c0 = (p0 + p1) & 1                     # a0 b0 + a1 b1
+    c1 = (p2 - p0) & 1                     # a0 b1 + a1 b0 + a1 b1
+    return (c0 + 2 * c1).to(torch.uint8)
+
+
+def section_mfma(ctx, data, reps=5):
+    torch = ctx.torch
+    out = {"note": "comparison only; not the method of the paper and not part of the library"}
+    for q in FIELDS:
+        d = data[q]
+        A8, B8 = d["Ad"].view(torch.int8), d["Bd"].view(torch.int8)
+        C = int8_product(torch, q, A8, B8)
+        torch.cuda.synchronize()
+        same = bool(torch.equal(C, d["Cd"]))
+        ev = ctx.events(4)
+        ev[0].record()
+        for _ in range(reps):
+            torch._int_mm(A8, B8)
+        ev[1].record()
+        for _ in range(reps):
+            int8_product(torch, q, A8, B8)
+        ev[2].record()
+        torch.cuda.synchronize()
+        gemm = ev[0].elapsed_time(ev[1]) / reps
+        full = ev[1].elapsed_time(ev[2]) / reps
+        out[f"F_{q}"] = {"int8_gemm_ms": round(gemm, 4), "with_mod_p_ms": round(full, 4),
+                         "field_ops_per_s": 2.0 * M * L * N / (full * 1e-3),
+                         "int8_gemm_ops_per_s": 2.0 * M * L * N / (gemm * 1e-3),
+                         "equals_bitsliced_product": same}
+    return out
+
+
+# ------------------------------------------------------------------------------------
 # c3: F_7 and GF(4), 16384 x 2048 times 2048 x 16384, dense and 10% density
 # ------------------------------------------------------------------------------------
 
@@ -371,12 +419,26 @@ def section_c3(ctx, reps=3, sample_rows=32):
             got = Cd[torch.from_numpy(rows).to(ctx.dev)].cpu().numpy()
             ok = bool(np.array_equal(got, ctx.oracle.matmul(q, A[rows], B)))
             ops = algorithmic_ops(q, m, l, n, cfg["k"], C_ACC, C_ADD)
+            # comparison only: the same product as int8 matrix-core GEMMs
+            A8, B8 = Ad.view(torch.int8), Bd.view(torch.int8)
+            C8 = int8_product(torch, q, A8, B8)
+            torch.cuda.synchronize()
+            same8 = bool(torch.equal(C8, Cd))
+            del C8
+            ev = ctx.events(2)
+            ev[0].record()
+            for _ in range(reps):
+                int8_product(torch, q, A8, B8)
+            ev[1].record()
+            torch.cuda.synchronize()
+            mfma_ms = ev[0].elapsed_time(ev[1]) / reps
             name = ("GF4" if q == 4 else f"F_{q}") + ("" if density == 1.0 else "_density0.1")
             res[name] = {"path_ms": round(path_ms, 4), "product_ms": round(pm, 4), "partial_sum_ms": round(rm, 4),
                          "field_ops_per_s_path": 2.0 * m * l * n / (path_ms * 1e-3),
                          "field_ops_per_s_product": 2.0 * m * l * n / ((pm + rm) * 1e-3),
                          "alu_frac": round(ops / (pm * 1e-3) / PEAK_VALU_OPS, 4), "config": cfg,
-                         "sampled_rows_bit_exact": ok, "sampled_rows": sample_rows}
+                         "sampled_rows_bit_exact": ok, "sampled_rows": sample_rows,
+                         "int8_mfma_comparison_ms": round(mfma_ms, 4), "int8_mfma_equals": same8}
             del Ad, Bd, Ap, Bp, Cp, Cd
     return {"workload": "A 16384x2048, B 2048x16384; uniform and 10% density", **res}
 
@@ -615,6 +677,9 @@ def main():
     if "c2_k" in sections:
         log("c2_k")
         res["c2_k"] = section_c2_k(ctx, data)
+    if "mfma" in sections:
+        log("mfma")
+        res["mfma"] = section_mfma(ctx, data)
     if not args.no_cpu:
         for q in FIELDS:
             data[q]["C_host"] = data[q]["Cd"].cpu().numpy()
