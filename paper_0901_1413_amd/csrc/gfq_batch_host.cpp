@@ -43,7 +43,7 @@ void gfq::plan_batch(int count, const gfq_problem *problems, const gfq_config *c
         int k = std::min(c.k, kcap);
         if (p.l > 0 && p.l < k) k = (int)p.l;
         if (k < 1) k = 1;
-        const int R = (c.rows <= 256 || p.q == 5) ? 2 : max_rows_per_lane(p.q);
+        const int R = (c.rows <= 256 || p.q == 5) ? 2 : max_rows_per_lane_batch(p.q);
         const int TM = NT_MM / 4 * R;
         MMArgs &a = bp.a;
         a.A = (const u32 *)p.A;
@@ -101,7 +101,7 @@ size_t gfq::batch_tiles_bound(int64_t m, int64_t n) {
 
 hipError_t gfq::set_batched_lds_limits() {
     for (int q : {3, 4, 5, 7})
-        for (int R : {2, max_rows_per_lane(q)}) {
+        for (int R : {2, max_rows_per_lane_batch(q)}) {
             if (q == 5 && R != 2) continue;       // F_5 batches use two rows per lane only
             const size_t lds = mm_lds_bytes(q, planes_of(q) == 2 ? 7 : 6, 256, NT_MM / 4 * R, nullptr);
             hipError_t e = hipFuncSetAttribute(batched_kernel(q, R), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

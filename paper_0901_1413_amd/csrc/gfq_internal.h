@@ -29,7 +29,10 @@ struct MMArgs {
 
 inline int planes_of(int q) { return (q == 3 || q == 4) ? 2 : 3; }
 inline int words_of(int64_t cols) { return (int)(((cols + 127) / 128) * 4); }
-inline int max_rows_per_lane(int q) { return q == 5 || q == 7 ? 4 : 8; }
+// Rows of C per lane: bounded by the accumulator registers (8 planes per word for F_5, 6
+// for F_7, 4 for F_3, 2 for GF(4)).  The work-list kernels of batches use at most 8.
+inline int max_rows_per_lane(int q) { return q == 5 || q == 7 ? 4 : (q == 4 ? 16 : 8); }
+inline int max_rows_per_lane_batch(int q) { return q == 5 ? 2 : (q == 7 ? 4 : 8); }
 
 // Table super-row bytes for field q and slab width k: the widest of 256, 128, 64, 32, 16
 // such that both table buffers fit TABLES_LDS (0 if none does).
@@ -74,8 +77,9 @@ inline MMPlan mm_plan(int q, int k, int rowsTile) {
     p.rep = p.srb / (4 * p.twd);
     const int lpr = p.twd / 4;
     int r = rowsTile * lpr / NT_MM;
-    r = r <= 2 ? 2 : (r <= 4 ? 4 : 8);
+    r = r <= 2 ? 2 : (r <= 4 ? 4 : (r <= 8 ? 8 : 16));
     if (r > max_rows_per_lane(q)) r = max_rows_per_lane(q);
+    if (r > 8 && p.twd < 16) r = 8;              // narrow tiles: 16 rows per lane would spill
     for (; r >= 2; r /= 2) {
         p.R = r;
         p.TM = NT_MM / lpr * r;

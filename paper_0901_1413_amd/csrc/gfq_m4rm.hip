@@ -37,6 +37,9 @@ static hipError_t launch_mm_rows(const MMArgs &a, const MMPlan &plan, hipStream_
         return launch_mm<Q, TWD, REP, 4>(a, plan, st);       // eight rows per lane would spill
     } else {
         if (plan.R == 4) return launch_mm<Q, TWD, REP, 4>(a, plan, st);
+        if constexpr (Q == 4 && TWD == 16) {
+            if (plan.R == 16) return launch_mm<Q, TWD, REP, 16>(a, plan, st);   // two planes per word
+        }
         return launch_mm<Q, TWD, REP, 8>(a, plan, st);
     }
 }
