@@ -57,8 +57,8 @@ C_ADD_PAPER = {3: 6, 4: 2, 5: 20, 7: 17}
 # valid only while the kernel sources hash to `src` (otherwise the roofline reports null).
 KERNEL_SOURCES = ("gfq_m4rm.hip", "gfq_m4rm_tile.h", "gfq_device.h", "gfq_field.h", "gfq_internal.h")
 MEASURED_TRAFFIC = {
-    3: {"src": "bb109ef77ad054eb", "read_mib": 597.4, "write_mib": 64.0},
-    5: {"src": "bb109ef77ad054eb", "read_mib": 243.4, "write_mib": 24.0},
+    3: {"src": "49f8073743fdc0e6", "read_mib": 655.1, "write_mib": 64.0},
+    5: {"src": "49f8073743fdc0e6", "read_mib": 243.1, "write_mib": 24.0},
 }
 
 
