@@ -78,7 +78,11 @@ int gfq_unpack(int q, int64_t rows, int64_t cols, const void *src, uint8_t *dst,
  * basis {alpha_d} with bit maps phi_d reduces each slab to binary combinations of rows).
  * A: packed m x l, B: packed l x n, C: packed m x n, all device pointers in the format
  * above.  C must not overlap A or B.  l must be below GFQ_MAX_DIM.  m == 0 or n == 0 is a
- * no-op; l == 0 writes a zero C.  Pad bits of A and B are ignored. */
+ * no-op; l == 0 writes a zero C.  Pad bits of A and B are ignored.
+ * When the configuration splits the inner dimension, the partial products go to a device
+ * workspace the library keeps per (device, stream) until the process ends (64 MiB or more;
+ * GFQ_ENOMEM if it cannot be had); growing it waits for that stream.  Products on different
+ * streams may run concurrently. */
 int gfq_matmul(int q, int64_t m, int64_t l, int64_t n, const void *A, const void *B, void *C);
 
 /* Explicit launch configuration for gfq_matmul_config (used by the autotuner and the k

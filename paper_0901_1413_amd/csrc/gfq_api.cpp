@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <vector>
 
@@ -48,42 +49,40 @@ template <typename Fn> hipError_t timed(int kind, Fn f) {
     return e;
 }
 
-// Device workspace for split-l partial products, one growing buffer per device.
+// Device workspace for split-l partial products: one growing buffer per (device, stream),
+// so products in flight on different streams never share partial sums.  A buffer is only
+// replaced after its stream has finished the work queued on it; buffers live until the
+// process ends (the library cannot tell when a caller destroys a stream).
 struct Workspace {
     std::mutex mu;
-    std::vector<void *> ptr;
-    std::vector<size_t> bytes;
+    std::map<std::pair<int, hipStream_t>, std::pair<void *, size_t>> buf;
 };
 Workspace g_ws;
 
-int workspace(size_t need, void **out) {
+int workspace(size_t need, hipStream_t st, void **out) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     std::lock_guard<std::mutex> lk(g_ws.mu);
-    if ((int)g_ws.ptr.size() <= dev) {
-        g_ws.ptr.resize(dev + 1, nullptr);
-        g_ws.bytes.resize(dev + 1, 0);
-    }
-    if (g_ws.bytes[dev] < need) {
-        if (g_ws.ptr[dev]) {
-            // kernels queued on any stream may still read the old buffer
-            e = hipDeviceSynchronize();
-            if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-            (void)hipFree(g_ws.ptr[dev]);
-            g_ws.ptr[dev] = nullptr;
-            g_ws.bytes[dev] = 0;
+    std::pair<void *, size_t> &b = g_ws.buf[std::make_pair(dev, st)];
+    if (b.second < need) {
+        if (b.first) {
+            // kernels queued on this stream may still read the old buffer
+            e = hipStreamSynchronize(st);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+            (void)hipFree(b.first);
+            b = std::make_pair(nullptr, (size_t)0);
         }
         size_t sz = std::max(need, (size_t)64 << 20);
-        e = hipMalloc(&g_ws.ptr[dev], sz);
+        void *p = nullptr;
+        e = hipMalloc(&p, sz);
         if (e != hipSuccess) {
-            g_ws.ptr[dev] = nullptr;
             hip_fail(e, "hipMalloc(workspace)");
             return GFQ_ENOMEM;
         }
-        g_ws.bytes[dev] = sz;
+        b = std::make_pair(p, sz);
     }
-    *out = g_ws.ptr[dev];
+    *out = b.first;
     return GFQ_OK;
 }
 
@@ -309,7 +308,7 @@ int gfq_matmul_config(int q, int64_t m, int64_t l, int64_t n, const void *A, con
         return e == hipSuccess ? GFQ_OK : hip_fail(e, "matmul launch");
     }
     void *ws = nullptr;
-    st = workspace(a.split_stride * 4 * split, &ws);
+    st = workspace(a.split_stride * 4 * split, t_stream, &ws);
     if (st != GFQ_OK) return st;
     a.out = (u32 *)ws;
     hipError_t e = timed(0, [&] { return launch_matmul(q, a, plan, t_stream); });

@@ -168,3 +168,23 @@ def test_pack_unpack_strided_and_offset(gfq_gpu, q):
         o = out.cpu().numpy()
         assert np.array_equal(o[:, 7:7 + cols], big[:, c0:c0 + cols]), (c0, cols)
         assert (o[:, :7] == 0xEE).all() and (o[:, 7 + cols:] == 0xEE).all()   # nothing outside
+
+
+def test_split_products_on_concurrent_streams(gfq_gpu):
+    """Products whose inner dimension is split write partial sums to a workspace; products in
+    flight on different streams must not share it."""
+    import torch
+    g = gfq_gpu
+    q, m, l, n = 5, 700, 2000, 900
+    pairs = [inputs.pair(q, m, l, n, cfg=0, idx=70 + i) for i in range(4)]
+    dev = [(g.pack(q, torch.from_numpy(A).cuda()), g.pack(q, torch.from_numpy(B).cuda())) for A, B in pairs]
+    outs = [g.empty_packed(q, m, n) for _ in pairs]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for rep in range(3):
+        for i, (Ap, Bp) in enumerate(dev):
+            with torch.cuda.stream(streams[i % 2]):
+                g.matmul(q, Ap, Bp, m, l, n, out=outs[i], k=6, rows=256, split=8)
+    torch.cuda.synchronize()
+    for i, (A, B) in enumerate(pairs):
+        assert np.array_equal(g.unpack(q, outs[i], m, n).cpu().numpy(), oracle.matmul(q, A, B)), i
