@@ -3,13 +3,16 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "gfq_m4rm_tile.h"
 
 namespace gfq {
 
+// grid (column tiles, row tiles, slab slices); row tile ty0 + blockIdx.y
 template <int Q, int TWD, int REP, int R, int NT>
-__global__ __launch_bounds__(NT) void m4rm_kernel(MMArgs a) {
-    m4rm_tile<Q, TWD, REP, R, NT>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+__global__ __launch_bounds__(NT) void m4rm_kernel(MMArgs a, int ty0) {
+    m4rm_tile<Q, TWD, REP, R, NT>(a, blockIdx.x, ty0 + (int)blockIdx.y, blockIdx.z);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -22,12 +25,19 @@ static hipError_t launch_mm(const MMArgs &a0, const MMPlan &plan, hipStream_t st
     if (plan.TM != TM || plan.lds > 163840) return hipErrorInvalidValue;
     MMArgs a = a0;
     a.tb1 = plan.tb1;
-    dim3 grid((a.Wn + TWD - 1) / TWD, (a.m + TM - 1) / TM, (a.S + a.slabs_per_split - 1) / a.slabs_per_split);
+    const int row_tiles = (a.m + TM - 1) / TM;
     auto kern = m4rm_kernel<Q, TWD, REP, R, NT_MM>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)plan.lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, grid, dim3(NT_MM), plan.lds, st, a);
-    return hipGetLastError();
+    // a grid's y extent is at most 65535: taller products take several launches
+    for (int ty0 = 0; ty0 < row_tiles; ty0 += 65535) {
+        dim3 grid((a.Wn + TWD - 1) / TWD, std::min(65535, row_tiles - ty0),
+                  (a.S + a.slabs_per_split - 1) / a.slabs_per_split);
+        hipLaunchKernelGGL(kern, grid, dim3(NT_MM), plan.lds, st, a, ty0);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <int Q, int TWD, int REP>

@@ -188,3 +188,21 @@ def test_split_products_on_concurrent_streams(gfq_gpu):
     torch.cuda.synchronize()
     for i, (A, B) in enumerate(pairs):
         assert np.array_equal(g.unpack(q, outs[i], m, n).cpu().numpy(), oracle.matmul(q, A, B)), i
+
+
+def test_more_row_tiles_than_one_grid_holds(gfq_gpu):
+    """A grid holds at most 65535 row tiles; a taller product is launched in pieces.  F_3 with
+    256-row tiles and m = 65535 * 256 + 300 rows, checked on rows around the piece boundary."""
+    import torch
+    g = gfq_gpu
+    q, l, n = 3, 32, 64
+    m = 65535 * 256 + 300
+    A, B = inputs.pair(q, m, l, n, cfg=0, idx=80)
+    Ap, Bp = g.pack(q, torch.from_numpy(A).cuda()), g.pack(q, torch.from_numpy(B).cuda())
+    Cp = g.empty_packed(q, m, n)
+    g.matmul(q, Ap, Bp, m, l, n, out=Cp, k=6, rows=256, split=1)
+    C = g.unpack(q, Cp, m, n)
+    edge = 65535 * 256
+    rows = np.concatenate([np.arange(0, 64), np.arange(edge - 300, edge + 300), np.arange(m - 64, m)])
+    got = C[torch.from_numpy(rows).cuda()].cpu().numpy()
+    assert np.array_equal(got, oracle.matmul(q, A[rows], B))
