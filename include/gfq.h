@@ -129,7 +129,9 @@ int gfq_matmul_batched(int count, const gfq_problem *problems);
  * product's size class), orders each (field, tile height) list of (product, row tile,
  * column tile) items longest first and uploads the descriptors; it synchronises.
  * gfq_batch_launch enqueues, on the calling thread's stream, one launch per list (a
- * workgroup per item) and allocates nothing, so it may be captured into a graph.
+ * workgroup per item) and allocates nothing, so it may be captured into a graph.  Launches
+ * of one batch must not overlap in time (they share its tile counters, completion stamps
+ * and outputs): issue them on one stream, or wait for one before issuing the next.
  * gfq_batch_times waits for that stream and writes, per product, the microseconds from the
  * start of the most recent launch to the completion of the product's last tile.
  * gfq_batch_destroy waits for the device and frees everything. */
