@@ -1,5 +1,5 @@
-// gfq_m4rm_tile.h -- the Four-Russians product on one tile, shared by the plain and the
-// batched (persistent) kernels.
+// gfq_m4rm_tile.h -- the Four-Russians product on one tile, shared by the plain kernel
+// and the work-list kernel of batches.
 //
 // Method (paper, Section 2): row i of C is sum_j a_ij B_j.  The inner dimension is cut
 // into slabs of k rows of B; for each slab a table of all 2^k binary combinations of its
@@ -15,8 +15,9 @@
 // Each lane owns 4 consecutive words of R rows of C and keeps their accumulators in VGPRs.
 //
 // Pipeline per workgroup (one barrier per slab).  Iteration s:
-//   stage   write slab s+2's rows of B (prefetched into registers one iteration earlier)
-//           and the phi_d table offsets of every row of the tile for slab s+2 into LDS;
+//   stage   write slab s+3's rows of B (loaded into registers one iteration earlier) and
+//           the phi_d table offsets of every row of the tile for slab s+2 into LDS;
+//   prefix  (three-plane fields) the chunk prefixes of slab s+2's table;
 //   build   the table of slab s+1 into the idle table buffer, in Gray-code order;
 //   gather  for every row, D table rows of slab s, alpha_d-scaled into the accumulator;
 //   barrier.
@@ -318,13 +319,22 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
     const u32 laneoff = (u32)(tid % (REP * LPR)) * 16u;
 
     // gathers of one row: D table rows, P planes each, 4 words per lane
+    // The kernels allocate no static LDS, so the dynamic buffer starts at LDS address 0 and
+    // an offset into it is its LDS address: the reads go through an LDS pointer made from
+    // the offset, which spares an addition of the buffer's base per table row.
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    typedef __attribute__((address_space(3))) const u32x4 lds_u32x4;
     auto fetch = [&](const u32 *iw, int r, u32 lo, uint4 (&t)[D][P]) {
 #pragma unroll
         for (int d = 0; d < D; d++) {
             const u32 x = iw[r * IBW + (d >> 1)];
             const u32 off = ((d & 1) ? (x >> 16) : (x & 0xffffu)) | lo;
+            lds_u32x4 *row = (lds_u32x4 *)(uintptr_t)off;
 #pragma unroll
-            for (int p = 0; p < P; p++) t[d][p] = *reinterpret_cast<const uint4 *>(smem + off + p * SRB);
+            for (int p = 0; p < P; p++) {
+                const u32x4 v = row[p * (SRB / 16)];
+                t[d][p] = make_uint4(v.x, v.y, v.z, v.w);
+            }
         }
     };
     auto consume = [&](int r, const uint4 (&t)[D][P]) {
