@@ -94,8 +94,17 @@ int gfq_matmul(int q, int64_t m, int64_t l, int64_t n, const void *A, const void
  *   rows   requested rows of C per workgroup: 256, 512, 1024 or 2048 (F_5 and F_7 are
  *          capped by their register use; the library covers what fits)
  *   split  number of slices of the inner dimension computed by separate workgroups and
- *          summed afterwards, 1..64 */
-typedef struct { int k; int rows; int split; int reserved; } gfq_config;
+ *          summed afterwards, 1..64
+ *   variant how GF(4) products are formed (other fields: GFQ_VARIANT_ROWWISE only):
+ *          GFQ_VARIANT_ROWWISE  row-wise additive basis {1, x}: two table rows of two
+ *                               planes per slab (Section 2 with the encoding of 4.3);
+ *          GFQ_VARIANT_KARATSUBA matrix-level Karatsuba over F_2 (Section 4.3): three F_2
+ *                               products, C0 = A0 B0 + A1 B1 and C1 = (A0 + A1)(B0 + B1) +
+ *                               A0 B0, on three-plane tables (one plane read per product)
+ *          Both give the same packed product; batches use the row-wise form. */
+#define GFQ_VARIANT_ROWWISE 0
+#define GFQ_VARIANT_KARATSUBA 1
+typedef struct { int k; int rows; int split; int variant; } gfq_config;
 
 /* gfq_matmul with an explicit configuration (used by the autotuner and the k sweep).
  * Returns GFQ_EINVAL for a configuration outside the ranges above. */

@@ -91,11 +91,17 @@ bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
     return na && nb && pa < pb + nb && pb < pa + na;
 }
 
+// Kernel field of a product over API field q in configuration c.
+int kernel_field(int q, const gfq_config &c) {
+    return (q == 4 && c.variant == GFQ_VARIANT_KARATSUBA) ? GF4_KARATSUBA : q;
+}
+
 int check_config(int q, const gfq_config &c) {
     if (c.k < 1 || c.k > KMAX) return GFQ_EINVAL;
     if (c.rows != 256 && c.rows != 512 && c.rows != 1024 && c.rows != 2048) return GFQ_EINVAL;
     if (c.split < 1 || c.split > 64) return GFQ_EINVAL;
-    if (mm_plan(q, c.k, c.rows).srb == 0) return GFQ_EINVAL;
+    if (c.variant != GFQ_VARIANT_ROWWISE && !(c.variant == GFQ_VARIANT_KARATSUBA && q == 4)) return GFQ_EINVAL;
+    if (mm_plan(kernel_field(q, c), c.k, c.rows).srb == 0) return GFQ_EINVAL;
     return GFQ_OK;
 }
 
@@ -263,7 +269,7 @@ int gfq_choose_config(int q, int64_t m, int64_t l, int64_t n, gfq_config *out) {
             best.split = (int)split;
         }
     }
-    best.reserved = 0;
+    best.variant = GFQ_VARIANT_ROWWISE;
     *out = best;
     return GFQ_OK;
 }
@@ -301,17 +307,18 @@ int gfq_matmul_config(int q, int64_t m, int64_t l, int64_t n, const void *A, con
     a.slabs_per_split = (a.S + split - 1) / split;
     split = (a.S + a.slabs_per_split - 1) / a.slabs_per_split;
     a.split_stride = (size_t)m * P * Wn;
-    const MMPlan plan = mm_plan(q, c.k, c.rows);
+    const int kq = kernel_field(q, c);
+    const MMPlan plan = mm_plan(kq, c.k, c.rows);
     if (split == 1) {
         a.out = (u32 *)C;
-        hipError_t e = timed(0, [&] { return launch_matmul(q, a, plan, t_stream); });
+        hipError_t e = timed(0, [&] { return launch_matmul(kq, a, plan, t_stream); });
         return e == hipSuccess ? GFQ_OK : hip_fail(e, "matmul launch");
     }
     void *ws = nullptr;
     st = workspace(a.split_stride * 4 * split, t_stream, &ws);
     if (st != GFQ_OK) return st;
     a.out = (u32 *)ws;
-    hipError_t e = timed(0, [&] { return launch_matmul(q, a, plan, t_stream); });
+    hipError_t e = timed(0, [&] { return launch_matmul(kq, a, plan, t_stream); });
     if (e != hipSuccess) return hip_fail(e, "matmul launch");
     e = timed(1, [&] {
         return launch_reduce(q, (const u32 *)ws, (u32 *)C, (int)m, (int)n, Wn, split, a.split_stride, t_stream);

@@ -12,6 +12,7 @@
 
 #define GFQ_HD __host__ __device__ __forceinline__
 #include "gfq_field.h"
+#include "gfq_internal.h"
 
 namespace gfq {
 
@@ -21,7 +22,8 @@ template <int Q> struct FT;
 // Table entries are binary residues mod 3; the accumulator is a carry-save pair mod 3 and
 // receives T[phi_0] and -T[phi_1] (the complement) per slab.
 template <> struct FT<3> {
-    static constexpr int P = 2, D = 2, PA = 4;
+    static constexpr int P = 2, PT = 2, D = 2, GP = 2, PA = 4;
+    static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0] ^ x[1]; f[1] = x[1]; }
     __device__ static void to_table(const u32 *x, u32 *t) { f3_to_bin(x[0], x[1], t); }
     __device__ static void tadd(const u32 *a, const u32 *b, u32 *r) { f3b_add(a, b, r); }
@@ -47,7 +49,8 @@ template <> struct FT<3> {
 // F_7 (Section 4.2).  Basis {1, 2, 4}, phi_d = plane d.  Doubling modulo 7 rotates the
 // planes, so alpha_d T[phi_d] costs nothing; the accumulator is a carry-save pair mod 7.
 template <> struct FT<7> {
-    static constexpr int P = 3, D = 3, PA = 6;
+    static constexpr int P = 3, PT = 3, D = 3, GP = 3, PA = 6;
+    static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; f[2] = x[2]; }
     __device__ static void to_table(const u32 *x, u32 *t) { t[0] = x[0]; t[1] = x[1]; t[2] = x[2]; }
     __device__ static void tadd(const u32 *a, const u32 *b, u32 *r) {
@@ -83,7 +86,8 @@ template <> struct FT<7> {
 // half of the carry-save pair) and is reduced mod 5 once, at the end; a slab's three
 // scaled rows enter it together (f5_csa_slab).
 template <> struct FT<5> {
-    static constexpr int P = 3, D = 3, PA = 8;
+    static constexpr int P = 3, PT = 3, D = 3, GP = 3, PA = 8;
+    static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; f[2] = x[2]; }
     __device__ static void to_table(const u32 *x, u32 *t) { t[0] = x[0]; t[1] = x[1]; t[2] = x[2]; }
     __device__ static void tadd(const u32 *a, const u32 *b, u32 *r) {
@@ -114,7 +118,8 @@ template <> struct FT<5> {
 // GF(4) (Section 4.3).  Basis {1, x}, phi_d = c_d.  Per slab the row receives
 // T[phi_0] + x T[phi_1]; with x (c0 + c1 x) = c1 + (c0 + c1) x that is two XOR planes.
 template <> struct FT<4> {
-    static constexpr int P = 2, D = 2, PA = 2;
+    static constexpr int P = 2, PT = 2, D = 2, GP = 2, PA = 2;
+    static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; }
     __device__ static void to_table(const u32 *x, u32 *t) { t[0] = x[0]; t[1] = x[1]; }
     __device__ static void tadd(const u32 *a, const u32 *b, u32 *r) { r[0] = a[0] ^ b[0]; r[1] = a[1] ^ b[1]; }
@@ -126,6 +131,30 @@ template <> struct FT<4> {
     }
     __device__ static void finish(const u32 *c, u32 *out) { out[0] = c[0]; out[1] = c[1]; }
     __device__ static void sadd(const u32 *a, const u32 *b, u32 *r) { tadd(a, b, r); }
+    __device__ static void scanon(u32 *) {}
+};
+
+// GF(4) by matrix-level Karatsuba over F_2 (Section 4.3): with A = A0 + x A1 and
+// B = B0 + x B1 (coefficient planes), C0 = A0 B0 + A1 B1 and C1 = (A0 + A1)(B0 + B1) + A0 B0,
+// three F_2 products.  Each table entry holds the three F_2 tables of the slab (planes
+// B0, B1, B0 + B1); a row gathers one plane of three entries: T0[a0], T1[a1], T2[a0 + a1].
+// Same packed operands and product as FT<4>; selected by the configuration.
+template <> struct FT<GF4_KARATSUBA> {
+    static constexpr int P = 2, PT = 3, D = 3, GP = 1, PA = 2;
+    static constexpr int gplane(int d, int) { return d; }
+    __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; f[2] = x[0] ^ x[1]; }
+    __device__ static void to_table(const u32 *x, u32 *t) { t[0] = x[0]; t[1] = x[1]; t[2] = x[0] ^ x[1]; }
+    __device__ static void tadd(const u32 *a, const u32 *b, u32 *r) {
+        r[0] = a[0] ^ b[0]; r[1] = a[1] ^ b[1]; r[2] = a[2] ^ b[2];
+    }
+    __device__ static void tsub(const u32 *a, const u32 *b, u32 *r) { tadd(a, b, r); }
+    __device__ static void acc_init(u32 *c, int) { c[0] = c[1] = 0u; }
+    __device__ static void accumulate(u32 *c, const u32 (*t)[GP]) {
+        c[0] = xor3(c[0], t[0][0], t[1][0]);              // A0 B0 + A1 B1
+        c[1] = xor3(c[1], t[2][0], t[0][0]);              // (A0 + A1)(B0 + B1) + A0 B0
+    }
+    __device__ static void finish(const u32 *c, u32 *out) { out[0] = c[0]; out[1] = c[1]; }
+    __device__ static void sadd(const u32 *a, const u32 *b, u32 *r) { r[0] = a[0] ^ b[0]; r[1] = a[1] ^ b[1]; }
     __device__ static void scanon(u32 *) {}
 };
 

@@ -27,18 +27,25 @@ struct MMArgs {
     u32 tb1;               // LDS offset of the second table (set by the launcher)
 };
 
-inline int planes_of(int q) { return (q == 3 || q == 4) ? 2 : 3; }
+// Kernel field of GF(4) products computed by matrix-level Karatsuba over F_2 (the API
+// field is q = 4, chosen by gfq_config.variant).
+constexpr int GF4_KARATSUBA = 40;
+
+// planes per packed row; planes per table entry; table rows gathered per slab
+inline int planes_of(int q) { return (q == 3 || q == 4 || q == GF4_KARATSUBA) ? 2 : 3; }
+inline int table_planes(int q) { return q == GF4_KARATSUBA ? 3 : planes_of(q); }
+inline int gathers_of(int q) { return (q == 3 || q == 4) ? 2 : 3; }
 inline int words_of(int64_t cols) { return (int)(((cols + 127) / 128) * 4); }
 // Rows of C per lane: bounded by the accumulator registers (8 planes per word for F_5, 6
 // for F_7, 4 for F_3, 2 for GF(4)).  The work-list kernels of batches use at most 8.
-inline int max_rows_per_lane(int q) { return q == 5 || q == 7 ? 4 : (q == 4 ? 16 : 8); }
+inline int max_rows_per_lane(int q) { return q == 5 || q == 7 ? 4 : (q == 4 || q == GF4_KARATSUBA ? 16 : 8); }
 inline int max_rows_per_lane_batch(int q) { return q == 5 ? 2 : (q == 7 ? 4 : 8); }
 
 // Table super-row bytes for field q and slab width k: the widest of 256, 128, 64, 32, 16
 // such that both table buffers fit TABLES_LDS (0 if none does).
 inline int srb_for(int q, int k) {
     for (int srb = 256; srb >= 16; srb >>= 1)
-        if (2 * ((size_t)1 << k) * planes_of(q) * srb <= TABLES_LDS) return srb;
+        if (2 * ((size_t)1 << k) * table_planes(q) * srb <= TABLES_LDS) return srb;
     return 0;
 }
 inline int twd_of(int srb) { return srb >= 64 ? 16 : srb / 4; }   // tile words per plane
@@ -55,14 +62,14 @@ struct MMPlan {
 };
 
 inline size_t mm_lds_bytes(int q, int k, int srb, int TM, u32 *tb1_out) {
-    const int P = planes_of(q), D = P;
-    const u32 tbytes = (u32)(1u << k) * P * srb;
+    const int P = planes_of(q), PT = table_planes(q), D = gathers_of(q);
+    const u32 tbytes = (u32)(1u << k) * PT * srb;
     u32 tb1 = 16;
     while (tb1 < tbytes) tb1 <<= 1;
     if (tb1_out) *tb1_out = tb1;
     // two tables, B staging [3][KMAX][P][TWD], chunk prefixes [2][NT/TWD][P][TWD] (three
     // planes only), table offsets [3][TM][(D+1)/2]
-    return (size_t)tb1 + tbytes + 3 * KMAX * P * twd_of(srb) * 4 + (P == 3 ? 2 * (size_t)NT_MM * P * 4 : 0) +
+    return (size_t)tb1 + tbytes + 3 * KMAX * P * twd_of(srb) * 4 + (P == 3 ? 2 * (size_t)NT_MM * PT * 4 : 0) +
            3 * (size_t)TM * ((D + 1) / 2) * 4;
 }
 

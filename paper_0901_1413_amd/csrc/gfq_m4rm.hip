@@ -47,7 +47,7 @@ static hipError_t launch_mm_rows(const MMArgs &a, const MMPlan &plan, hipStream_
         return launch_mm<Q, TWD, REP, 4>(a, plan, st);       // eight rows per lane would spill
     } else {
         if (plan.R == 4) return launch_mm<Q, TWD, REP, 4>(a, plan, st);
-        if constexpr (Q == 4 && TWD == 16) {
+        if constexpr ((Q == 4 || Q == GF4_KARATSUBA) && TWD == 16) {
             if (plan.R == 16) return launch_mm<Q, TWD, REP, 16>(a, plan, st);   // two planes per word
         }
         return launch_mm<Q, TWD, REP, 8>(a, plan, st);
@@ -70,6 +70,7 @@ hipError_t launch_matmul(int q, const MMArgs &a, const MMPlan &plan, hipStream_t
     switch (q) {
     case 3: return launch_mm_q<3>(a, plan, st);
     case 4: return launch_mm_q<4>(a, plan, st);
+    case GF4_KARATSUBA: return launch_mm_q<GF4_KARATSUBA>(a, plan, st);
     case 5: return launch_mm_q<5>(a, plan, st);
     default: return launch_mm_q<7>(a, plan, st);
     }

@@ -48,7 +48,9 @@ __device__ __forceinline__ u32 comp4(const uint4 &v, int i) {
 template <int Q, int TWD, int REP, int R, int NT>
 __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int bz) {
     typedef FT<Q> F;
-    constexpr int P = F::P, D = F::D, PA = F::PA;
+    // P planes per row in the packed operands, PT planes per table entry, D table rows
+    // gathered per slab (GP planes of each), PA accumulator planes per word
+    constexpr int P = F::P, PT = F::PT, D = F::D, GP = F::GP, PA = F::PA;
     constexpr int LPR = TWD / 4;                 // lanes per row of C
     constexpr int SRB = REP * TWD * 4;           // bytes per (entry, plane) super-row
     constexpr int RS = NT / LPR;                 // row slots per pass
@@ -64,7 +66,7 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
 
     extern __shared__ __align__(16) unsigned char smem[];
     const int k = a.k;
-    const u32 tbytes = (u32)(1u << k) * P * SRB;
+    const u32 tbytes = (u32)(1u << k) * PT * SRB;
     const u32 TB1 = a.tb1;                       // power of two >= tbytes, <= 65536
     u32 *Bst = reinterpret_cast<u32 *>(smem + TB1 + tbytes);   // [3][KMAX][P][TWD]
     u32 *PB = Bst + 3 * KMAX * P * TWD;                         // [2][NCH][P][TWD] (P = 3 only)
@@ -120,7 +122,7 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
         const int lr = tid + j * NT;
         return (lr < TM && row0 + lr < a.m && w < a.Wl) ? 0xffffffffu : 0u;
     };
-    // offsets (u16, entry * P * SRB) of the D table rows for slab s, for every tile row
+    // offsets (u16, entry * PT * SRB) of the D table rows for slab s, for every tile row
     auto stage_idx = [&](int s) {
         const int sh = (s * k) & 31;
         u32 *ib = Ib + (s % 3) * TM * IBW;
@@ -134,7 +136,7 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
                 F::phis(x, f);
                 u32 o[IBW * 2];
 #pragma unroll
-                for (int d = 0; d < IBW * 2; d++) o[d] = d < D ? f[d < D ? d : 0] * (u32)(P * SRB) : 0u;
+                for (int d = 0; d < IBW * 2; d++) o[d] = d < D ? f[d < D ? d : 0] * (u32)(PT * SRB) : 0u;
                 // slot-major: the R rows of one row slot are adjacent, so a lane fetches
                 // all of its offsets with one or two 128-bit reads
                 const int pos = (lr % RS) * R + lr / RS;
@@ -183,7 +185,7 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
     // two) and leave them in a small buffer.  For two planes, where a table addition costs
     // only 6 (F_3) or 2 (GF(4)) instructions, each thread sums its own prefix (a masked sum).
     // The rows a stage needs are read from LDS in one batch before its chain of additions. ----
-    constexpr bool SPLIT_PREFIX = P == 3;
+    constexpr bool SPLIT_PREFIX = P == 3 && PT == 3;
     constexpr int GMAX = KMAX > LOG_NCH ? KMAX - LOG_NCH : 0;   // longest walk: 2^GMAX entries
     constexpr int PFW = NCH / 4;                                // prefix threads per word
     constexpr int PFB = LOG_NCH > 2 ? LOG_NCH - 2 : 0;         // masked bits per prefix thread
@@ -196,11 +198,11 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
 #pragma unroll
     for (int i = 0; i < REP; i++) rep_off[i] = (u32)(((i + ch) % REP) * TWD * 4);
     auto step = [&](u32 *v, const u32 *r, bool on) {
-        u32 z[P];
+        u32 z[PT];
         if (on) F::tadd(v, r, z);
         else F::tsub(v, r, z);
 #pragma unroll
-        for (int p = 0; p < P; p++) v[p] = z[p];
+        for (int p = 0; p < PT; p++) v[p] = z[p];
     };
     // Every staged row index read below is below KMAX, inside the staging buffer, so the
     // reads are unconditional (rows at or beyond k hold stale data and are masked or never
@@ -208,8 +210,8 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
     auto prefix = [&](int s) {
         if (!SPLIT_PREFIX || ch >= PFW) return;  // thread (dw, g = ch) of the first NT/4
         const u32 *bs = Bst + (s % 3) * KMAX * P * TWD + dw;
-        u32 *pb = PB + (s & 1) * NCH * P * TWD + dw;
-        u32 hr[PFB > 0 ? PFB : 1][P], lo0[P], lo1[P];
+        u32 *pb = PB + (s & 1) * NCH * PT * TWD + dw;
+        u32 hr[PFB > 0 ? PFB : 1][PT], lo0[PT], lo1[PT];
 #pragma unroll
         for (int t = 0; t < PFB; t++) {
             u32 x[P];
@@ -227,22 +229,22 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
             F::to_table(x, lo0);
             F::to_table(y, lo1);
         }
-        u32 v[P];
+        u32 v[PT];
 #pragma unroll
-        for (int p = 0; p < P; p++) v[p] = 0u;
+        for (int p = 0; p < PT; p++) v[p] = 0u;
 #pragma unroll
         for (int t = 0; t < PFB; t++) {
             const u32 m = (2 + t < C) ? 0u - (u32)((ch >> t) & 1) : 0u;
-            u32 r[P];
+            u32 r[PT];
 #pragma unroll
-            for (int p = 0; p < P; p++) r[p] = hr[t][p] & m;         // the zero row adds nothing
+            for (int p = 0; p < PT; p++) r[p] = hr[t][p] & m;        // the zero row adds nothing
             step(v, r, true);
         }
         const int c0 = ch * 4;
         auto put = [&](int c, const u32 *x) {
             if (c < nchunks)
 #pragma unroll
-                for (int p = 0; p < P; p++) pb[(c * P + p) * TWD] = x[p];
+                for (int p = 0; p < PT; p++) pb[(c * PT + p) * TWD] = x[p];
         };
         put(c0, v);
         step(v, lo0, true);
@@ -260,13 +262,13 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
 #pragma unroll
             for (int i = 0; i < REP; i++)
 #pragma unroll
-                for (int p = 0; p < P; p++) *reinterpret_cast<u32 *>(dst + p * SRB + rep_off[i]) = v[p];
+                for (int p = 0; p < PT; p++) *reinterpret_cast<u32 *>(dst + p * SRB + rep_off[i]) = v[p];
         };
-        u32 v[P];
+        u32 v[PT];
         if constexpr (SPLIT_PREFIX) {
-            const u32 *pb = PB + (s & 1) * NCH * P * TWD + dw;
+            const u32 *pb = PB + (s & 1) * NCH * PT * TWD + dw;
 #pragma unroll
-            for (int p = 0; p < P; p++) v[p] = pb[(ch * P + p) * TWD];
+            for (int p = 0; p < PT; p++) v[p] = pb[(ch * PT + p) * TWD];
         } else {
             // the chunk's prefix here: a masked sum of its rows G + t
             u32 pr[LOG_NCH][P];
@@ -275,21 +277,21 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
 #pragma unroll
                 for (int p = 0; p < P; p++) pr[t][p] = bs[((G + t) * P + p) * TWD];
 #pragma unroll
-            for (int p = 0; p < P; p++) v[p] = 0u;
+            for (int p = 0; p < PT; p++) v[p] = 0u;
 #pragma unroll
             for (int t = 0; t < LOG_NCH; t++) {
                 const u32 m = (t < C) ? 0u - (u32)((ch >> t) & 1) : 0u;
-                u32 r[P], x[P];
+                u32 r[PT], x[PT];
                 F::to_table(pr[t], x);
 #pragma unroll
-                for (int p = 0; p < P; p++) r[p] = x[p] & m;         // the zero row adds nothing
+                for (int p = 0; p < PT; p++) r[p] = x[p] & m;        // the zero row adds nothing
                 step(v, r, true);
             }
         }
-        unsigned char *eb = T + (u32)(ch << G) * (P * SRB);
+        unsigned char *eb = T + (u32)(ch << G) * (PT * SRB);
         store(eb, v);
         if constexpr (GMAX > 0) {
-            u32 wr[GMAX > 0 ? GMAX : 1][P];
+            u32 wr[GMAX > 0 ? GMAX : 1][PT];
 #pragma unroll
             for (int b = 0; b < GMAX; b++) {
                 u32 x[P];
@@ -303,7 +305,7 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
                 const int b = __builtin_ctz(j);
                 const int g = j ^ (j >> 1);
                 step(v, wr[b], (g >> b) & 1);
-                store(eb + g * (P * SRB), v);
+                store(eb + g * (PT * SRB), v);
             }
         }
     };
@@ -318,33 +320,34 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
     const int rs = tid / LPR, cg = tid % LPR;
     const u32 laneoff = (u32)(tid % (REP * LPR)) * 16u;
 
-    // gathers of one row: D table rows, P planes each, 4 words per lane
+    // gathers of one row: D table rows, GP planes each (plane F::gplane(d, p) of row d), 4 words
+    // per lane
     // The kernels allocate no static LDS, so the dynamic buffer starts at LDS address 0 and
     // an offset into it is its LDS address: the reads go through an LDS pointer made from
     // the offset, which spares an addition of the buffer's base per table row.
     typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
     typedef __attribute__((address_space(3))) const u32x4 lds_u32x4;
-    auto fetch = [&](const u32 *iw, int r, u32 lo, uint4 (&t)[D][P]) {
+    auto fetch = [&](const u32 *iw, int r, u32 lo, uint4 (&t)[D][GP]) {
 #pragma unroll
         for (int d = 0; d < D; d++) {
             const u32 x = iw[r * IBW + (d >> 1)];
             const u32 off = ((d & 1) ? (x >> 16) : (x & 0xffffu)) | lo;
             lds_u32x4 *row = (lds_u32x4 *)(uintptr_t)off;
 #pragma unroll
-            for (int p = 0; p < P; p++) {
-                const u32x4 v = row[p * (SRB / 16)];
+            for (int p = 0; p < GP; p++) {
+                const u32x4 v = row[F::gplane(d, p) * (SRB / 16)];
                 t[d][p] = make_uint4(v.x, v.y, v.z, v.w);
             }
         }
     };
-    auto consume = [&](int r, const uint4 (&t)[D][P]) {
+    auto consume = [&](int r, const uint4 (&t)[D][GP]) {
 #pragma unroll
         for (int i = 0; i < 4; i++) {
-            u32 ti[D][P];
+            u32 ti[D][GP];
 #pragma unroll
             for (int d = 0; d < D; d++)
 #pragma unroll
-                for (int p = 0; p < P; p++) ti[d][p] = comp4(t[d][p], i);
+                for (int p = 0; p < GP; p++) ti[d][p] = comp4(t[d][p], i);
             F::accumulate(acc[r][i], ti);
         }
     };
@@ -366,7 +369,7 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
                 iw[w] = v.x; iw[w + 1] = v.y;
             }
         }
-        uint4 ta[D][P], tb[D][P];
+        uint4 ta[D][GP], tb[D][GP];
         fetch(iw, 0, lo, ta);
 #pragma unroll
         for (int r = 0; r < R; r += 2) {

@@ -142,17 +142,21 @@ int gfq_tune(int q, int64_t m, int64_t l, int64_t n, int mode, gfq_config *out) 
         if (status == GFQ_OK) {
             char *A = (char *)base, *B = A + ba, *C = B + bb;
             const int reps = ops < 1e10 ? 7 : 3;
+            // GF(4) also tries its Karatsuba form
+            const int nvar = q == 4 ? 2 : 1;
+            for (int var = 0; var < nvar; var++)
             for (int k = 3; k <= KMAX; k++) {
                 if (k > l) break;
+                const int kq = var == GFQ_VARIANT_KARATSUBA ? GF4_KARATSUBA : q;
                 for (int rows = 256; rows <= 2048; rows *= 2) {
-                    const MMPlan pl = mm_plan(q, k, rows);
+                    const MMPlan pl = mm_plan(kq, k, rows);
                     if (!pl.srb) continue;
-                    if (rows > 256 && pl.TM == mm_plan(q, k, rows / 2).TM) continue;   // same tile
+                    if (rows > 256 && pl.TM == mm_plan(kq, k, rows / 2).TM) continue;   // same tile
                     const int64_t S = (l + k - 1) / k;
                     const int64_t tiles = ((words_of(n) + pl.twd - 1) / pl.twd) * ((m + pl.TM - 1) / pl.TM);
                     for (int split = 1; split <= 16; split *= 2) {
                         if (split > 1 && (S / split < 8 || tiles * split > 2048)) break;
-                        gfq_config c = {k, rows, split, 0};
+                        gfq_config c = {k, rows, split, var};
                         const double ms = time_plain(q, m, l, n, A, B, C, c, st, e0, e1, reps);
                         if (ms > 0 && ops / ms > best_rate) { best_rate = ops / ms; best = c; }
                     }
@@ -216,11 +220,12 @@ int gfq_tune_save(const char *path) {
     FILE *f = fopen(path, "w");
     if (!f) return GFQ_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
-    fprintf(f, "# arch mode q m_class l_class n_class k rows split\n");
+    fprintf(f, "# arch mode q m_class l_class n_class k rows split variant\n");
     for (const auto &kv : g_cache) {
         const Key &k = kv.first;
-        fprintf(f, "%s %d %d %d %d %d %d %d %d\n", std::get<0>(k).c_str(), std::get<1>(k), std::get<2>(k),
-                std::get<3>(k), std::get<4>(k), std::get<5>(k), kv.second.k, kv.second.rows, kv.second.split);
+        fprintf(f, "%s %d %d %d %d %d %d %d %d %d\n", std::get<0>(k).c_str(), std::get<1>(k), std::get<2>(k),
+                std::get<3>(k), std::get<4>(k), std::get<5>(k), kv.second.k, kv.second.rows, kv.second.split,
+                kv.second.variant);
     }
     fclose(f);
     return GFQ_OK;
@@ -236,13 +241,18 @@ int gfq_tune_load(const char *path) {
     while (fgets(line, sizeof line, f)) {
         if (line[0] == '#' || line[0] == '\n') continue;
         char arch[64];
-        int mode, q, bm, bl, bn, k, rows, split;
-        if (sscanf(line, "%63s %d %d %d %d %d %d %d %d", arch, &mode, &q, &bm, &bl, &bn, &k, &rows, &split) != 9) {
+        int mode, q, bm, bl, bn, k, rows, split, variant = GFQ_VARIANT_ROWWISE;
+        const int got = sscanf(line, "%63s %d %d %d %d %d %d %d %d %d", arch, &mode, &q, &bm, &bl, &bn, &k, &rows,
+                               &split, &variant);
+        if (got != 9 && got != 10) {                  // the variant column may be absent
             status = GFQ_EINVAL;
             continue;
         }
-        gfq_config c = {k, rows, split, 0};
-        if (k < 1 || k > KMAX || mm_plan(q, k, rows).srb == 0 || split < 1 || split > 64) {
+        gfq_config c = {k, rows, split, variant};
+        const bool var_ok = variant == GFQ_VARIANT_ROWWISE || (variant == GFQ_VARIANT_KARATSUBA && q == 4);
+        if (k < 1 || k > KMAX || !var_ok ||
+            mm_plan(variant == GFQ_VARIANT_KARATSUBA ? GF4_KARATSUBA : q, k, rows).srb == 0 || split < 1 ||
+            split > 64) {
             status = GFQ_EINVAL;
             continue;
         }

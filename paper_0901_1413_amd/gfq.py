@@ -25,10 +25,10 @@ class GfqError(RuntimeError):
 
 class Config(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int), ("rows", ctypes.c_int), ("split", ctypes.c_int),
-                ("reserved", ctypes.c_int)]
+                ("variant", ctypes.c_int)]
 
     def as_dict(self):
-        return {"k": self.k, "rows": self.rows, "split": self.split}
+        return {"k": self.k, "rows": self.rows, "split": self.split, "variant": self.variant}
 
 
 class Problem(ctypes.Structure):
@@ -174,12 +174,17 @@ def choose_config(q: int, m: int, l: int, n: int) -> dict:
     return c.as_dict()
 
 
-def matmul(q: int, A, B, m: int, l: int, n: int, out=None, k: int = 0, rows: int = 0, split: int = 0):
-    """C = A B on packed device operands; returns the packed product."""
+VARIANT_ROWWISE, VARIANT_KARATSUBA = 0, 1
+
+
+def matmul(q: int, A, B, m: int, l: int, n: int, out=None, k: int = 0, rows: int = 0, split: int = 0,
+           variant=None):
+    """C = A B on packed device operands; returns the packed product.  k, rows, split and
+    variant (GF(4): VARIANT_ROWWISE or VARIANT_KARATSUBA) override the chosen configuration."""
     if out is None:
         out = empty_packed(q, m, n, A.device)
     _bind_stream()
-    if k or rows or split:
+    if k or rows or split or variant is not None:
         c = Config()
         _check(load().gfq_choose_config(q, m, l, n, ctypes.byref(c)), "gfq_choose_config")
         if k:
@@ -188,6 +193,8 @@ def matmul(q: int, A, B, m: int, l: int, n: int, out=None, k: int = 0, rows: int
             c.rows = rows
         if split:
             c.split = split
+        if variant is not None:
+            c.variant = variant
         _check(load().gfq_matmul_config(q, m, l, n, _VP(A.data_ptr()), _VP(B.data_ptr()), _VP(out.data_ptr()),
                                         ctypes.byref(c)), "gfq_matmul_config")
     else:

@@ -81,20 +81,25 @@ def test_choose_config_degenerate_shapes():
 def test_tune_cache_text_roundtrip(tmp_path):
     """The tuning cache file is plain text; loading validates each entry (host logic only)."""
     f = tmp_path / "tune.txt"
-    f.write_text("# arch mode q m_class l_class n_class k rows split\n"
-                 "gfx950 0 3 13 13 13 7 2048 2\n"
-                 "gfx950 1 5 9 10 0 6 256 1\n")
+    f.write_text("# arch mode q m_class l_class n_class k rows split variant\n"
+                 "gfx950 0 3 13 13 13 7 2048 2\n"                # an entry without the variant column
+                 "gfx950 1 5 9 10 0 6 256 1 0\n"
+                 "gfx950 0 4 12 11 12 6 2048 1 1\n")             # GF(4) by Karatsuba
     gfq.tune_clear()
     gfq.tune_load(str(f))
     out = tmp_path / "out.txt"
     gfq.tune_save(str(out))
     lines = [l.split() for l in out.read_text().splitlines() if not l.startswith("#")]
-    assert sorted(lines) == sorted([["gfx950", "0", "3", "13", "13", "13", "7", "2048", "2"],
-                                    ["gfx950", "1", "5", "9", "10", "0", "6", "256", "1"]])
-    bad = tmp_path / "bad.txt"
-    bad.write_text("gfx950 0 3 13 13 13 11 2048 2\n")          # k = 11 is out of range
-    with pytest.raises(gfq.GfqError):
-        gfq.tune_load(str(bad))
+    assert sorted(lines) == sorted([["gfx950", "0", "3", "13", "13", "13", "7", "2048", "2", "0"],
+                                    ["gfx950", "1", "5", "9", "10", "0", "6", "256", "1", "0"],
+                                    ["gfx950", "0", "4", "12", "11", "12", "6", "2048", "1", "1"]])
+    for bad_line in ("gfx950 0 3 13 13 13 11 2048 2\n",       # k = 11 is out of range
+                     "gfx950 0 3 13 13 13 7 2048 2 1\n",      # Karatsuba is for GF(4) only
+                     "gfx950 0 4 13 13 13 7 2048 2 2\n"):     # no such variant
+        bad = tmp_path / "bad.txt"
+        bad.write_text(bad_line)
+        with pytest.raises(gfq.GfqError):
+            gfq.tune_load(str(bad))
     gfq.tune_clear()
     out2 = tmp_path / "empty.txt"
     gfq.tune_save(str(out2))

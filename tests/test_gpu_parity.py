@@ -206,3 +206,43 @@ def test_more_row_tiles_than_one_grid_holds(gfq_gpu):
     rows = np.concatenate([np.arange(0, 64), np.arange(edge - 300, edge + 300), np.arange(m - 64, m)])
     got = C[torch.from_numpy(rows).cuda()].cpu().numpy()
     assert np.array_equal(got, oracle.matmul(q, A[rows], B))
+
+
+# GF(4) by matrix-level Karatsuba over F_2 (the second way to form GF(4) products): every
+# configuration gives the oracle's product, byte for byte in packed form.
+@pytest.mark.parametrize("shape", [(1, 1, 1), (5, 7, 3), (33, 65, 129), (130, 259, 1057), (257, 33, 4099),
+                                   (600, 1000, 70)])
+def test_gf4_karatsuba_shapes(gfq_gpu, shape):
+    m, l, n = shape
+    A, B = inputs.pair(4, m, l, n, cfg=210, idx=m * 7 + n)
+    check(gfq_gpu, 4, A, B, variant=gfq_gpu.VARIANT_KARATSUBA)
+
+
+@pytest.mark.parametrize("k", list(range(1, 11)))
+def test_gf4_karatsuba_every_k(gfq_gpu, k):
+    A, B = inputs.pair(4, 97, 301, 1100, cfg=211, idx=k)
+    check(gfq_gpu, 4, A, B, k=k, variant=gfq_gpu.VARIANT_KARATSUBA)
+
+
+@pytest.mark.parametrize("rows,split", [(256, 1), (512, 1), (1024, 1), (2048, 1), (256, 3), (2048, 7), (1024, 64)])
+def test_gf4_karatsuba_tiles_and_splits(gfq_gpu, rows, split):
+    A, B = inputs.pair(4, 600, 700, 300, cfg=212, idx=rows + split)
+    check(gfq_gpu, 4, A, B, rows=rows, split=split, variant=gfq_gpu.VARIANT_KARATSUBA)
+
+
+def test_gf4_karatsuba_sparse_and_identity(gfq_gpu):
+    A, B = inputs.pair(4, 300, 513, 257, cfg=213, idx=0, density=0.1)
+    check(gfq_gpu, 4, A, B, variant=gfq_gpu.VARIANT_KARATSUBA)
+    eye = np.eye(513, dtype=np.uint8)
+    check(gfq_gpu, 4, eye, B, variant=gfq_gpu.VARIANT_KARATSUBA)
+
+
+def test_variant_validation(gfq_gpu):
+    import torch
+    g = gfq_gpu
+    Ap, Bp = g.pack(3, dev(np.zeros((64, 64), np.uint8))), g.pack(3, dev(np.zeros((64, 64), np.uint8)))
+    for q, var in ((3, g.VARIANT_KARATSUBA), (5, g.VARIANT_KARATSUBA), (4, 2), (4, -1)):
+        with pytest.raises(g.GfqError) as e:
+            g.matmul(q, Ap, Bp, 64, 64, 64, variant=var)
+        assert e.value.status == -1, (q, var)
+    torch.cuda.synchronize()
