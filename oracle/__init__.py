@@ -1,4 +1,4 @@
-"""CPU oracle for C = A B over F_3, F_5, F_7 and GF(4) -- TEST INFRASTRUCTURE ONLY.
+"""CPU oracle for C = A B over F_3, F_5, F_7, GF(4) and GF(8) -- TEST INFRASTRUCTURE ONLY.
 
 Only the tests, the smoke check of the entry module and the CPU-baseline leg of the
 benchmark may import this package.  The GPU library never uses it, and it shares no code
@@ -26,7 +26,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gfq_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
-FIELDS = (3, 4, 5, 7)
+FIELDS = (3, 4, 5, 7, 8)
 
 
 def build(force: bool = True) -> str:
@@ -64,16 +64,17 @@ def max_threads() -> int:
 
 
 def planes(q: int) -> int:
-    """Bit-planes per element: 2 for F_3 (unit, sign) and GF(4) (c0, c1); 3 for F_5, F_7."""
+    """Bit-planes per element: 2 for F_3 (unit, sign) and GF(4) (c0, c1); 3 for F_5, F_7
+    and GF(8) (c0, c1, c2)."""
     if q in (3, 4):
         return 2
-    if q in (5, 7):
+    if q in (5, 7, 8):
         return 3
     raise ValueError(f"unsupported field q={q}")
 
 
 def matmul(q: int, A: np.ndarray, B: np.ndarray, threads: int = 0) -> np.ndarray:
-    """C = A B over F_q (q = 4 means GF(4)); A, B canonical uint8, C canonical uint8."""
+    """C = A B over F_q (q = 4 means GF(4), q = 8 GF(8)); A, B and C canonical uint8."""
     A = np.ascontiguousarray(A, dtype=np.uint8)
     B = np.ascontiguousarray(B, dtype=np.uint8)
     if A.ndim != 2 or B.ndim != 2 or A.shape[1] != B.shape[0]:
@@ -95,6 +96,7 @@ def encode_planes(q: int, X: np.ndarray) -> list:
     unit and the second bit x1 the sign; the integer 2 stands for -1.
     F_5, F_7 (Section 4.2): the binary digits of the representative, plane d = bit d.
     GF(4) (Section 4.3, basis {1, x}): e = c0 + 2 c1, plane d = c_d.
+    GF(8) (Section 4.3, power basis {1, x, x^2}): e = c0 + 2 c1 + 4 c2, plane d = c_d.
     """
     X = np.asarray(X, dtype=np.uint8)
     if q == 3:

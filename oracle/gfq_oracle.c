@@ -1,5 +1,5 @@
 /*
- * gfq_oracle.c -- CPU oracle for dense matrix products over F_3, F_5, F_7 and GF(4).
+ * gfq_oracle.c -- CPU oracle for dense matrix products over F_3, F_5, F_7, GF(4) and GF(8).
  *
  * TEST INFRASTRUCTURE ONLY.  This file exists so that tests, the smoke check and the
  * CPU-baseline leg of the benchmark can check the GPU library against an obviously
@@ -18,6 +18,10 @@
  *     x^2 + x + 1): element e = c0 + 2 c1 stands for c0 + c1 x.  Addition is XOR of the
  *     coefficient bits; the product of (a0 + a1 x)(b0 + b1 x) is
  *     a0 b0 + (a0 b1 + a1 b0) x + a1 b1 x^2 with x^2 replaced by x + 1.
+ *   - GF(8) = F_2[x]/(x^3 + x + 1) (paper, Section 4.3, extension fields viewed as
+ *     polynomials over the base field, reduced by the defining polynomial): element
+ *     e = c0 + 2 c1 + 4 c2 stands for c0 + c1 x + c2 x^2.  The product is the schoolbook
+ *     polynomial product over F_2 (degree up to 4), then x^4 -> x^2 + x and x^3 -> x + 1.
  *
  * Loop order is i, t, j with no blocking: a row of C is built as a linear combination of
  * the rows of B, exactly as the equation reads.  OpenMP splits the rows of C.
@@ -41,12 +45,24 @@ static uint8_t gf4_mul(uint8_t a, uint8_t b)
     return (uint8_t)(c0 | (c1 << 1));
 }
 
+static uint8_t gf8_mul(uint8_t a, uint8_t b)
+{
+    /* schoolbook product over F_2: coefficient k collects a_i b_j with i + j = k */
+    unsigned p[5] = {0, 0, 0, 0, 0};
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) p[i + j] ^= ((a >> i) & 1u) & ((b >> j) & 1u);
+    /* reduce by x^3 + x + 1, highest degree first: x^4 = x^2 + x, x^3 = x + 1 */
+    p[2] ^= p[4]; p[1] ^= p[4];
+    p[1] ^= p[3]; p[0] ^= p[3];
+    return (uint8_t)(p[0] | (p[1] << 1) | (p[2] << 2));
+}
+
 int gfq_oracle_matmul(int q, int64_t m, int64_t l, int64_t n,
                       const uint8_t *A, int64_t lda,
                       const uint8_t *B, int64_t ldb,
                       uint8_t *C, int64_t ldc, int nthreads)
 {
-    if (q != 3 && q != 4 && q != 5 && q != 7) return -1;
+    if (q != 3 && q != 4 && q != 5 && q != 7 && q != 8) return -1;
     if (m < 0 || l < 0 || n < 0 || l >= (1 << 24)) return -2;
     if (m == 0 || n == 0) return 0;
     if (C == NULL || (l > 0 && (A == NULL || B == NULL))) return -3;
@@ -69,12 +85,13 @@ int gfq_oracle_matmul(int q, int64_t m, int64_t l, int64_t n,
             if (acc == NULL) continue;
             memset(acc, 0, (size_t)n * sizeof(int32_t));
             const uint8_t *arow = A + i * lda;
-            if (q == 4) {
+            if (q == 4 || q == 8) {
+                uint8_t (*mul)(uint8_t, uint8_t) = q == 4 ? gf4_mul : gf8_mul;
                 for (int64_t t = 0; t < l; t++) {
                     uint8_t a = arow[t];
                     if (a == 0) continue;
                     const uint8_t *brow = B + t * ldb;
-                    for (int64_t j = 0; j < n; j++) acc[j] ^= gf4_mul(a, brow[j]);
+                    for (int64_t j = 0; j < n; j++) acc[j] ^= mul(a, brow[j]);
                 }
                 for (int64_t j = 0; j < n; j++) C[i * ldc + j] = (uint8_t)acc[j];
             } else {

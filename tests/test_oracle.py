@@ -3,8 +3,11 @@
 * F_p products against numpy's int64 matrix product reduced mod p (a library routine).
 * GF(4) products against the paper's matrix-level Karatsuba identity (Section 4.3) built
   from numpy products over F_2, and against the hand-derived multiplication table.
+* GF(8) products against the paper's six-product trinomial formula (Section 4.3) built
+  from numpy products over F_2 and reduced by x^3 + x + 1, and against a multiplication
+  table derived by hand from the powers of x; field axioms on that table.
 * Exhaustive tiny inputs: every 2x2 by 2x2 pair over F_3, every 1x2 by 2x1 pair over
-  F_5, F_7 and GF(4).
+  F_5, F_7, GF(4) and GF(8).
 * Invariants of matrix multiplication: identity, zero, associativity, both distributive
   laws, transpose, scalars, and the additive-basis split of Section 2.
 * Packed encodings against the paper's printed element codes (Sections 4.1-4.3).
@@ -19,7 +22,7 @@ import oracle
 from paper_0901_1413_amd import inputs
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
-FIELDS = (3, 4, 5, 7)
+FIELDS = (3, 4, 5, 7, 8)
 
 
 def np_fp(q, A, B):
@@ -38,13 +41,51 @@ def gf4_karatsuba(A, B):
     return (c0 + 2 * c1).astype(np.uint8)
 
 
+def gf8_trinomial(A, B):
+    """Six F_2 products by the trinomial formula of Section 4.3, then reduction.
+
+    With a = a0 + a1 x + a2 x^2 (and b alike) the product coefficients are
+    c0 = a0b0, c1 = (a0+a1)(b0+b1) - a0b0 - a1b1, c2 = (a0+a2)(b0+b2) - a0b0 - a2b2 + a1b1,
+    c3 = (a1+a2)(b1+b2) - a1b1 - a2b2, c4 = a2b2; modulo x^3 + x + 1, x^3 = x + 1 and
+    x^4 = x^2 + x fold c3 into c0 and c1 and c4 into c1 and c2."""
+    a = [((A >> d) & 1).astype(np.int64) for d in range(3)]
+    b = [((B >> d) & 1).astype(np.int64) for d in range(3)]
+    mul = lambda X, Y: (X @ Y) % 2
+    P = {(i, i): mul(a[i], b[i]) for i in range(3)}
+    for i, j in ((0, 1), (0, 2), (1, 2)):
+        P[i, j] = mul((a[i] + a[j]) % 2, (b[i] + b[j]) % 2)
+    c0 = P[0, 0]
+    c1 = P[0, 1] - P[0, 0] - P[1, 1]
+    c2 = P[0, 2] - P[0, 0] - P[2, 2] + P[1, 1]
+    c3 = P[1, 2] - P[1, 1] - P[2, 2]
+    c4 = P[2, 2]
+    r0, r1, r2 = (c0 + c3) % 2, (c1 + c3 + c4) % 2, (c2 + c4) % 2
+    return (r0 + 2 * r1 + 4 * r2).astype(np.uint8)
+
+
 def reference(q, A, B):
-    return gf4_karatsuba(A, B) if q == 4 else np_fp(q, A, B)
+    if q == 4:
+        return gf4_karatsuba(A, B)
+    if q == 8:
+        return gf8_trinomial(A, B)
+    return np_fp(q, A, B)
+
+
+def read_table(name):
+    rows = [l.split() for l in open(os.path.join(GOLD, name)) if l.strip() and not l.startswith("#")]
+    return np.array(rows, dtype=np.uint8)
 
 
 def gf4_table():
-    rows = [l.split() for l in open(os.path.join(GOLD, "gf4_mul.txt")) if l.strip() and not l.startswith("#")]
-    return np.array(rows, dtype=np.uint8)
+    return read_table("gf4_mul.txt")
+
+
+def gf8_table():
+    return read_table("gf8_mul.txt")
+
+
+def table_of(q):
+    return gf4_table() if q == 4 else gf8_table()
 
 
 @pytest.mark.parametrize("q", FIELDS)
@@ -74,6 +115,37 @@ def test_gf4_multiplication_table():
             assert gf4_karatsuba(np.array([[a]], np.uint8), np.array([[b]], np.uint8))[0, 0] == T[a, b]
 
 
+def test_gf8_multiplication_table():
+    T = gf8_table()
+    for a in range(8):
+        for b in range(8):
+            A = np.array([[a]], np.uint8)
+            B = np.array([[b]], np.uint8)
+            assert oracle.matmul(8, A, B)[0, 0] == T[a, b], (a, b)
+            assert gf8_trinomial(A, B)[0, 0] == T[a, b], (a, b)
+
+
+@pytest.mark.parametrize("q", [4, 8])
+def test_extension_field_axioms(q):
+    """The golden tables describe a field: commutative, associative, distributive over XOR,
+    1 is the identity and every nonzero element has an inverse (rows are permutations)."""
+    T = table_of(q).astype(int)
+    r = range(q)
+    assert (T == T.T).all()
+    assert list(T[1]) == list(r) and not T[0].any()
+    for a, b, c in itertools.product(r, repeat=3):
+        assert T[T[a, b], c] == T[a, T[b, c]]
+        assert T[a, b ^ c] == T[a, b] ^ T[a, c]
+    for a in range(1, q):
+        assert sorted(T[a, 1:]) == list(range(1, q))
+    # the multiplicative group is cyclic of order q - 1, generated by x (= 2)
+    p, seen = 1, []
+    for _ in range(q - 1):
+        seen.append(p)
+        p = T[p, 2]
+    assert p == 1 and sorted(seen) == list(range(1, q))
+
+
 def test_exhaustive_f3_2x2():
     vals = np.array(list(itertools.product(range(3), repeat=4)), dtype=np.uint8).reshape(-1, 2, 2)
     Aall = np.repeat(vals, len(vals), axis=0)
@@ -90,14 +162,14 @@ def test_exhaustive_f3_2x2():
     assert np.array_equal(got, want)
 
 
-@pytest.mark.parametrize("q", [4, 5, 7])
+@pytest.mark.parametrize("q", [4, 5, 7, 8])
 def test_exhaustive_1x2_by_2x1(q):
-    T = gf4_table()
+    T = table_of(q) if q in (4, 8) else None
     for a0, a1, b0, b1 in itertools.product(range(q), repeat=4):
         A = np.array([[a0, a1]], np.uint8)
         B = np.array([[b0], [b1]], np.uint8)
         got = oracle.matmul(q, A, B)[0, 0]
-        if q == 4:
+        if q in (4, 8):
             want = T[a0, b0] ^ T[a1, b1]
         else:
             want = (a0 * b0 + a1 * b1) % q
@@ -111,7 +183,7 @@ def test_invariants(q):
     B = inputs.matrix(q, l, n, 103, q, 1)
     B2 = inputs.matrix(q, l, n, 103, q, 3)
     D = inputs.matrix(q, n, p, 103, q, 4)
-    add = (lambda X, Y: X ^ Y) if q == 4 else (lambda X, Y: ((X.astype(int) + Y) % q).astype(np.uint8))
+    add = (lambda X, Y: X ^ Y) if q in (4, 8) else (lambda X, Y: ((X.astype(int) + Y) % q).astype(np.uint8))
     I_l = np.eye(l, dtype=np.uint8)
     mm = lambda X, Y: oracle.matmul(q, X, Y)
     assert np.array_equal(mm(A, I_l), A)
@@ -131,7 +203,8 @@ def test_invariants(q):
 def test_additive_basis_split(q):
     """Section 2: a = sum_d alpha_d phi_d(a) gives AB = sum_d alpha_d (Phi_d(A) B) with
     Phi_d(A) the 0/1 matrix of phi_d.  F_3 uses {1, -1} with phi_0 = [a = 1],
-    phi_1 = [a = -1]; F_5, F_7 use {1, 2, 4} with binary digits; GF(4) uses {1, x}."""
+    phi_1 = [a = -1]; F_5, F_7 use {1, 2, 4} with binary digits; GF(4) uses {1, x} and
+    GF(8) {1, x, x^2} (the integers 1, 2, 4 encode those elements)."""
     A, B = inputs.pair(q, 23, 61, 19, cfg=104)
     if q == 3:
         alphas, phis = [1, 2], [(A == 1), (A == 2)]
@@ -143,7 +216,7 @@ def test_additive_basis_split(q):
     for alpha, phi in zip(alphas, phis):
         part = oracle.matmul(q, phi.astype(np.uint8), B)
         scaled = oracle.matmul(q, part, (alpha * np.eye(19)).astype(np.uint8))   # part * alpha
-        acc = (acc ^ scaled) if q == 4 else ((acc.astype(int) + scaled) % q).astype(np.uint8)
+        acc = (acc ^ scaled) if q in (4, 8) else ((acc.astype(int) + scaled) % q).astype(np.uint8)
     assert np.array_equal(acc, oracle.matmul(q, A, B))
 
 
