@@ -37,16 +37,17 @@ M = L = N = 8192
 FIELDS = (3, 5)
 PEAK_VALU_OPS = 256 * 64 * 2.4e9          # 32-bit VALU lane-operations per second
 PEAK_HBM = 8.0e12
-SECTIONS = ("c1", "c2_k", "mfma", "c3", "c4", "c5")
+SECTIONS = ("c1", "c2_k", "mfma", "c3", "gf8", "c4", "c5")
 
 # Per-unit operation counts of the method on gfx950 (three-input bitwise instructions).
 # A unit is (row of C, slab of k rows of B, 32-column word).  Accumulate: the slab's D
 # alpha-scaled table rows into a carry-save accumulator, one full adder (2 instructions)
-# per addend bit (F_3 4 bits, F_7 9; F_5 9 bits plus one half adder; GF(4) 3 XORs).
-# Table build: one field addition per table entry and word.  Finish: per output word.
-C_ACC = {3: 8, 4: 3, 5: 20, 7: 18}
-C_ADD = {3: 6, 4: 2, 5: 13, 7: 11}
-C_FIN = {3: 8, 4: 0, 5: 30, 7: 15}
+# per addend bit (F_3 4 bits, F_7 9; F_5 9 bits plus one half adder; GF(4) 3 XORs; GF(8)
+# 6 XORs).  Table build: one field addition per table entry and word.  Finish: per output
+# word.
+C_ACC = {3: 8, 4: 3, 5: 20, 7: 18, 8: 6}
+C_ADD = {3: 6, 4: 2, 5: 13, 7: 11, 8: 3}
+C_FIN = {3: 8, 4: 0, 5: 30, 7: 15, 8: 0}
 # The paper's two-input operation counts (Sections 4.1 and 4.2) for the same units.
 C_ACC_PAPER = {3: 12, 4: 4, 5: 60, 7: 51}
 C_ADD_PAPER = {3: 6, 4: 2, 5: 20, 7: 17}
@@ -335,7 +336,20 @@ def section_c2_k(ctx, data, reps=3):
 def int8_product(torch, q, A8, B8):
     """C = A B over F_q from int8 GEMMs with int32 accumulation (exact while l (q-1)^2 <
     2^31): one GEMM and a reduction mod p for F_p; for GF(4) = F_2[x]/(x^2+x+1) the
-    coefficient planes by Karatsuba, three GEMMs reduced mod 2."""
+    coefficient planes by Karatsuba, three GEMMs reduced mod 2; for GF(8) =
+    F_2[x]/(x^3+x+1) the trinomial formula of Section 4.3, six GEMMs reduced mod 2."""
+    if q == 8:
+        a = [(A8 >> d) & 1 for d in range(3)]
+        b = [(B8 >> d) & 1 for d in range(3)]
+        p00, p11, p22 = (torch._int_mm(a[i], b[i]) for i in range(3))
+        p01 = torch._int_mm(a[0] ^ a[1], b[0] ^ b[1])
+        p02 = torch._int_mm(a[0] ^ a[2], b[0] ^ b[2])
+        p12 = torch._int_mm(a[1] ^ a[2], b[1] ^ b[2])
+        # product coefficients c0..c4 mod 2, then x^3 = x + 1 and x^4 = x^2 + x
+        c0, c1, c2 = p00, p01 - p00 - p11, p02 - p00 - p22 + p11
+        c3, c4 = p12 - p11 - p22, p22
+        r0, r1, r2 = (c0 + c3) & 1, (c1 + c3 + c4) & 1, (c2 + c4) & 1
+        return (r0 + 2 * r1 + 4 * r2).to(torch.uint8)
     if q != 4:
         return torch.remainder(torch._int_mm(A8, B8), q).to(torch.uint8)
     a0, a1 = A8 & 1, A8 >> 1
@@ -466,6 +480,56 @@ def section_c3(ctx, reps=3, sample_rows=32):
                 res[name]["karatsuba_variant"] = kara
             del Ad, Bd, Ap, Bp, Cp, Cd
     return {"workload": "A 16384x2048, B 2048x16384; uniform and 10% density", **res}
+
+
+# ------------------------------------------------------------------------------------
+# gf8: the cubic extension GF(8) = F_2[x]/(x^3 + x + 1), row-wise with basis {1, x, x^2}
+# ------------------------------------------------------------------------------------
+
+def section_gf8(ctx, reps=3, sample_rows=32):
+    import numpy as np
+    torch, gfq, inputs = ctx.torch, ctx.gfq, ctx.inputs
+    q = 8
+    res = {}
+    for (m, l, n), density in (((16384, 2048, 16384), 1.0), ((16384, 2048, 16384), 0.1), ((M, L, N), 1.0)):
+        A, B = inputs.pair(q, m, l, n, cfg=6, idx=m + l, density=density)
+        Ad, Bd = ctx.up(A), ctx.up(B)
+        Ap, Bp, Cp = gfq.pack(q, Ad), gfq.pack(q, Bd), gfq.empty_packed(q, m, n)
+        gfq.matmul(q, Ap, Bp, m, l, n, out=Cp)
+        Cd = gfq.unpack(q, Cp, m, n)
+        torch.cuda.synchronize()
+        gfq.set_timing(True)
+        gfq.timing_read()
+        for _ in range(reps):
+            gfq.matmul(q, Ap, Bp, m, l, n, out=Cp)
+        torch.cuda.synchronize()
+        t = gfq.timing_read()
+        gfq.set_timing(False)
+        pm = t["product_ms"] / t["product_launches"]
+        rm = (t["reduce_ms"] / t["reduce_launches"]) if t["reduce_launches"] else 0.0
+        cfg = gfq.choose_config(q, m, l, n)
+        rows = np.sort(inputs.rng(6, m, 3).choice(m, size=sample_rows, replace=False))
+        got = Cd[torch.from_numpy(rows).to(ctx.dev)].cpu().numpy()
+        ok = bool(np.array_equal(got, ctx.oracle.matmul(q, A[rows], B)))
+        ops = algorithmic_ops(q, m, l, n, cfg["k"], C_ACC, C_ADD)
+        A8, B8 = Ad.view(torch.int8), Bd.view(torch.int8)
+        same8 = bool(torch.equal(int8_product(torch, q, A8, B8), Cd))
+        ev = ctx.events(2)
+        ev[0].record()
+        for _ in range(reps):
+            int8_product(torch, q, A8, B8)
+        ev[1].record()
+        torch.cuda.synchronize()
+        mfma_ms = ev[0].elapsed_time(ev[1]) / reps
+        name = f"{m}x{l}x{n}" + ("" if density == 1.0 else "_density0.1")
+        res[name] = {"product_ms": round(pm, 4), "partial_sum_ms": round(rm, 4),
+                     "field_ops_per_s_product": 2.0 * m * l * n / ((pm + rm) * 1e-3),
+                     "alu_frac": round(ops / (pm * 1e-3) / PEAK_VALU_OPS, 4), "config": cfg,
+                     "sampled_rows_bit_exact": ok, "sampled_rows": sample_rows,
+                     "int8_mfma_comparison_ms": round(mfma_ms, 4), "int8_mfma_equals": same8}
+        del Ad, Bd, Ap, Bp, Cp, Cd, A8, B8
+        torch.cuda.empty_cache()
+    return {"workload": "GF(8), A m x l, B l x n uniform (and 10% density)", **res}
 
 
 # ------------------------------------------------------------------------------------
@@ -718,6 +782,10 @@ def main():
     if "c3" in sections:
         log("c3")
         res["c3"] = section_c3(ctx)
+        torch.cuda.empty_cache()
+    if "gf8" in sections:
+        log("gf8")
+        res["gf8"] = section_gf8(ctx)
         torch.cuda.empty_cache()
     if "c4" in sections:
         log("c4")

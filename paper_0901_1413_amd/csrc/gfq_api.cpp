@@ -21,8 +21,6 @@ thread_local hipStream_t t_stream = nullptr;
 thread_local char t_hip_error[256] = "";
 
 
-bool valid_field(int q) { return q == 3 || q == 4 || q == 5 || q == 7; }
-
 // Optional per-launch timing (gfq_set_timing).
 struct TimedLaunch { hipEvent_t e0, e1; int kind; };   // kind 0: product, 1: partial sum
 thread_local bool t_timing = false;

@@ -46,6 +46,7 @@ const void *batched_kernel(int q, int R) {
     case 3: return R == 2 ? list_kernel_ptr<3, 2>() : list_kernel_ptr<3, 8>();
     case 4: return R == 2 ? list_kernel_ptr<4, 2>() : list_kernel_ptr<4, 8>();
     case 5: return list_kernel_ptr<5, 2>();      // four rows per lane would spill here
+    case 8: return R == 2 ? list_kernel_ptr<8, 2>() : list_kernel_ptr<8, 8>();
     default: return R == 2 ? list_kernel_ptr<7, 2>() : list_kernel_ptr<7, 4>();
     }
 }

@@ -18,7 +18,7 @@ using namespace gfq;
 namespace {
 
 int group_index(int q, int R) {
-    const int qi = q == 3 ? 0 : (q == 4 ? 1 : (q == 5 ? 2 : 3));
+    const int qi = q == 3 ? 0 : (q == 4 ? 1 : (q == 5 ? 2 : (q == 7 ? 3 : 4)));
     return qi * 2 + (R == 2 ? 0 : 1);
 }
 
@@ -28,7 +28,7 @@ int group_index(int q, int R) {
 // ordered longest first within a group.
 void gfq::plan_batch(int count, const gfq_problem *problems, const gfq_config *cfgs, BatchProd *prods,
                      std::vector<BatchGroup> *groups, size_t *nitems) {
-    std::vector<BatchGroup> g(8);
+    std::vector<BatchGroup> g(10);
     for (int i = 0; i < count; i++) {
         const gfq_problem &p = problems[i];
         BatchProd &bp = prods[i];
@@ -100,7 +100,7 @@ size_t gfq::batch_tiles_bound(int64_t m, int64_t n) {
 }
 
 hipError_t gfq::set_batched_lds_limits() {
-    for (int q : {3, 4, 5, 7})
+    for (int q : {3, 4, 5, 7, 8})
         for (int R : {2, max_rows_per_lane_batch(q)}) {
             if (q == 5 && R != 2) continue;       // F_5 batches use two rows per lane only
             const size_t lds = mm_lds_bytes(q, planes_of(q) == 2 ? 7 : 6, 256, NT_MM / 4 * R, nullptr);

@@ -4,7 +4,9 @@
 //   storage     the packed format of the C ABI (Section 4 encodings), P planes;
 //   table       how table entries (sums of rows of B) are held in LDS, P planes;
 //   accumulator how a lane keeps its running row of C, PA planes (carry-save pairs of
-//               residues modulo 2^NB - 1, see gfq_field.h).
+//               residues modulo 2^NB - 1 for the prime fields, see gfq_field.h).
+// SPLIT_PREFIX: table chunk prefixes are summed one slab ahead by a quarter of the threads
+// (fields whose table addition is long) rather than by every build thread for itself.
 // Every trait works on one 32-bit word per plane (32 columns); the kernels apply it to
 // the four words of a 128-bit LDS read.
 #pragma once
@@ -23,6 +25,7 @@ template <int Q> struct FT;
 // receives T[phi_0] and -T[phi_1] (the complement) per slab.
 template <> struct FT<3> {
     static constexpr int P = 2, PT = 2, D = 2, GP = 2, PA = 4;
+    static constexpr bool SPLIT_PREFIX = false;
     static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0] ^ x[1]; f[1] = x[1]; }
     __device__ static void to_table(const u32 *x, u32 *t) { f3_to_bin(x[0], x[1], t); }
@@ -50,6 +53,7 @@ template <> struct FT<3> {
 // planes, so alpha_d T[phi_d] costs nothing; the accumulator is a carry-save pair mod 7.
 template <> struct FT<7> {
     static constexpr int P = 3, PT = 3, D = 3, GP = 3, PA = 6;
+    static constexpr bool SPLIT_PREFIX = true;
     static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; f[2] = x[2]; }
     __device__ static void to_table(const u32 *x, u32 *t) { t[0] = x[0]; t[1] = x[1]; t[2] = x[2]; }
@@ -87,6 +91,7 @@ template <> struct FT<7> {
 // scaled rows enter it together (f5_csa_slab).
 template <> struct FT<5> {
     static constexpr int P = 3, PT = 3, D = 3, GP = 3, PA = 8;
+    static constexpr bool SPLIT_PREFIX = true;
     static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; f[2] = x[2]; }
     __device__ static void to_table(const u32 *x, u32 *t) { t[0] = x[0]; t[1] = x[1]; t[2] = x[2]; }
@@ -119,6 +124,7 @@ template <> struct FT<5> {
 // T[phi_0] + x T[phi_1]; with x (c0 + c1 x) = c1 + (c0 + c1) x that is two XOR planes.
 template <> struct FT<4> {
     static constexpr int P = 2, PT = 2, D = 2, GP = 2, PA = 2;
+    static constexpr bool SPLIT_PREFIX = false;
     static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; }
     __device__ static void to_table(const u32 *x, u32 *t) { t[0] = x[0]; t[1] = x[1]; }
@@ -141,6 +147,7 @@ template <> struct FT<4> {
 // Same packed operands and product as FT<4>; selected by the configuration.
 template <> struct FT<GF4_KARATSUBA> {
     static constexpr int P = 2, PT = 3, D = 3, GP = 1, PA = 2;
+    static constexpr bool SPLIT_PREFIX = false;
     static constexpr int gplane(int d, int) { return d; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; f[2] = x[0] ^ x[1]; }
     __device__ static void to_table(const u32 *x, u32 *t) { t[0] = x[0]; t[1] = x[1]; t[2] = x[0] ^ x[1]; }
@@ -155,6 +162,26 @@ template <> struct FT<GF4_KARATSUBA> {
     }
     __device__ static void finish(const u32 *c, u32 *out) { out[0] = c[0]; out[1] = c[1]; }
     __device__ static void sadd(const u32 *a, const u32 *b, u32 *r) { r[0] = a[0] ^ b[0]; r[1] = a[1] ^ b[1]; }
+    __device__ static void scanon(u32 *) {}
+};
+
+// GF(8) (Section 4.3, the power basis of the extension times the basis {1} of F_2).
+// Basis {1, x, x^2}, phi_d = c_d.  Per slab the row receives T[phi_0] + x T[phi_1] +
+// x^2 T[phi_2] (g8_acc, six operations for three planes).
+template <> struct FT<8> {
+    static constexpr int P = 3, PT = 3, D = 3, GP = 3, PA = 3;
+    static constexpr bool SPLIT_PREFIX = false;
+    static constexpr int gplane(int, int p) { return p; }
+    __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; f[2] = x[2]; }
+    __device__ static void to_table(const u32 *x, u32 *t) { t[0] = x[0]; t[1] = x[1]; t[2] = x[2]; }
+    __device__ static void tadd(const u32 *a, const u32 *b, u32 *r) {
+        r[0] = a[0] ^ b[0]; r[1] = a[1] ^ b[1]; r[2] = a[2] ^ b[2];
+    }
+    __device__ static void tsub(const u32 *a, const u32 *b, u32 *r) { tadd(a, b, r); }
+    __device__ static void acc_init(u32 *c, int) { c[0] = c[1] = c[2] = 0u; }
+    __device__ static void accumulate(u32 *c, const u32 (*t)[P]) { g8_acc(c, t[0], t[1], t[2]); }
+    __device__ static void finish(const u32 *c, u32 *out) { out[0] = c[0]; out[1] = c[1]; out[2] = c[2]; }
+    __device__ static void sadd(const u32 *a, const u32 *b, u32 *r) { tadd(a, b, r); }
     __device__ static void scanon(u32 *) {}
 };
 

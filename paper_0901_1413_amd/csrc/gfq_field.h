@@ -154,6 +154,25 @@ struct G4v { u32 c0, c1; };
 GFQ_HD G4v g4_add(G4v a, G4v b) { G4v r; r.c0 = a.c0 ^ b.c0; r.c1 = a.c1 ^ b.c1; return r; }
 GFQ_HD G4v g4_mulx(G4v a) { G4v r; r.c0 = a.c1; r.c1 = a.c0 ^ a.c1; return r; }
 
+// ---------------------------------------------------------------------------------------
+// GF(8) = F_2[x]/(x^3 + x + 1) with the power basis {1, x, x^2} (Section 4.3): planes
+// (c0, c1, c2) of c0 + c1 x + c2 x^2.  Addition is XOR per plane.  With x^3 = x + 1,
+// multiplying by x maps (c0, c1, c2) to (c2, c0 + c2, c1) and by x^2 to
+// (c1, c1 + c2, c0 + c2).
+// ---------------------------------------------------------------------------------------
+struct G8v { u32 c0, c1, c2; };
+GFQ_HD G8v g8_add(G8v a, G8v b) { G8v r; r.c0 = a.c0 ^ b.c0; r.c1 = a.c1 ^ b.c1; r.c2 = a.c2 ^ b.c2; return r; }
+GFQ_HD G8v g8_mulx(G8v a) { G8v r; r.c0 = a.c2; r.c1 = a.c0 ^ a.c2; r.c2 = a.c1; return r; }
+GFQ_HD G8v g8_mulx2(G8v a) { G8v r; r.c0 = a.c1; r.c1 = a.c1 ^ a.c2; r.c2 = a.c0 ^ a.c2; return r; }
+// c += t + x u + x^2 v in six operations: the x^2 v and x u terms meet in plane 0 as u2 + v1,
+// which plane 1 reuses.
+GFQ_HD void g8_acc(u32 *c, const u32 *t, const u32 *u, const u32 *v) {
+    const u32 s = u[2] ^ v[1];
+    c[0] = xor3(c[0], t[0], s);
+    c[1] = xor3(xor3(c[1], t[1], u[0]), s, v[2]);
+    c[2] = xor3(xor3(c[2], t[2], u[1]), v[0], v[2]);
+}
+
 
 // ---------------------------------------------------------------------------------------
 // Working representations used inside the product kernel (not storage formats).

@@ -31,13 +31,18 @@ struct MMArgs {
 // field is q = 4, chosen by gfq_config.variant).
 constexpr int GF4_KARATSUBA = 40;
 
+// fields of the C ABI: F_3, F_5, F_7, GF(4) (q = 4) and GF(8) (q = 8)
+inline bool valid_field(int q) { return q == 3 || q == 4 || q == 5 || q == 7 || q == 8; }
+
 // planes per packed row; planes per table entry; table rows gathered per slab
 inline int planes_of(int q) { return (q == 3 || q == 4 || q == GF4_KARATSUBA) ? 2 : 3; }
 inline int table_planes(int q) { return q == GF4_KARATSUBA ? 3 : planes_of(q); }
 inline int gathers_of(int q) { return (q == 3 || q == 4) ? 2 : 3; }
+inline bool split_prefix(int q) { return q == 5 || q == 7; }   // FT<q>::SPLIT_PREFIX
 inline int words_of(int64_t cols) { return (int)(((cols + 127) / 128) * 4); }
 // Rows of C per lane: bounded by the accumulator registers (8 planes per word for F_5, 6
-// for F_7, 4 for F_3, 2 for GF(4)).  The work-list kernels of batches use at most 8.
+// for F_7, 4 for F_3, 3 for GF(8), 2 for GF(4)).  The work-list kernels of batches use at
+// most 8.
 inline int max_rows_per_lane(int q) { return q == 5 || q == 7 ? 4 : (q == 4 || q == GF4_KARATSUBA ? 16 : 8); }
 inline int max_rows_per_lane_batch(int q) { return q == 5 ? 2 : (q == 7 ? 4 : 8); }
 
@@ -67,9 +72,9 @@ inline size_t mm_lds_bytes(int q, int k, int srb, int TM, u32 *tb1_out) {
     u32 tb1 = 16;
     while (tb1 < tbytes) tb1 <<= 1;
     if (tb1_out) *tb1_out = tb1;
-    // two tables, B staging [3][KMAX][P][TWD], chunk prefixes [2][NT/TWD][P][TWD] (three
-    // planes only), table offsets [3][TM][(D+1)/2]
-    return (size_t)tb1 + tbytes + 3 * KMAX * P * twd_of(srb) * 4 + (P == 3 ? 2 * (size_t)NT_MM * PT * 4 : 0) +
+    // two tables, B staging [3][KMAX][P][TWD], chunk prefixes [2][NT/TWD][PT][TWD] (F_5,
+    // F_7 only), table offsets [3][TM][(D+1)/2]
+    return (size_t)tb1 + tbytes + 3 * KMAX * P * twd_of(srb) * 4 + (split_prefix(q) ? 2 * (size_t)NT_MM * PT * 4 : 0) +
            3 * (size_t)TM * ((D + 1) / 2) * 4;
 }
 
@@ -87,6 +92,7 @@ inline MMPlan mm_plan(int q, int k, int rowsTile) {
     r = r <= 2 ? 2 : (r <= 4 ? 4 : (r <= 8 ? 8 : 16));
     if (r > max_rows_per_lane(q)) r = max_rows_per_lane(q);
     if (r > 8 && p.twd < 16) r = 8;              // narrow tiles: 16 rows per lane would spill
+    if (r > 4 && p.twd < 16 && q == 8) r = 4;    // ... and for GF(8) eight would
     for (; r >= 2; r /= 2) {
         p.R = r;
         p.TM = NT_MM / lpr * r;

@@ -17,7 +17,7 @@
 // Pipeline per workgroup (one barrier per slab).  Iteration s:
 //   stage   write slab s+3's rows of B (loaded into registers one iteration earlier) and
 //           the phi_d table offsets of every row of the tile for slab s+2 into LDS;
-//   prefix  (three-plane fields) the chunk prefixes of slab s+2's table;
+//   prefix  (F_5, F_7) the chunk prefixes of slab s+2's table;
 //   build   the table of slab s+1 into the idle table buffer, in Gray-code order;
 //   gather  for every row, D table rows of slab s, alpha_d-scaled into the accumulator;
 //   barrier.
@@ -69,8 +69,8 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
     const u32 tbytes = (u32)(1u << k) * PT * SRB;
     const u32 TB1 = a.tb1;                       // power of two >= tbytes, <= 65536
     u32 *Bst = reinterpret_cast<u32 *>(smem + TB1 + tbytes);   // [3][KMAX][P][TWD]
-    u32 *PB = Bst + 3 * KMAX * P * TWD;                         // [2][NCH][P][TWD] (P = 3 only)
-    u32 *Ib = PB + (P == 3 ? 2 * NCH * P * TWD : 0);            // [3][TM][IBW]
+    u32 *PB = Bst + 3 * KMAX * P * TWD;                         // [2][NCH][PT][TWD] (split prefixes)
+    u32 *Ib = PB + (F::SPLIT_PREFIX ? 2 * NCH * PT * TWD : 0);  // [3][TM][IBW]
 
     const int tid = threadIdx.x;
     const int colw0 = bx * TWD;
@@ -182,10 +182,11 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
     // subtracting it when it switches off.  For three-plane fields the prefixes come from
     // a stage one slab earlier (prefix): NCH/4 threads per word each take four consecutive
     // chunks (a masked sum over the bits above the lowest two, then a Gray walk over those
-    // two) and leave them in a small buffer.  For two planes, where a table addition costs
-    // only 6 (F_3) or 2 (GF(4)) instructions, each thread sums its own prefix (a masked sum).
-    // The rows a stage needs are read from LDS in one batch before its chain of additions. ----
-    constexpr bool SPLIT_PREFIX = P == 3 && PT == 3;
+    // two) and leave them in a small buffer.  Where a table addition is short (F_3: 6
+    // instructions; GF(4), GF(8): one XOR per plane) each thread sums its own prefix (a
+    // masked sum).  The rows a stage needs are read from LDS in one batch before its chain
+    // of additions. ----
+    constexpr bool SPLIT_PREFIX = F::SPLIT_PREFIX;
     constexpr int GMAX = KMAX > LOG_NCH ? KMAX - LOG_NCH : 0;   // longest walk: 2^GMAX entries
     constexpr int PFW = NCH / 4;                                // prefix threads per word
     constexpr int PFB = LOG_NCH > 2 ? LOG_NCH - 2 : 0;         // masked bits per prefix thread

@@ -67,7 +67,7 @@ template <int Q> __device__ __forceinline__ u32 encode_spread(u32 v) {
         return (v != 0u ? 1u : 0u) | (v == 2u ? 1u << 8 : 0u);
     }
     if (Q == 4) return (v & 1u) | ((v >> 1) & 1u) << 8;
-    v %= (u32)Q;                                  // binary digits (F_5, F_7)
+    if (Q != 8) v %= (u32)Q;                      // binary digits (F_5, F_7; GF(8): c0, c1, c2)
     return (v & 1u) | ((v >> 1) & 1u) << 8 | ((v >> 2) & 1u) << 16;
 }
 
@@ -146,7 +146,7 @@ __device__ __forceinline__ void unpack_unit(const u32 *src, uint8_t *dst, int64_
         u32 v;
         if (Q == 3) {
             v = (code & 0x01010101u) + ((code >> 1) & 0x01010101u);            // unit + sign
-        } else if (Q == 4) {
+        } else if (Q == 4 || Q == 8) {
             v = code;
         } else if (Q == 7) {
             const u32 is7 = code & (code >> 1) & (code >> 2) & 0x01010101u;    // 7 = 0
@@ -191,6 +191,7 @@ __device__ __forceinline__ u32 encode_spread_q(int q, u32 v) {
     case 3: return encode_spread<3>(v);
     case 4: return encode_spread<4>(v);
     case 5: return encode_spread<5>(v);
+    case 8: return encode_spread<8>(v);
     default: return encode_spread<7>(v);
     }
 }
@@ -219,6 +220,7 @@ __global__ __launch_bounds__(256) void conv_list_kernel(const ConvJob *jobs, int
         case 3: pack_unit<3>(src, j.ld, dst, j.cols, j.W, j.aligned, enc, row, w); break;
         case 4: pack_unit<4>(src, j.ld, dst, j.cols, j.W, j.aligned, enc, row, w); break;
         case 5: pack_unit<5>(src, j.ld, dst, j.cols, j.W, j.aligned, enc, row, w); break;
+        case 8: pack_unit<8>(src, j.ld, dst, j.cols, j.W, j.aligned, enc, row, w); break;
         default: pack_unit<7>(src, j.ld, dst, j.cols, j.W, j.aligned, enc, row, w); break;
         }
     } else {
@@ -228,6 +230,7 @@ __global__ __launch_bounds__(256) void conv_list_kernel(const ConvJob *jobs, int
         case 3: unpack_unit<3>(src, dst, j.ld, j.cols, j.W, j.aligned, row, w); break;
         case 4: unpack_unit<4>(src, dst, j.ld, j.cols, j.W, j.aligned, row, w); break;
         case 5: unpack_unit<5>(src, dst, j.ld, j.cols, j.W, j.aligned, row, w); break;
+        case 8: unpack_unit<8>(src, dst, j.ld, j.cols, j.W, j.aligned, row, w); break;
         default: unpack_unit<7>(src, dst, j.ld, j.cols, j.W, j.aligned, row, w); break;
         }
     }
@@ -281,6 +284,7 @@ hipError_t launch_reduce(int q, const u32 *part, u32 *C, int m, int n, int Wn, i
     case 3: hipLaunchKernelGGL(reduce_partials_kernel<3>, grid, dim3(256), 0, st, part, C, m, n, Wn, splits, stride); break;
     case 4: hipLaunchKernelGGL(reduce_partials_kernel<4>, grid, dim3(256), 0, st, part, C, m, n, Wn, splits, stride); break;
     case 5: hipLaunchKernelGGL(reduce_partials_kernel<5>, grid, dim3(256), 0, st, part, C, m, n, Wn, splits, stride); break;
+    case 8: hipLaunchKernelGGL(reduce_partials_kernel<8>, grid, dim3(256), 0, st, part, C, m, n, Wn, splits, stride); break;
     default: hipLaunchKernelGGL(reduce_partials_kernel<7>, grid, dim3(256), 0, st, part, C, m, n, Wn, splits, stride); break;
     }
     return hipGetLastError();
@@ -300,6 +304,7 @@ hipError_t launch_pack(int q, const uint8_t *src, int64_t ld, u32 *dst, int rows
     case 3: hipLaunchKernelGGL(pack_kernel<3>, grid, dim3(256), 0, st, src, ld, dst, rows, cols, W, aligned); break;
     case 4: hipLaunchKernelGGL(pack_kernel<4>, grid, dim3(256), 0, st, src, ld, dst, rows, cols, W, aligned); break;
     case 5: hipLaunchKernelGGL(pack_kernel<5>, grid, dim3(256), 0, st, src, ld, dst, rows, cols, W, aligned); break;
+    case 8: hipLaunchKernelGGL(pack_kernel<8>, grid, dim3(256), 0, st, src, ld, dst, rows, cols, W, aligned); break;
     default: hipLaunchKernelGGL(pack_kernel<7>, grid, dim3(256), 0, st, src, ld, dst, rows, cols, W, aligned); break;
     }
     return hipGetLastError();
@@ -312,6 +317,7 @@ hipError_t launch_unpack(int q, const u32 *src, uint8_t *dst, int64_t ld, int ro
     case 3: hipLaunchKernelGGL(unpack_kernel<3>, grid, dim3(256), 0, st, src, dst, ld, rows, cols, W, aligned); break;
     case 4: hipLaunchKernelGGL(unpack_kernel<4>, grid, dim3(256), 0, st, src, dst, ld, rows, cols, W, aligned); break;
     case 5: hipLaunchKernelGGL(unpack_kernel<5>, grid, dim3(256), 0, st, src, dst, ld, rows, cols, W, aligned); break;
+    case 8: hipLaunchKernelGGL(unpack_kernel<8>, grid, dim3(256), 0, st, src, dst, ld, rows, cols, W, aligned); break;
     default: hipLaunchKernelGGL(unpack_kernel<7>, grid, dim3(256), 0, st, src, dst, ld, rows, cols, W, aligned); break;
     }
     return hipGetLastError();

@@ -398,7 +398,7 @@ int gfq_server_submit(gfq_server *s, const gfq_request *reqs, int count) {
     const double t = s->now();
     for (int i = 0; i < count; i++) {
         const gfq_request &r = reqs[i];
-        if (r.q != 3 && r.q != 4 && r.q != 5 && r.q != 7) return GFQ_EFIELD;
+        if (!valid_field(r.q)) return GFQ_EFIELD;
         if (r.m < 0 || r.l < 0 || r.n < 0 || r.m > kMaxSide || r.l > kMaxSide || r.n > kMaxSide) return GFQ_EDIM;
         if (r.flags & ~(GFQ_REQ_A_PACKED | GFQ_REQ_B_PACKED | GFQ_REQ_C_PACKED)) return GFQ_EINVAL;
         const bool pa = r.flags & GFQ_REQ_A_PACKED, pb = r.flags & GFQ_REQ_B_PACKED, pc = r.flags & GFQ_REQ_C_PACKED;

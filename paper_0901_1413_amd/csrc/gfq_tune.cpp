@@ -120,7 +120,7 @@ int gfq_tune_lookup(int q, int64_t m, int64_t l, int64_t n, int mode, gfq_config
 
 int gfq_tune(int q, int64_t m, int64_t l, int64_t n, int mode, gfq_config *out) {
     if (!out) return GFQ_ENULL;
-    if (q != 3 && q != 4 && q != 5 && q != 7) return GFQ_EFIELD;
+    if (!valid_field(q)) return GFQ_EFIELD;
     if (m <= 0 || l <= 0 || n <= 0 || m > (1 << 16) || l > (1 << 16) || n > (1 << 16)) return GFQ_EDIM;
     if (mode != 0 && mode != GFQ_TUNE_BATCH) return GFQ_EINVAL;
     std::string arch;

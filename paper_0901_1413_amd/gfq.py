@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgfq.so")
 
 GFQ_OK = 0
-FIELDS = (3, 4, 5, 7)
+FIELDS = (3, 4, 5, 7, 8)
 
 
 class GfqError(RuntimeError):

@@ -25,7 +25,7 @@ def mid(b: int) -> int:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=os.path.join(HERE, "tuning", "gfx950.txt"))
-    ap.add_argument("--fields", default="3,4,5,7")
+    ap.add_argument("--fields", default="3,4,5,7,8")
     ap.add_argument("--batch-classes", default="6,7,8,9,10,11,12", help="log2 classes of m and l for batch mode")
     ap.add_argument("--plain", action="store_true", help="also tune the plain single-product shapes")
     args = ap.parse_args()

@@ -28,6 +28,21 @@ int main() {
         G4v s = g4_add(x, y), mx = g4_mulx(x);
         printf("g4 %u %u add %u mulx %u\n", a, b, bit(s.c0) | bit(s.c1) << 1, bit(mx.c0) | bit(mx.c1) << 1);
     }
+    // GF(8): add, multiply by x and x^2, and the accumulate step c + t + x u + x^2 v
+    for (unsigned a = 0; a < 8; a++) for (unsigned b = 0; b < 8; b++) {
+        G8v x; x.c0 = a & 1; x.c1 = (a >> 1) & 1; x.c2 = a >> 2;
+        G8v y; y.c0 = b & 1; y.c1 = (b >> 1) & 1; y.c2 = b >> 2;
+        G8v s = g8_add(x, y), m1 = g8_mulx(x), m2 = g8_mulx2(x);
+        printf("g8 %u %u add %u mulx %u mulx2 %u\n", a, b, bit(s.c0) | bit(s.c1) << 1 | bit(s.c2) << 2,
+               bit(m1.c0) | bit(m1.c1) << 1 | bit(m1.c2) << 2, bit(m2.c0) | bit(m2.c1) << 1 | bit(m2.c2) << 2);
+    }
+    for (unsigned c = 0; c < 8; c++) for (unsigned t = 0; t < 8; t++)
+        for (unsigned u = 0; u < 8; u++) for (unsigned v = 0; v < 8; v++) {
+            u32 cc[3], tt[3], uu[3], vv[3];
+            for (int i = 0; i < 3; i++) { cc[i] = (c >> i) & 1; tt[i] = (t >> i) & 1; uu[i] = (u >> i) & 1; vv[i] = (v >> i) & 1; }
+            g8_acc(cc, tt, uu, vv);
+            printf("g8acc %u %u %u %u %u\n", c, t, u, v, bit(cc[0]) | bit(cc[1]) << 1 | bit(cc[2]) << 2);
+        }
     // binary mod 3 working form
     for (unsigned a = 0; a < 4; a++) for (unsigned b = 0; b < 4; b++) {
         u32 x[2] = {a & 1, a >> 1}, y[2] = {b & 1, b >> 1}, r[2], d[2];

@@ -71,6 +71,31 @@ def test_gf4(table):
         assert mx == mul[2][a]
 
 
+def gf8_table():
+    path = os.path.join(ROOT, "tests", "golden", "gf8_mul.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    return [[int(x) for x in r] for r in rows]
+
+
+def test_gf8(table):
+    mul = gf8_table()
+    rows = [r for r in table if r[0] == "g8"]
+    assert len(rows) == 64
+    for r in rows:
+        a, b, s, m1, m2 = map(int, (r[1], r[2], r[4], r[6], r[8]))
+        assert s == a ^ b
+        assert m1 == mul[2][a] and m2 == mul[4][a]
+
+
+def test_gf8_accumulate_step(table):
+    mul = gf8_table()
+    rows = [r for r in table if r[0] == "g8acc"]
+    assert len(rows) == 8 ** 4
+    for r in rows:
+        c, t, u, v, out = map(int, r[1:])
+        assert out == c ^ t ^ mul[2][u] ^ mul[4][v], r
+
+
 def test_f3_binary_working_form(table):
     for r in (r for r in table if r[0] == "f3b"):
         a, b, add, sub, c0, c1 = int(r[1]), int(r[2]), int(r[4]), int(r[6]), int(r[8]), int(r[9])

@@ -11,7 +11,7 @@ import oracle
 from paper_0901_1413_amd import inputs
 
 pytestmark = pytest.mark.gpu
-FIELDS = (3, 4, 5, 7)
+FIELDS = (3, 4, 5, 7, 8)
 
 
 def dev(x):
@@ -52,7 +52,7 @@ def test_pack_matches_oracle_encoding(gfq_gpu, q, cols):
 def test_pack_reduces_integers(gfq_gpu, q):
     X = np.arange(256, dtype=np.uint8).reshape(2, 128)
     got = gfq_gpu.unpack(q, gfq_gpu.pack(q, dev(X)), 2, 128).cpu().numpy()
-    want = (X & 3) if q == 4 else (X % q)
+    want = {4: X & 3, 8: X & 7}.get(q, X % q)      # GF(4), GF(8): the low coefficient bits
     assert np.array_equal(got, want.astype(np.uint8))
 
 
@@ -241,8 +241,24 @@ def test_variant_validation(gfq_gpu):
     import torch
     g = gfq_gpu
     Ap, Bp = g.pack(3, dev(np.zeros((64, 64), np.uint8))), g.pack(3, dev(np.zeros((64, 64), np.uint8)))
-    for q, var in ((3, g.VARIANT_KARATSUBA), (5, g.VARIANT_KARATSUBA), (4, 2), (4, -1)):
+    for q, var in ((3, g.VARIANT_KARATSUBA), (5, g.VARIANT_KARATSUBA), (8, g.VARIANT_KARATSUBA), (4, 2), (4, -1)):
         with pytest.raises(g.GfqError) as e:
             g.matmul(q, Ap, Bp, 64, 64, 64, variant=var)
         assert e.value.status == -1, (q, var)
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("rows,k", [(2048, 8), (1024, 7), (256, 10)])
+def test_gf8_4096_sampled(gfq_gpu, rows, k):
+    """GF(8), A and B 4096 x 4096 uniform, in three launch configurations (eight rows per
+    lane, four, and narrow tiles at k = 10): sampled rows, spread over every row tile and
+    covering the last one, against the oracle."""
+    import torch
+    g = gfq_gpu
+    q, N = 8, 4096
+    A, B = inputs.pair(q, N, N, N, cfg=220, idx=rows)
+    Ap, Bp = g.pack(q, dev(A)), g.pack(q, dev(B))
+    C = g.unpack(q, g.matmul(q, Ap, Bp, N, N, N, rows=rows, k=k), N, N)
+    sample = np.unique(np.concatenate([np.arange(0, N, 97), np.arange(N - 5, N)]))
+    got = C[torch.from_numpy(sample).cuda()].cpu().numpy()
+    assert np.array_equal(got, oracle.matmul(q, A[sample], B))
