@@ -1,4 +1,4 @@
-"""CPU oracle for C = A B over F_3, F_5, F_7, GF(4) and GF(8) -- TEST INFRASTRUCTURE ONLY.
+"""CPU oracle for C = A B over F_3, F_5, F_7, GF(4), GF(8), F_9 -- TEST INFRASTRUCTURE ONLY.
 
 Only the tests, the smoke check of the entry module and the CPU-baseline leg of the
 benchmark may import this package.  The GPU library never uses it, and it shares no code
@@ -26,7 +26,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gfq_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
-FIELDS = (3, 4, 5, 7, 8)
+FIELDS = (3, 4, 5, 7, 8, 9)
 
 
 def build(force: bool = True) -> str:
@@ -65,16 +65,19 @@ def max_threads() -> int:
 
 def planes(q: int) -> int:
     """Bit-planes per element: 2 for F_3 (unit, sign) and GF(4) (c0, c1); 3 for F_5, F_7
-    and GF(8) (c0, c1, c2)."""
+    and GF(8) (c0, c1, c2); 4 for F_9 (unit and sign of a0, then of a1)."""
     if q in (3, 4):
         return 2
     if q in (5, 7, 8):
         return 3
+    if q == 9:
+        return 4
     raise ValueError(f"unsupported field q={q}")
 
 
 def matmul(q: int, A: np.ndarray, B: np.ndarray, threads: int = 0) -> np.ndarray:
-    """C = A B over F_q (q = 4 means GF(4), q = 8 GF(8)); A, B and C canonical uint8."""
+    """C = A B over F_q (q = 4 means GF(4), q = 8 GF(8), q = 9 F_9 = F_3[i]/(i^2 + 1));
+    A, B and C canonical uint8."""
     A = np.ascontiguousarray(A, dtype=np.uint8)
     B = np.ascontiguousarray(B, dtype=np.uint8)
     if A.ndim != 2 or B.ndim != 2 or A.shape[1] != B.shape[0]:
@@ -97,10 +100,14 @@ def encode_planes(q: int, X: np.ndarray) -> list:
     F_5, F_7 (Section 4.2): the binary digits of the representative, plane d = bit d.
     GF(4) (Section 4.3, basis {1, x}): e = c0 + 2 c1, plane d = c_d.
     GF(8) (Section 4.3, power basis {1, x, x^2}): e = c0 + 2 c1 + 4 c2, plane d = c_d.
+    F_9 (Section 4.3, F_3[i]/(i^2 + 1)): e = a0 + 3 a1; each coefficient in the F_3 code of
+    Section 4.1, planes (unit a0, sign a0, unit a1, sign a1).
     """
     X = np.asarray(X, dtype=np.uint8)
     if q == 3:
         return [(X != 0).astype(np.uint8), (X == 2).astype(np.uint8)]
+    if q == 9:
+        return encode_planes(3, X % 3) + encode_planes(3, X // 3)
     return [((X >> d) & 1).astype(np.uint8) for d in range(planes(q))]
 
 
@@ -109,6 +116,8 @@ def decode_planes(q: int, bits: list) -> np.ndarray:
     if q == 3:
         x0, x1 = bits
         return np.where(x0 == 0, 0, np.where(x1 == 0, 1, 2)).astype(np.uint8)
+    if q == 9:
+        return (decode_planes(3, bits[:2]) + 3 * decode_planes(3, bits[2:])).astype(np.uint8)
     v = np.zeros_like(bits[0], dtype=np.int64)
     for d, b in enumerate(bits):
         v |= b.astype(np.int64) << d

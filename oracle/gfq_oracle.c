@@ -1,5 +1,6 @@
 /*
- * gfq_oracle.c -- CPU oracle for dense matrix products over F_3, F_5, F_7, GF(4) and GF(8).
+ * gfq_oracle.c -- CPU oracle for dense matrix products over F_3, F_5, F_7, GF(4), GF(8)
+ * and F_9.
  *
  * TEST INFRASTRUCTURE ONLY.  This file exists so that tests, the smoke check and the
  * CPU-baseline leg of the benchmark can check the GPU library against an obviously
@@ -22,6 +23,11 @@
  *     polynomials over the base field, reduced by the defining polynomial): element
  *     e = c0 + 2 c1 + 4 c2 stands for c0 + c1 x + c2 x^2.  The product is the schoolbook
  *     polynomial product over F_2 (degree up to 4), then x^4 -> x^2 + x and x^3 -> x + 1.
+ *   - F_9 = F_3[i]/(i^2 + 1) (paper, Section 4.3, the same polynomial view over F_3; i^2 + 1
+ *     has no root mod 3): element e = a0 + 3 a1 with a0, a1 in [0, 3) stands for a0 + a1 i.
+ *     (a0 + a1 i)(b0 + b1 i) = (a0 b0 - a1 b1) + (a0 b1 + a1 b0) i; the real and imaginary
+ *     sums are taken exactly in 32-bit integers (|sum| <= 2 l (p-1)^2) and reduced mod 3
+ *     at the end.
  *
  * Loop order is i, t, j with no blocking: a row of C is built as a linear combination of
  * the rows of B, exactly as the equation reads.  OpenMP splits the rows of C.
@@ -62,7 +68,7 @@ int gfq_oracle_matmul(int q, int64_t m, int64_t l, int64_t n,
                       const uint8_t *B, int64_t ldb,
                       uint8_t *C, int64_t ldc, int nthreads)
 {
-    if (q != 3 && q != 4 && q != 5 && q != 7 && q != 8) return -1;
+    if (q != 3 && q != 4 && q != 5 && q != 7 && q != 8 && q != 9) return -1;
     if (m < 0 || l < 0 || n < 0 || l >= (1 << 24)) return -2;
     if (m == 0 || n == 0) return 0;
     if (C == NULL || (l > 0 && (A == NULL || B == NULL))) return -3;
@@ -75,7 +81,7 @@ int gfq_oracle_matmul(int q, int64_t m, int64_t l, int64_t n,
     int err = 0;
 #pragma omp parallel
     {
-        int32_t *acc = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+        int32_t *acc = (int32_t *)malloc((size_t)n * 2 * sizeof(int32_t));
         if (acc == NULL) {
 #pragma omp atomic write
             err = -4;
@@ -83,9 +89,25 @@ int gfq_oracle_matmul(int q, int64_t m, int64_t l, int64_t n,
 #pragma omp for schedule(static)
         for (int64_t i = 0; i < m; i++) {
             if (acc == NULL) continue;
-            memset(acc, 0, (size_t)n * sizeof(int32_t));
+            memset(acc, 0, (size_t)n * 2 * sizeof(int32_t));
             const uint8_t *arow = A + i * lda;
-            if (q == 4 || q == 8) {
+            if (q == 9) {
+                int32_t *re = acc, *im = acc + n;
+                for (int64_t t = 0; t < l; t++) {
+                    int32_t a0 = arow[t] % 3, a1 = arow[t] / 3;
+                    if (a0 == 0 && a1 == 0) continue;
+                    const uint8_t *brow = B + t * ldb;
+                    for (int64_t j = 0; j < n; j++) {
+                        int32_t b0 = brow[j] % 3, b1 = brow[j] / 3;
+                        re[j] += a0 * b0 - a1 * b1;
+                        im[j] += a0 * b1 + a1 * b0;
+                    }
+                }
+                for (int64_t j = 0; j < n; j++) {
+                    int32_t r = ((re[j] % 3) + 3) % 3, m = ((im[j] % 3) + 3) % 3;
+                    C[i * ldc + j] = (uint8_t)(r + 3 * m);
+                }
+            } else if (q == 4 || q == 8) {
                 uint8_t (*mul)(uint8_t, uint8_t) = q == 4 ? gf4_mul : gf8_mul;
                 for (int64_t t = 0; t < l; t++) {
                     uint8_t a = arow[t];

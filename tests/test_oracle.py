@@ -6,8 +6,10 @@
 * GF(8) products against the paper's six-product trinomial formula (Section 4.3) built
   from numpy products over F_2 and reduced by x^3 + x + 1, and against a multiplication
   table derived by hand from the powers of x; field axioms on that table.
+* F_9 = F_3[i]/(i^2 + 1) products against matrix-level Karatsuba over F_3 (Section 4.3:
+  three numpy products mod 3), against a hand-derived table, and on the subfield F_3.
 * Exhaustive tiny inputs: every 2x2 by 2x2 pair over F_3, every 1x2 by 2x1 pair over
-  F_5, F_7, GF(4) and GF(8).
+  F_5, F_7, GF(4), GF(8) and F_9.
 * Invariants of matrix multiplication: identity, zero, associativity, both distributive
   laws, transpose, scalars, and the additive-basis split of Section 2.
 * Packed encodings against the paper's printed element codes (Sections 4.1-4.3).
@@ -22,7 +24,7 @@ import oracle
 from paper_0901_1413_amd import inputs
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
-FIELDS = (3, 4, 5, 7, 8)
+FIELDS = (3, 4, 5, 7, 8, 9)
 
 
 def np_fp(q, A, B):
@@ -63,12 +65,38 @@ def gf8_trinomial(A, B):
     return (r0 + 2 * r1 + 4 * r2).astype(np.uint8)
 
 
+def f9_karatsuba(A, B):
+    """A = A0 + i A1, B = B0 + i B1 over F_3 with i^2 = -1 (Section 4.3, matrix-level):
+    AB = (A0B0 - A1B1) + i((A0+A1)(B0+B1) - A0B0 - A1B1), three F_3 products."""
+    A0, A1 = (A % 3).astype(np.int64), (A // 3).astype(np.int64)
+    B0, B1 = (B % 3).astype(np.int64), (B // 3).astype(np.int64)
+    P00, P11 = A0 @ B0, A1 @ B1
+    Pss = (A0 + A1) @ (B0 + B1)
+    re, im = (P00 - P11) % 3, (Pss - P00 - P11) % 3
+    return (re + 3 * im).astype(np.uint8)
+
+
 def reference(q, A, B):
     if q == 4:
         return gf4_karatsuba(A, B)
     if q == 8:
         return gf8_trinomial(A, B)
+    if q == 9:
+        return f9_karatsuba(A, B)
     return np_fp(q, A, B)
+
+
+def f9_add(X, Y):
+    X, Y = np.asarray(X, dtype=np.int64), np.asarray(Y, dtype=np.int64)
+    return ((X % 3 + Y % 3) % 3 + 3 * ((X // 3 + Y // 3) % 3)).astype(np.uint8)
+
+
+def field_add(q):
+    if q in (4, 8):
+        return lambda X, Y: X ^ Y
+    if q == 9:
+        return f9_add
+    return lambda X, Y: ((X.astype(int) + Y) % q).astype(np.uint8)
 
 
 def read_table(name):
@@ -85,7 +113,7 @@ def gf8_table():
 
 
 def table_of(q):
-    return gf4_table() if q == 4 else gf8_table()
+    return {4: gf4_table, 8: gf8_table, 9: lambda: read_table("f9_mul.txt")}[q]()
 
 
 @pytest.mark.parametrize("q", FIELDS)
@@ -125,25 +153,43 @@ def test_gf8_multiplication_table():
             assert gf8_trinomial(A, B)[0, 0] == T[a, b], (a, b)
 
 
-@pytest.mark.parametrize("q", [4, 8])
-def test_extension_field_axioms(q):
-    """The golden tables describe a field: commutative, associative, distributive over XOR,
-    1 is the identity and every nonzero element has an inverse (rows are permutations)."""
+@pytest.mark.parametrize("q,gen", [(4, 2), (8, 2), (9, 4)])
+def test_extension_field_axioms(q, gen):
+    """The golden tables describe a field: commutative, associative, distributive over the
+    field's addition, 1 is the identity and every nonzero element has an inverse (rows are
+    permutations); the multiplicative group is cyclic of order q - 1 (generator x for
+    GF(4), GF(8); 1 + i for F_9, as i alone has order 4)."""
     T = table_of(q).astype(int)
+    add = field_add(q)
     r = range(q)
     assert (T == T.T).all()
     assert list(T[1]) == list(r) and not T[0].any()
     for a, b, c in itertools.product(r, repeat=3):
         assert T[T[a, b], c] == T[a, T[b, c]]
-        assert T[a, b ^ c] == T[a, b] ^ T[a, c]
+        assert T[a, int(add(b, c))] == int(add(T[a, b], T[a, c]))
     for a in range(1, q):
         assert sorted(T[a, 1:]) == list(range(1, q))
-    # the multiplicative group is cyclic of order q - 1, generated by x (= 2)
     p, seen = 1, []
     for _ in range(q - 1):
         seen.append(p)
-        p = T[p, 2]
+        p = T[p, gen]
     assert p == 1 and sorted(seen) == list(range(1, q))
+
+
+def test_f9_table_and_subfield():
+    T = table_of(9)
+    for a in range(9):
+        for b in range(9):
+            A, B = np.array([[a]], np.uint8), np.array([[b]], np.uint8)
+            assert oracle.matmul(9, A, B)[0, 0] == T[a, b], (a, b)
+            assert f9_karatsuba(A, B)[0, 0] == T[a, b], (a, b)
+    # i^2 = -1, and on F_3 (a1 = 0) the product is the F_3 product
+    assert T[3, 3] == 2
+    A, B = inputs.pair(3, 31, 70, 45, cfg=106)
+    assert np.array_equal(oracle.matmul(9, A, B), oracle.matmul(3, A, B))
+    # on i F_3 x i F_3 the product is minus the F_3 product of the coefficients
+    C3 = oracle.matmul(3, A, B)
+    assert np.array_equal(oracle.matmul(9, 3 * A, 3 * B), (3 - C3) % 3)
 
 
 def test_exhaustive_f3_2x2():
@@ -162,15 +208,16 @@ def test_exhaustive_f3_2x2():
     assert np.array_equal(got, want)
 
 
-@pytest.mark.parametrize("q", [4, 5, 7, 8])
+@pytest.mark.parametrize("q", [4, 5, 7, 8, 9])
 def test_exhaustive_1x2_by_2x1(q):
-    T = table_of(q) if q in (4, 8) else None
+    T = table_of(q) if q in (4, 8, 9) else None
+    add = field_add(q)
     for a0, a1, b0, b1 in itertools.product(range(q), repeat=4):
         A = np.array([[a0, a1]], np.uint8)
         B = np.array([[b0], [b1]], np.uint8)
         got = oracle.matmul(q, A, B)[0, 0]
-        if q in (4, 8):
-            want = T[a0, b0] ^ T[a1, b1]
+        if q in (4, 8, 9):
+            want = add(T[a0, b0], T[a1, b1])
         else:
             want = (a0 * b0 + a1 * b1) % q
         assert got == want, (a0, a1, b0, b1)
@@ -183,7 +230,7 @@ def test_invariants(q):
     B = inputs.matrix(q, l, n, 103, q, 1)
     B2 = inputs.matrix(q, l, n, 103, q, 3)
     D = inputs.matrix(q, n, p, 103, q, 4)
-    add = (lambda X, Y: X ^ Y) if q in (4, 8) else (lambda X, Y: ((X.astype(int) + Y) % q).astype(np.uint8))
+    add = field_add(q)
     I_l = np.eye(l, dtype=np.uint8)
     mm = lambda X, Y: oracle.matmul(q, X, Y)
     assert np.array_equal(mm(A, I_l), A)
@@ -204,19 +251,23 @@ def test_additive_basis_split(q):
     """Section 2: a = sum_d alpha_d phi_d(a) gives AB = sum_d alpha_d (Phi_d(A) B) with
     Phi_d(A) the 0/1 matrix of phi_d.  F_3 uses {1, -1} with phi_0 = [a = 1],
     phi_1 = [a = -1]; F_5, F_7 use {1, 2, 4} with binary digits; GF(4) uses {1, x} and
-    GF(8) {1, x, x^2} (the integers 1, 2, 4 encode those elements)."""
+    GF(8) {1, x, x^2} (the integers 1, 2, 4 encode those elements); F_9 uses the products
+    of {1, i} with the F_3 basis, {1, -1, i, -i} (codes 1, 2, 3, 6), phi = [a0 = 1],
+    [a0 = -1], [a1 = 1], [a1 = -1]."""
     A, B = inputs.pair(q, 23, 61, 19, cfg=104)
     if q == 3:
         alphas, phis = [1, 2], [(A == 1), (A == 2)]
     elif q == 4:
         alphas, phis = [1, 2], [(A & 1), (A >> 1) & 1]
+    elif q == 9:
+        alphas, phis = [1, 2, 3, 6], [(A % 3 == 1), (A % 3 == 2), (A // 3 == 1), (A // 3 == 2)]
     else:
         alphas, phis = [1, 2, 4], [(A >> d) & 1 for d in range(3)]
     acc = np.zeros((23, 19), np.uint8)
     for alpha, phi in zip(alphas, phis):
         part = oracle.matmul(q, phi.astype(np.uint8), B)
         scaled = oracle.matmul(q, part, (alpha * np.eye(19)).astype(np.uint8))   # part * alpha
-        acc = (acc ^ scaled) if q in (4, 8) else ((acc.astype(int) + scaled) % q).astype(np.uint8)
+        acc = field_add(q)(acc, scaled)
     assert np.array_equal(acc, oracle.matmul(q, A, B))
 
 
