@@ -37,17 +37,17 @@ M = L = N = 8192
 FIELDS = (3, 5)
 PEAK_VALU_OPS = 256 * 64 * 2.4e9          # 32-bit VALU lane-operations per second
 PEAK_HBM = 8.0e12
-SECTIONS = ("c1", "c2_k", "mfma", "c3", "gf8", "c4", "c5")
+SECTIONS = ("c1", "c2_k", "mfma", "c3", "ext", "c4", "c5")
 
 # Per-unit operation counts of the method on gfx950 (three-input bitwise instructions).
 # A unit is (row of C, slab of k rows of B, 32-column word).  Accumulate: the slab's D
 # alpha-scaled table rows into a carry-save accumulator, one full adder (2 instructions)
 # per addend bit (F_3 4 bits, F_7 9; F_5 9 bits plus one half adder; GF(4) 3 XORs; GF(8)
-# 6 XORs).  Table build: one field addition per table entry and word.  Finish: per output
-# word.
-C_ACC = {3: 8, 4: 3, 5: 20, 7: 18, 8: 6}
-C_ADD = {3: 6, 4: 2, 5: 13, 7: 11, 8: 3}
-C_FIN = {3: 8, 4: 0, 5: 30, 7: 15, 8: 0}
+# 6 XORs; F_9 8 bits).  Table build: one field addition per table entry and word.  Finish:
+# per output word.
+C_ACC = {3: 8, 4: 3, 5: 20, 7: 18, 8: 6, 9: 32}
+C_ADD = {3: 6, 4: 2, 5: 13, 7: 11, 8: 3, 9: 12}
+C_FIN = {3: 8, 4: 0, 5: 30, 7: 15, 8: 0, 9: 16}
 # The paper's two-input operation counts (Sections 4.1 and 4.2) for the same units.
 C_ACC_PAPER = {3: 12, 4: 4, 5: 60, 7: 51}
 C_ADD_PAPER = {3: 6, 4: 2, 5: 20, 7: 17}
@@ -337,7 +337,15 @@ def int8_product(torch, q, A8, B8):
     """C = A B over F_q from int8 GEMMs with int32 accumulation (exact while l (q-1)^2 <
     2^31): one GEMM and a reduction mod p for F_p; for GF(4) = F_2[x]/(x^2+x+1) the
     coefficient planes by Karatsuba, three GEMMs reduced mod 2; for GF(8) =
-    F_2[x]/(x^3+x+1) the trinomial formula of Section 4.3, six GEMMs reduced mod 2."""
+    F_2[x]/(x^3+x+1) the trinomial formula of Section 4.3, six GEMMs reduced mod 2; for
+    F_9 = F_3[i]/(i^2+1) Karatsuba over F_3, three GEMMs reduced mod 3."""
+    if q == 9:
+        a0, a1 = torch.remainder(A8, 3), torch.div(A8, 3, rounding_mode="floor")
+        b0, b1 = torch.remainder(B8, 3), torch.div(B8, 3, rounding_mode="floor")
+        p00, p11 = torch._int_mm(a0, b0), torch._int_mm(a1, b1)
+        pss = torch._int_mm(a0 + a1, b0 + b1)
+        re, im = torch.remainder(p00 - p11, 3), torch.remainder(pss - p00 - p11, 3)
+        return (re + 3 * im).to(torch.uint8)
     if q == 8:
         a = [(A8 >> d) & 1 for d in range(3)]
         b = [(B8 >> d) & 1 for d in range(3)]
@@ -483,16 +491,18 @@ def section_c3(ctx, reps=3, sample_rows=32):
 
 
 # ------------------------------------------------------------------------------------
-# gf8: the cubic extension GF(8) = F_2[x]/(x^3 + x + 1), row-wise with basis {1, x, x^2}
+# ext: the extension fields GF(8) = F_2[x]/(x^3 + x + 1) (basis {1, x, x^2}) and
+# F_9 = F_3[i]/(i^2 + 1) (basis {1, -1, i, -i}), row-wise
 # ------------------------------------------------------------------------------------
 
-def section_gf8(ctx, reps=3, sample_rows=32):
+def section_ext(ctx, reps=3, sample_rows=32):
     import numpy as np
     torch, gfq, inputs = ctx.torch, ctx.gfq, ctx.inputs
-    q = 8
     res = {}
-    for (m, l, n), density in (((16384, 2048, 16384), 1.0), ((16384, 2048, 16384), 0.1), ((M, L, N), 1.0)):
-        A, B = inputs.pair(q, m, l, n, cfg=6, idx=m + l, density=density)
+    cases = [(8, (16384, 2048, 16384), 1.0), (8, (16384, 2048, 16384), 0.1), (8, (M, L, N), 1.0),
+             (9, (16384, 2048, 16384), 1.0), (9, (M, L, N), 1.0)]
+    for q, (m, l, n), density in cases:
+        A, B = inputs.pair(q, m, l, n, cfg=6, idx=q * 100000 + m + l, density=density)
         Ad, Bd = ctx.up(A), ctx.up(B)
         Ap, Bp, Cp = gfq.pack(q, Ad), gfq.pack(q, Bd), gfq.empty_packed(q, m, n)
         gfq.matmul(q, Ap, Bp, m, l, n, out=Cp)
@@ -521,7 +531,7 @@ def section_gf8(ctx, reps=3, sample_rows=32):
         ev[1].record()
         torch.cuda.synchronize()
         mfma_ms = ev[0].elapsed_time(ev[1]) / reps
-        name = f"{m}x{l}x{n}" + ("" if density == 1.0 else "_density0.1")
+        name = ("GF8_" if q == 8 else "F9_") + f"{m}x{l}x{n}" + ("" if density == 1.0 else "_density0.1")
         res[name] = {"product_ms": round(pm, 4), "partial_sum_ms": round(rm, 4),
                      "field_ops_per_s_product": 2.0 * m * l * n / ((pm + rm) * 1e-3),
                      "alu_frac": round(ops / (pm * 1e-3) / PEAK_VALU_OPS, 4), "config": cfg,
@@ -529,7 +539,7 @@ def section_gf8(ctx, reps=3, sample_rows=32):
                      "int8_mfma_comparison_ms": round(mfma_ms, 4), "int8_mfma_equals": same8}
         del Ad, Bd, Ap, Bp, Cp, Cd, A8, B8
         torch.cuda.empty_cache()
-    return {"workload": "GF(8), A m x l, B l x n uniform (and 10% density)", **res}
+    return {"workload": "GF(8) and F_9, A m x l, B l x n uniform (and 10% density)", **res}
 
 
 # ------------------------------------------------------------------------------------
@@ -783,9 +793,9 @@ def main():
         log("c3")
         res["c3"] = section_c3(ctx)
         torch.cuda.empty_cache()
-    if "gf8" in sections:
-        log("gf8")
-        res["gf8"] = section_gf8(ctx)
+    if "ext" in sections:
+        log("ext")
+        res["ext"] = section_ext(ctx)
         torch.cuda.empty_cache()
     if "c4" in sections:
         log("c4")

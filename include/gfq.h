@@ -1,7 +1,7 @@
 /*
  * gfq.h -- C ABI of libgfq: dense matrix products C = A B over F_3, F_5, F_7,
- * GF(4) = F_2[x]/(x^2 + x + 1) and GF(8) = F_2[x]/(x^3 + x + 1) on one AMD Instinct
- * MI355X (gfx950), computed by the
+ * GF(4) = F_2[x]/(x^2 + x + 1), GF(8) = F_2[x]/(x^3 + x + 1) and F_9 = F_3[i]/(i^2 + 1) on
+ * one AMD Instinct MI355X (gfx950), computed by the
  * Method of Four Russians with an additive basis on bitsliced rows (Boothby and
  * Bradshaw, "Bitslicing and the Method of Four Russians Over Larger Finite Fields":
  * Section 2 for the method, Section 3 for the row-wise bitsliced format, Section 4 for
@@ -9,22 +9,24 @@
  *
  * Conventions shared by every call
  * --------------------------------
- *  - Field selector q is 3, 5 or 7 for the prime fields, 4 for GF(4) and 8 for GF(8).  Any
- *    other value returns GFQ_EFIELD.
+ *  - Field selector q is 3, 5 or 7 for the prime fields, 4 for GF(4), 8 for GF(8) and 9
+ *    for F_9.  Any other value returns GFQ_EFIELD.
  *  - Unpacked matrices are uint8, row-major with a leading dimension in elements, holding
  *    canonical representatives: 0..q-1 for F_q; for F_3 the value 2 stands for -1; for
  *    GF(4) the value c0 + 2 c1 stands for c0 + c1 x; for GF(8) the value c0 + 2 c1 + 4 c2
- *    stands for c0 + c1 x + c2 x^2.
+ *    stands for c0 + c1 x + c2 x^2; for F_9 the value a0 + 3 a1 (a0, a1 in 0..2, 2 standing
+ *    for -1) stands for a0 + a1 i.
  *  - Packed matrices use the row-wise bitsliced format of Section 3, the same format for
  *    the left operand, the right operand and the product.  A matrix of R rows and N
  *    columns over a field with P bit-planes (P = 2 for F_3 and GF(4), P = 3 for F_5, F_7
- *    and GF(8))
+ *    and GF(8), P = 4 for F_9)
  *    occupies R * P * W 32-bit words with W = ceil(N / 128) * 4: row r holds plane 0,
  *    then plane 1, ..., each W little-endian words; element j of the row is bit (j mod 32)
  *    of word (j / 32) of each plane.  Element encodings per plane:
  *        F_3 (Section 4.1): plane 0 marks a unit, plane 1 the sign (0 = 00, 1 = 10, -1 = 11)
  *        F_5, F_7 (Section 4.2): plane d is binary digit d of the representative
  *        GF(4), GF(8) (Section 4.3): plane d is the coefficient c_d of x^d
+ *        F_9 (Section 4.3 over 4.1): planes 0, 1 are the F_3 code of a0, planes 2, 3 of a1
  *    Bits beyond column N-1 ("pad bits") are zero in every buffer this library writes.
  *    Products are written canonical (F_5, F_7: representatives below q), so a packed
  *    product is unique.
@@ -47,7 +49,7 @@ extern "C" {
 enum {
     GFQ_OK = 0,
     GFQ_EINVAL = -1,  /* malformed argument not covered below (e.g. bad config field)  */
-    GFQ_EFIELD = -2,  /* q not in {3, 4, 5, 7, 8}                                       */
+    GFQ_EFIELD = -2,  /* q not in {3, 4, 5, 7, 8, 9}                                    */
     GFQ_EDIM = -3,    /* negative or too large dimension, or leading dimension too small */
     GFQ_ENULL = -4,   /* null pointer where data is needed                               */
     GFQ_EALIGN = -5,  /* packed buffer not 16-byte aligned                              */
@@ -68,7 +70,7 @@ size_t gfq_packed_bytes(int q, int64_t rows, int64_t cols);
 /* Pack (Section 3 bitslicing with the encodings of Section 4).
  * src: device, rows x cols uint8, leading dimension ld_src >= cols.  Values are taken as
  *      integers: for F_p the residue mod p is packed; for GF(4) only bits 0 and 1 are used,
- *      for GF(8) bits 0 to 2.
+ *      for GF(8) bits 0 to 2; for F_9 the residue mod 9.
  * dst: device, gfq_packed_bytes(q, rows, cols) bytes, 16-byte aligned; pad bits are zeroed.
  * rows == 0 or cols == 0 is a no-op. */
 int gfq_pack(int q, int64_t rows, int64_t cols, const uint8_t *src, int64_t ld_src, void *dst);
@@ -93,10 +95,10 @@ int gfq_matmul(int q, int64_t m, int64_t l, int64_t n, const void *A, const void
  * sweep).
  *   k      slab width, 1..10: each slab of k rows of B gets a table of its 2^k binary row
  *          combinations.  Two tables live in LDS at once; up to k = 7 (F_3, GF(4)) or
- *          k = 6 (F_5, F_7, GF(8)) their rows are 256 bytes wide, larger k narrows the rows and
+ *          k = 6 (F_5, F_7, GF(8), F_9) their rows are 256 bytes wide, larger k narrows the rows and
  *          lets 128-bit LDS reads conflict.
- *   rows   requested rows of C per workgroup: 256, 512, 1024 or 2048 (F_5, F_7 and GF(8)
- *          are capped by their register use; the library covers what fits)
+ *   rows   requested rows of C per workgroup: 256, 512, 1024 or 2048 (F_5, F_7, GF(8) and
+ *          F_9 are capped by their register use; the library covers what fits)
  *   split  number of slices of the inner dimension computed by separate workgroups and
  *          summed afterwards, 1..64
  *   variant how GF(4) products are formed (other fields: GFQ_VARIANT_ROWWISE only):

@@ -47,6 +47,7 @@ const void *batched_kernel(int q, int R) {
     case 4: return R == 2 ? list_kernel_ptr<4, 2>() : list_kernel_ptr<4, 8>();
     case 5: return list_kernel_ptr<5, 2>();      // four rows per lane would spill here
     case 8: return R == 2 ? list_kernel_ptr<8, 2>() : list_kernel_ptr<8, 8>();
+    case 9: return list_kernel_ptr<9, 2>();      // four rows per lane would spill here
     default: return R == 2 ? list_kernel_ptr<7, 2>() : list_kernel_ptr<7, 4>();
     }
 }

@@ -18,7 +18,7 @@ using namespace gfq;
 namespace {
 
 int group_index(int q, int R) {
-    const int qi = q == 3 ? 0 : (q == 4 ? 1 : (q == 5 ? 2 : (q == 7 ? 3 : 4)));
+    const int qi = q == 3 ? 0 : (q == 4 ? 1 : (q == 5 ? 2 : (q == 7 ? 3 : (q == 8 ? 4 : 5))));
     return qi * 2 + (R == 2 ? 0 : 1);
 }
 
@@ -28,7 +28,7 @@ int group_index(int q, int R) {
 // ordered longest first within a group.
 void gfq::plan_batch(int count, const gfq_problem *problems, const gfq_config *cfgs, BatchProd *prods,
                      std::vector<BatchGroup> *groups, size_t *nitems) {
-    std::vector<BatchGroup> g(10);
+    std::vector<BatchGroup> g(12);
     for (int i = 0; i < count; i++) {
         const gfq_problem &p = problems[i];
         BatchProd &bp = prods[i];
@@ -38,12 +38,12 @@ void gfq::plan_batch(int count, const gfq_problem *problems, const gfq_config *c
         else if (gfq_tune_lookup(p.q, p.m, p.l, p.n, GFQ_TUNE_BATCH, &c) != GFQ_OK)
             gfq_choose_config(p.q, p.m, p.l, p.n, &c);
         const int P = planes_of(p.q);
-        // the batched kernels use 256-byte super-rows: k <= 7 (two planes) or 6 (three)
-        const int kcap = P == 2 ? 7 : 6;
+        // the batched kernels use 256-byte super-rows: k <= 7 (two planes), 6 (three or four)
+        const int kcap = kmax_wide(p.q);
         int k = std::min(c.k, kcap);
         if (p.l > 0 && p.l < k) k = (int)p.l;
         if (k < 1) k = 1;
-        const int R = (c.rows <= 256 || p.q == 5) ? 2 : max_rows_per_lane_batch(p.q);
+        const int R = c.rows <= 256 ? 2 : max_rows_per_lane_batch(p.q);
         const int TM = NT_MM / 4 * R;
         MMArgs &a = bp.a;
         a.A = (const u32 *)p.A;
@@ -100,10 +100,9 @@ size_t gfq::batch_tiles_bound(int64_t m, int64_t n) {
 }
 
 hipError_t gfq::set_batched_lds_limits() {
-    for (int q : {3, 4, 5, 7, 8})
+    for (int q : {3, 4, 5, 7, 8, 9})
         for (int R : {2, max_rows_per_lane_batch(q)}) {
-            if (q == 5 && R != 2) continue;       // F_5 batches use two rows per lane only
-            const size_t lds = mm_lds_bytes(q, planes_of(q) == 2 ? 7 : 6, 256, NT_MM / 4 * R, nullptr);
+            const size_t lds = mm_lds_bytes(q, kmax_wide(q), 256, NT_MM / 4 * R, nullptr);
             hipError_t e = hipFuncSetAttribute(batched_kernel(q, R), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
         }

@@ -185,4 +185,45 @@ template <> struct FT<8> {
     __device__ static void scanon(u32 *) {}
 };
 
+// F_9 = F_3[i]/(i^2 + 1) (Section 4.3: the power basis {1, i} of the extension times the
+// basis {1, -1} of F_3 gives the additive basis {1, -1, i, -i}).  Storage: the F_3 code of
+// a0, then of a1 (four planes); phi = [a0 = 1], [a0 = -1], [a1 = 1], [a1 = -1].  Table
+// entries are pairs of binary residues mod 3 (real, imaginary).  With i (x + y i) =
+// -y + x i the slab adds T0 - T1 + i T2 - i T3, i.e. real += T0.re - T1.re - T2.im + T3.im
+// and imaginary += T0.im - T1.im + T2.re - T3.re, into two carry-save pairs mod 3.
+template <> struct FT<9> {
+    static constexpr int P = 4, PT = 4, D = 4, GP = 4, PA = 8;
+    static constexpr bool SPLIT_PREFIX = false;
+    static constexpr int gplane(int, int p) { return p; }
+    __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0] ^ x[1]; f[1] = x[1]; f[2] = x[2] ^ x[3]; f[3] = x[3]; }
+    __device__ static void to_table(const u32 *x, u32 *t) { f3_to_bin(x[0], x[1], t); f3_to_bin(x[2], x[3], t + 2); }
+    __device__ static void tadd(const u32 *a, const u32 *b, u32 *r) { f3b_add(a, b, r); f3b_add(a + 2, b + 2, r + 2); }
+    __device__ static void tsub(const u32 *a, const u32 *b, u32 *r) { f3b_sub(a, b, r); f3b_sub(a + 2, b + 2, r + 2); }
+    __device__ static void acc_init(u32 *c, int) { for (int i = 0; i < PA; i++) c[i] = 0u; }
+    __device__ static void accumulate(u32 *c, const u32 (*t)[P]) {
+        u32 *Sr = c, *Kr = c + 2, *Si = c + 4, *Ki = c + 6;
+        csa_step<2>(Sr, Kr, t[0]);
+        csa_step_neg<2>(Sr, Kr, t[1]);
+        csa_step_neg<2>(Sr, Kr, t[2] + 2);
+        csa_step<2>(Sr, Kr, t[3] + 2);
+        csa_step<2>(Si, Ki, t[0] + 2);
+        csa_step_neg<2>(Si, Ki, t[1] + 2);
+        csa_step<2>(Si, Ki, t[2]);
+        csa_step_neg<2>(Si, Ki, t[3]);
+    }
+    __device__ static void finish(const u32 *c, u32 *out) {
+        u32 v[2];
+        f3b_add(c, c + 2, v);
+        f3_from_bin(v, &out[0], &out[1]);
+        f3b_add(c + 4, c + 6, v);
+        f3_from_bin(v, &out[2], &out[3]);
+    }
+    __device__ static void sadd(const u32 *a, const u32 *b, u32 *r) {
+        F3v re = f3_add(F3v{a[0], a[1]}, F3v{b[0], b[1]});
+        F3v im = f3_add(F3v{a[2], a[3]}, F3v{b[2], b[3]});
+        r[0] = re.u; r[1] = re.s; r[2] = im.u; r[3] = im.s;
+    }
+    __device__ static void scanon(u32 *) {}
+};
+
 }  // namespace gfq

@@ -31,20 +31,23 @@ struct MMArgs {
 // field is q = 4, chosen by gfq_config.variant).
 constexpr int GF4_KARATSUBA = 40;
 
-// fields of the C ABI: F_3, F_5, F_7, GF(4) (q = 4) and GF(8) (q = 8)
-inline bool valid_field(int q) { return q == 3 || q == 4 || q == 5 || q == 7 || q == 8; }
+// fields of the C ABI: F_3, F_5, F_7, GF(4) (q = 4), GF(8) (q = 8) and F_9 (q = 9)
+inline bool valid_field(int q) { return q == 3 || q == 4 || q == 5 || q == 7 || q == 8 || q == 9; }
 
 // planes per packed row; planes per table entry; table rows gathered per slab
-inline int planes_of(int q) { return (q == 3 || q == 4 || q == GF4_KARATSUBA) ? 2 : 3; }
+inline int planes_of(int q) { return (q == 3 || q == 4 || q == GF4_KARATSUBA) ? 2 : (q == 9 ? 4 : 3); }
 inline int table_planes(int q) { return q == GF4_KARATSUBA ? 3 : planes_of(q); }
-inline int gathers_of(int q) { return (q == 3 || q == 4) ? 2 : 3; }
+inline int gathers_of(int q) { return (q == 3 || q == 4) ? 2 : (q == 9 ? 4 : 3); }
 inline bool split_prefix(int q) { return q == 5 || q == 7; }   // FT<q>::SPLIT_PREFIX
 inline int words_of(int64_t cols) { return (int)(((cols + 127) / 128) * 4); }
-// Rows of C per lane: bounded by the accumulator registers (8 planes per word for F_5, 6
-// for F_7, 4 for F_3, 3 for GF(8), 2 for GF(4)).  The work-list kernels of batches use at
+// Rows of C per lane: bounded by the accumulator registers (8 planes per word for F_5 and
+// F_9, 6 for F_7, 4 for F_3, 3 for GF(8), 2 for GF(4)) and the gathered table rows in
+// flight (F_9: two rows of 16 128-bit reads).  The work-list kernels of batches use at
 // most 8.
-inline int max_rows_per_lane(int q) { return q == 5 || q == 7 ? 4 : (q == 4 || q == GF4_KARATSUBA ? 16 : 8); }
-inline int max_rows_per_lane_batch(int q) { return q == 5 ? 2 : (q == 7 ? 4 : 8); }
+inline int max_rows_per_lane(int q) {
+    return q == 9 ? 2 : (q == 5 || q == 7 ? 4 : (q == 4 || q == GF4_KARATSUBA ? 16 : 8));
+}
+inline int max_rows_per_lane_batch(int q) { return q == 5 || q == 9 ? 2 : (q == 7 ? 4 : 8); }
 
 // Table super-row bytes for field q and slab width k: the widest of 256, 128, 64, 32, 16
 // such that both table buffers fit TABLES_LDS (0 if none does).
@@ -54,6 +57,12 @@ inline int srb_for(int q, int k) {
     return 0;
 }
 inline int twd_of(int srb) { return srb >= 64 ? 16 : srb / 4; }   // tile words per plane
+// largest slab width whose tables keep 256-byte super-rows (the batched kernels' layout)
+inline int kmax_wide(int q) {
+    int k = 1;
+    while (k < KMAX && srb_for(q, k + 1) == 256) k++;
+    return k;
+}
 
 // Everything a product launch needs, derived from (field, slab width, requested tile rows).
 struct MMPlan {

@@ -42,8 +42,10 @@ static hipError_t launch_mm(const MMArgs &a0, const MMPlan &plan, hipStream_t st
 
 template <int Q, int TWD, int REP>
 static hipError_t launch_mm_rows(const MMArgs &a, const MMPlan &plan, hipStream_t st) {
-    if (plan.R == 2) return launch_mm<Q, TWD, REP, 2>(a, plan, st);
-    if constexpr (Q == 5 || Q == 7 || (Q == 8 && TWD < 16)) {
+    if (plan.R == 2 || Q == 9) return launch_mm<Q, TWD, REP, 2>(a, plan, st);   // F_9: two only
+    if constexpr (Q == 9) {
+        return hipErrorInvalidValue;
+    } else if constexpr (Q == 5 || Q == 7 || (Q == 8 && TWD < 16)) {
         return launch_mm<Q, TWD, REP, 4>(a, plan, st);       // eight rows per lane would spill
     } else {
         if (plan.R == 4) return launch_mm<Q, TWD, REP, 4>(a, plan, st);
@@ -73,6 +75,7 @@ hipError_t launch_matmul(int q, const MMArgs &a, const MMPlan &plan, hipStream_t
     case GF4_KARATSUBA: return launch_mm_q<GF4_KARATSUBA>(a, plan, st);
     case 5: return launch_mm_q<5>(a, plan, st);
     case 8: return launch_mm_q<8>(a, plan, st);
+    case 9: return launch_mm_q<9>(a, plan, st);
     default: return launch_mm_q<7>(a, plan, st);
     }
 }

@@ -67,6 +67,12 @@ template <int Q> __device__ __forceinline__ u32 encode_spread(u32 v) {
         return (v != 0u ? 1u : 0u) | (v == 2u ? 1u << 8 : 0u);
     }
     if (Q == 4) return (v & 1u) | ((v >> 1) & 1u) << 8;
+    if (Q == 9) {                                 // a0 + 3 a1: the F_3 code of a0, then of a1
+        v %= 9u;
+        const u32 a0 = v % 3u, a1 = v / 3u;
+        return (a0 != 0u ? 1u : 0u) | (a0 == 2u ? 1u << 8 : 0u) | (a1 != 0u ? 1u << 16 : 0u) |
+               (a1 == 2u ? 1u << 24 : 0u);
+    }
     if (Q != 8) v %= (u32)Q;                      // binary digits (F_5, F_7; GF(8): c0, c1, c2)
     return (v & 1u) | ((v >> 1) & 1u) << 8 | ((v >> 2) & 1u) << 16;
 }
@@ -148,6 +154,10 @@ __device__ __forceinline__ void unpack_unit(const u32 *src, uint8_t *dst, int64_
             v = (code & 0x01010101u) + ((code >> 1) & 0x01010101u);            // unit + sign
         } else if (Q == 4 || Q == 8) {
             v = code;
+        } else if (Q == 9) {
+            const u32 a0 = (code & 0x01010101u) + ((code >> 1) & 0x01010101u);     // unit + sign
+            const u32 a1 = ((code >> 2) & 0x01010101u) + ((code >> 3) & 0x01010101u);
+            v = a0 + 3u * a1;
         } else if (Q == 7) {
             const u32 is7 = code & (code >> 1) & (code >> 2) & 0x01010101u;    // 7 = 0
             v = code ^ (is7 * 7u);
@@ -192,6 +202,7 @@ __device__ __forceinline__ u32 encode_spread_q(int q, u32 v) {
     case 4: return encode_spread<4>(v);
     case 5: return encode_spread<5>(v);
     case 8: return encode_spread<8>(v);
+    case 9: return encode_spread<9>(v);
     default: return encode_spread<7>(v);
     }
 }
@@ -221,6 +232,7 @@ __global__ __launch_bounds__(256) void conv_list_kernel(const ConvJob *jobs, int
         case 4: pack_unit<4>(src, j.ld, dst, j.cols, j.W, j.aligned, enc, row, w); break;
         case 5: pack_unit<5>(src, j.ld, dst, j.cols, j.W, j.aligned, enc, row, w); break;
         case 8: pack_unit<8>(src, j.ld, dst, j.cols, j.W, j.aligned, enc, row, w); break;
+        case 9: pack_unit<9>(src, j.ld, dst, j.cols, j.W, j.aligned, enc, row, w); break;
         default: pack_unit<7>(src, j.ld, dst, j.cols, j.W, j.aligned, enc, row, w); break;
         }
     } else {
@@ -231,6 +243,7 @@ __global__ __launch_bounds__(256) void conv_list_kernel(const ConvJob *jobs, int
         case 4: unpack_unit<4>(src, dst, j.ld, j.cols, j.W, j.aligned, row, w); break;
         case 5: unpack_unit<5>(src, dst, j.ld, j.cols, j.W, j.aligned, row, w); break;
         case 8: unpack_unit<8>(src, dst, j.ld, j.cols, j.W, j.aligned, row, w); break;
+        case 9: unpack_unit<9>(src, dst, j.ld, j.cols, j.W, j.aligned, row, w); break;
         default: unpack_unit<7>(src, dst, j.ld, j.cols, j.W, j.aligned, row, w); break;
         }
     }
@@ -285,6 +298,7 @@ hipError_t launch_reduce(int q, const u32 *part, u32 *C, int m, int n, int Wn, i
     case 4: hipLaunchKernelGGL(reduce_partials_kernel<4>, grid, dim3(256), 0, st, part, C, m, n, Wn, splits, stride); break;
     case 5: hipLaunchKernelGGL(reduce_partials_kernel<5>, grid, dim3(256), 0, st, part, C, m, n, Wn, splits, stride); break;
     case 8: hipLaunchKernelGGL(reduce_partials_kernel<8>, grid, dim3(256), 0, st, part, C, m, n, Wn, splits, stride); break;
+    case 9: hipLaunchKernelGGL(reduce_partials_kernel<9>, grid, dim3(256), 0, st, part, C, m, n, Wn, splits, stride); break;
     default: hipLaunchKernelGGL(reduce_partials_kernel<7>, grid, dim3(256), 0, st, part, C, m, n, Wn, splits, stride); break;
     }
     return hipGetLastError();
@@ -305,6 +319,7 @@ hipError_t launch_pack(int q, const uint8_t *src, int64_t ld, u32 *dst, int rows
     case 4: hipLaunchKernelGGL(pack_kernel<4>, grid, dim3(256), 0, st, src, ld, dst, rows, cols, W, aligned); break;
     case 5: hipLaunchKernelGGL(pack_kernel<5>, grid, dim3(256), 0, st, src, ld, dst, rows, cols, W, aligned); break;
     case 8: hipLaunchKernelGGL(pack_kernel<8>, grid, dim3(256), 0, st, src, ld, dst, rows, cols, W, aligned); break;
+    case 9: hipLaunchKernelGGL(pack_kernel<9>, grid, dim3(256), 0, st, src, ld, dst, rows, cols, W, aligned); break;
     default: hipLaunchKernelGGL(pack_kernel<7>, grid, dim3(256), 0, st, src, ld, dst, rows, cols, W, aligned); break;
     }
     return hipGetLastError();
@@ -318,6 +333,7 @@ hipError_t launch_unpack(int q, const u32 *src, uint8_t *dst, int64_t ld, int ro
     case 4: hipLaunchKernelGGL(unpack_kernel<4>, grid, dim3(256), 0, st, src, dst, ld, rows, cols, W, aligned); break;
     case 5: hipLaunchKernelGGL(unpack_kernel<5>, grid, dim3(256), 0, st, src, dst, ld, rows, cols, W, aligned); break;
     case 8: hipLaunchKernelGGL(unpack_kernel<8>, grid, dim3(256), 0, st, src, dst, ld, rows, cols, W, aligned); break;
+    case 9: hipLaunchKernelGGL(unpack_kernel<9>, grid, dim3(256), 0, st, src, dst, ld, rows, cols, W, aligned); break;
     default: hipLaunchKernelGGL(unpack_kernel<7>, grid, dim3(256), 0, st, src, dst, ld, rows, cols, W, aligned); break;
     }
     return hipGetLastError();

@@ -166,7 +166,7 @@ int gfq_tune(int q, int64_t m, int64_t l, int64_t n, int mode, gfq_config *out) 
     } else {
         // a batch of identical products of the class's shape, enough of them for ~1024 tiles
         const int64_t nb = 512;
-        const int kcap = P == 2 ? 7 : 6;
+        const int kcap = kmax_wide(q);
         const int64_t items_per = std::max<int64_t>(1, (m + 255) / 256);
         const int count = (int)std::max<int64_t>(16, std::min<int64_t>(2048, 1024 / items_per));
         const size_t ba = rup(gfq_packed_bytes(q, m, l)), bb = rup(gfq_packed_bytes(q, l, nb));

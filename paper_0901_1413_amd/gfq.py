@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgfq.so")
 
 GFQ_OK = 0
-FIELDS = (3, 4, 5, 7, 8)
+FIELDS = (3, 4, 5, 7, 8, 9)
 
 
 class GfqError(RuntimeError):
@@ -131,7 +131,7 @@ def _bind_stream():
 
 
 def planes(q: int) -> int:
-    return 2 if q in (3, 4) else 3
+    return 2 if q in (3, 4) else (4 if q == 9 else 3)
 
 
 def packed_bytes(q: int, rows: int, cols: int) -> int:

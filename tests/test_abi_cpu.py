@@ -29,6 +29,7 @@ def test_packed_bytes():
     assert gfq.packed_bytes(3, 10, 1) == 10 * 2 * 4 * 4
     assert gfq.packed_bytes(5, 3, 129) == 3 * 3 * 8 * 4
     assert gfq.packed_bytes(8, 3, 129) == 3 * 3 * 8 * 4
+    assert gfq.packed_bytes(9, 3, 129) == 3 * 4 * 8 * 4
     assert gfq.packed_bytes(4, 0, 100) == 0
     assert gfq.packed_bytes(11, 3, 3) == 0
     assert gfq.packed_bytes(3, -1, 3) == 0
@@ -73,7 +74,7 @@ def test_strerror():
 
 def test_choose_config_degenerate_shapes():
     """Empty products have no tiles; choosing their configuration must not divide by zero."""
-    for q in (3, 4, 5, 7, 8):
+    for q in (3, 4, 5, 7, 8, 9):
         for m, l, n in ((0, 4, 4), (4, 4, 0), (0, 0, 0), (5, 0, 7), (1, 1, 1)):
             c = gfq.choose_config(q, m, l, n)
             assert 1 <= c["k"] <= 10 and c["split"] >= 1

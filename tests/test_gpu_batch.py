@@ -42,10 +42,11 @@ def test_mixed_batch(gfq_gpu):
     rng = np.random.default_rng(301)
     specs = []
     for i in range(60):
-        q = int(rng.choice([3, 4, 5, 7, 8]))
+        q = int(rng.choice([3, 4, 5, 7, 8, 9]))
         m, l, n = (int(x) for x in rng.integers(1, 700, size=3))
         specs.append((q, m, l, n))
-    specs += [(3, 1, 1, 1), (5, 1025, 33, 7), (7, 64, 2048, 64), (4, 2048, 64, 1000), (8, 1500, 700, 1200)]
+    specs += [(3, 1, 1, 1), (5, 1025, 33, 7), (7, 64, 2048, 64), (4, 2048, 64, 1000), (8, 1500, 700, 1200),
+              (9, 900, 500, 1300)]
     probs, host = make_batch(g, specs, 302)
     g.matmul_batched(probs)
     g.sync()
@@ -55,7 +56,7 @@ def test_mixed_batch(gfq_gpu):
 def test_batch_replay_and_times(gfq_gpu):
     g = gfq_gpu
     specs = [(3, 300, 200, 100), (5, 64, 64, 64), (7, 1000, 900, 130), (4, 513, 127, 511), (3, 2048, 2048, 2048),
-             (8, 777, 300, 555)]
+             (8, 777, 300, 555), (9, 300, 400, 500)]
     probs, host = make_batch(g, specs, 303)
     b = g.Batch(probs)
     for rep in range(3):
@@ -71,7 +72,7 @@ def test_batch_replay_and_times(gfq_gpu):
 
 def test_batch_degenerate_and_rejection(gfq_gpu):
     g = gfq_gpu
-    specs = [(3, 5, 0, 7), (5, 0, 4, 4), (7, 4, 4, 0), (4, 9, 3, 9), (8, 6, 0, 6)]
+    specs = [(3, 5, 0, 7), (5, 0, 4, 4), (7, 4, 4, 0), (4, 9, 3, 9), (8, 6, 0, 6), (9, 0, 3, 3)]
     probs, host = make_batch(g, specs, 304)
     g.matmul_batched(probs)
     g.sync()

@@ -11,7 +11,7 @@ import oracle
 from paper_0901_1413_amd import inputs
 
 pytestmark = pytest.mark.gpu
-FIELDS = (3, 4, 5, 7, 8)
+FIELDS = (3, 4, 5, 7, 8, 9)
 
 
 def dev(x):
@@ -241,7 +241,8 @@ def test_variant_validation(gfq_gpu):
     import torch
     g = gfq_gpu
     Ap, Bp = g.pack(3, dev(np.zeros((64, 64), np.uint8))), g.pack(3, dev(np.zeros((64, 64), np.uint8)))
-    for q, var in ((3, g.VARIANT_KARATSUBA), (5, g.VARIANT_KARATSUBA), (8, g.VARIANT_KARATSUBA), (4, 2), (4, -1)):
+    for q, var in ((3, g.VARIANT_KARATSUBA), (5, g.VARIANT_KARATSUBA), (8, g.VARIANT_KARATSUBA),
+                   (9, g.VARIANT_KARATSUBA), (4, 2), (4, -1)):
         with pytest.raises(g.GfqError) as e:
             g.matmul(q, Ap, Bp, 64, 64, 64, variant=var)
         assert e.value.status == -1, (q, var)
@@ -260,5 +261,21 @@ def test_gf8_4096_sampled(gfq_gpu, rows, k):
     Ap, Bp = g.pack(q, dev(A)), g.pack(q, dev(B))
     C = g.unpack(q, g.matmul(q, Ap, Bp, N, N, N, rows=rows, k=k), N, N)
     sample = np.unique(np.concatenate([np.arange(0, N, 97), np.arange(N - 5, N)]))
+    got = C[torch.from_numpy(sample).cuda()].cpu().numpy()
+    assert np.array_equal(got, oracle.matmul(q, A[sample], B))
+
+
+@pytest.mark.parametrize("k", [6, 8, 10])
+def test_f9_2048_sampled(gfq_gpu, k):
+    """F_9, A and B 2048 x 2048 uniform, at the widest tables (k = 6) and at narrowed ones
+    (k = 8, 10): sampled rows, spread over every row tile and covering the last one,
+    against the oracle."""
+    import torch
+    g = gfq_gpu
+    q, N = 9, 2048
+    A, B = inputs.pair(q, N, N, N, cfg=221, idx=k)
+    Ap, Bp = g.pack(q, dev(A)), g.pack(q, dev(B))
+    C = g.unpack(q, g.matmul(q, Ap, Bp, N, N, N, k=k), N, N)
+    sample = np.unique(np.concatenate([np.arange(0, N, 61), np.arange(N - 5, N)]))
     got = C[torch.from_numpy(sample).cuda()].cpu().numpy()
     assert np.array_equal(got, oracle.matmul(q, A[sample], B))

@@ -50,7 +50,7 @@ def mixed_specs(seed, count, lo=16, hi=700):
     rng = np.random.default_rng(seed)
     specs = []
     for _ in range(count):
-        q = int(rng.choice([3, 4, 5, 7, 8]))
+        q = int(rng.choice([3, 4, 5, 7, 8, 9]))
         if rng.random() < 0.5:
             n = int(round(np.exp(rng.uniform(np.log(lo), np.log(hi)))))
             specs.append((q, n, n, n))
@@ -187,7 +187,7 @@ def test_server_pool_slices(gfq_gpu):
     try:
         reqs, keep, host = [], [], []
         rng = np.random.default_rng(410)
-        for i, q in enumerate([3, 4, 5, 7, 8, 5]):
+        for i, q in enumerate([3, 4, 5, 7, 8, 9]):
             pa = inputs.matrix(q, P, P, cfg=0, idx=920 + i, which=0)
             pb = inputs.matrix(q, P, P, cfg=0, idx=920 + i, which=1)
             m, l, n = (int(x) for x in rng.integers(1, 400, size=3))
