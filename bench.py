@@ -37,7 +37,7 @@ M = L = N = 8192
 FIELDS = (3, 5)
 PEAK_VALU_OPS = 256 * 64 * 2.4e9          # 32-bit VALU lane-operations per second
 PEAK_HBM = 8.0e12
-SECTIONS = ("c1", "c2_k", "mfma", "c3", "ext", "c4", "c5")
+SECTIONS = ("c1", "c2_k", "mfma", "c3", "ext", "sw", "c4", "c5")
 
 # Per-unit operation counts of the method on gfx950 (three-input bitwise instructions).
 # A unit is (row of C, slab of k rows of B, 32-column word).  Accumulate: the slab's D
@@ -543,6 +543,44 @@ def section_ext(ctx, reps=3, sample_rows=32):
 
 
 # ------------------------------------------------------------------------------------
+# sw: Strassen-Winograd levels over the Four-Russians product (effective 2mln/t)
+# ------------------------------------------------------------------------------------
+
+def section_sw(ctx, reps=5, sizes=(8192, 16384), fields=(3, 5, 4, 8), max_levels=3):
+    torch, gfq, inputs = ctx.torch, ctx.gfq, ctx.inputs
+    res = {}
+    for N in sizes:
+        for q in fields:
+            A, B = inputs.pair(q, N, N, N, cfg=7, idx=q * 100 + N % 97)
+            Ap, Bp = gfq.pack(q, ctx.up(A)), gfq.pack(q, ctx.up(B))
+            del A, B
+            ref = gfq.matmul(q, Ap, Bp, N, N, N)
+            Cp = gfq.empty_packed(q, N, N)
+            row = {}
+            for levels in range(0, max_levels + 1):
+                gfq.matmul_sw(q, Ap, Bp, N, N, N, levels, out=Cp)
+                torch.cuda.synchronize()
+                same = bool(torch.equal(Cp, ref))
+                ev = ctx.events(2)
+                ev[0].record()
+                for _ in range(reps):
+                    gfq.matmul_sw(q, Ap, Bp, N, N, N, levels, out=Cp)
+                ev[1].record()
+                torch.cuda.synchronize()
+                ms = ev[0].elapsed_time(ev[1]) / reps
+                row[f"levels{levels}"] = {"ms": round(ms, 4), "field_ops_per_s": 2.0 * N ** 3 / (ms * 1e-3),
+                                          "equals_plain": same}
+            base = row["levels0"]["ms"]
+            for v in row.values():
+                v["speedup"] = round(base / v["ms"], 3)
+            res[("GF" if q in (4, 8) else "F_") + f"{q}_{N}"] = row
+            del Ap, Bp, ref, Cp
+            torch.cuda.empty_cache()
+    return {"workload": "square N x N products, uniform entries; levels 0 = the plain product; "
+                        "rate = classical 2 N^3 / t", **res}
+
+
+# ------------------------------------------------------------------------------------
 # c4: 4096 products of mixed fields and shapes, batched vs plain
 # ------------------------------------------------------------------------------------
 
@@ -796,6 +834,10 @@ def main():
     if "ext" in sections:
         log("ext")
         res["ext"] = section_ext(ctx)
+        torch.cuda.empty_cache()
+    if "sw" in sections:
+        log("sw")
+        res["sw"] = section_sw(ctx)
         torch.cuda.empty_cache()
     if "c4" in sections:
         log("c4")

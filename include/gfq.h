@@ -129,6 +129,29 @@ typedef struct {
     void *C;
 } gfq_problem;
 
+/* C = A B by Strassen-Winograd recursion with the Four-Russians product as its base case
+ * (the paper applies asymptotically faster algorithms above the Four-Russians method for
+ * large matrices, Section 2 and Section 5).  Each level splits A, B and C into quadrants
+ * and forms C from seven half-size products instead of eight, in Winograd's form:
+ *   S1 = A21 + A22, S2 = S1 - A11, S3 = A11 - A21, S4 = A12 - S2,
+ *   T1 = B12 - B11, T2 = B22 - T1, T3 = B22 - B12, T4 = T2 - B21,
+ *   P1 = A11 B11, P2 = A12 B21, P3 = S4 B22, P4 = A22 T4, P5 = S1 T1, P6 = S2 T2, P7 = S3 T3,
+ *   C11 = P1 + P2, C12 = P1 + P6 + P5 + P3, C21 = P1 + P6 + P7 - P4, C22 = P1 + P6 + P7 + P5.
+ * Rows split at ceil(d / 2) and columns (and the inner dimension) at ceil(d / 2) rounded up
+ * to a multiple of 32; the missing rows and columns of the second halves are zero.  The
+ * arithmetic is exact, so C is the same packed product as gfq_matmul's, byte for byte.
+ * levels  0..GFQ_SW_MAX_LEVELS; 0 is gfq_matmul_config(..., leaf).  All 7^levels leaf
+ *         products run in one launch of the product kernel.
+ * leaf    configuration of the leaf products (NULL: the slab width and route chosen for
+ *         one leaf, the tile height and inner-dimension slices fitted to all leaves together);
+ *         with more than one slice, the leaves' partial products are summed by one launch.
+ * A, B, C and the return codes as for gfq_matmul.  The operand sums and the products of
+ * every level live in the per-(device, stream) workspace (about (7/4)^levels times the
+ * packed sizes of A, B and C together, summed over the levels). */
+#define GFQ_SW_MAX_LEVELS 4
+int gfq_matmul_sw(int q, int64_t m, int64_t l, int64_t n, const void *A, const void *B, void *C, int levels,
+                  const gfq_config *leaf);
+
 /* Run count independent products (fields and shapes may differ) as one launch per
  * (field, tile height) whose workgroups take (product, row tile, column tile) items from a
  * longest-first work list.  problems is a host array.  Each product obeys the gfq_matmul
@@ -281,10 +304,11 @@ int gfq_set_stream(void *hip_stream);
 int gfq_sync(void);
 
 /* Kernel timing for measurement tools (off by default).  While on, every launch of the
- * product kernel and of the partial-sum kernel made by this thread is bracketed by HIP
- * events on the launch stream.  gfq_timing_read waits for the recorded events, returns
- * the summed milliseconds and launch counts of both kernels (any pointer may be NULL) and
- * clears the record. */
+ * product kernel and of the elementwise kernels around it (partial sums of split products,
+ * the splits and merges of gfq_matmul_sw) made by this thread is bracketed by HIP events
+ * on the launch stream.  gfq_timing_read waits for the recorded events, returns the summed
+ * milliseconds and launch counts of the product kernel and of the elementwise kernels
+ * (reduce_*; any pointer may be NULL) and clears the record. */
 int gfq_set_timing(int on);
 int gfq_timing_read(double *product_ms, int *product_launches, double *reduce_ms, int *reduce_launches);
 

@@ -11,6 +11,7 @@
 
 #include "gfq.h"
 #include "gfq_host.h"
+#include "gfq_sw.h"
 #include "gfq_internal.h"
 
 using namespace gfq;
@@ -92,6 +93,38 @@ bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
 // Kernel field of a product over API field q in configuration c.
 int kernel_field(int q, const gfq_config &c) {
     return (q == 4 && c.variant == GFQ_VARIANT_KARATSUBA) ? GF4_KARATSUBA : q;
+}
+
+// Tile height and inner-dimension slices for slab width c->k (kernel field of c) on an
+// m x l x n product: the fewest slab steps on the busiest compute unit, i.e. ceil(workgroups
+// / 256) rounds of (slabs per slice + 2) steps of a TM-row tile (the 2 stand for a slice's
+// prologue and store), each step weighted by the table it builds; among near-equal choices
+// the tallest tile and the fewest slices (least partial-sum traffic) win.
+void fit_tiles(int q, int64_t m, int64_t l, int64_t n, gfq_config *c) {
+    const int kq = kernel_field(q, *c), kk = c->k;
+    const int twd = twd_of(srb_for(kq, kk));
+    const int64_t ctiles = (words_of(n) + twd - 1) / twd;
+    const int64_t S = l > 0 ? (l + kk - 1) / kk : 1;
+    const int64_t max_split = std::max<int64_t>(1, std::min<int64_t>(S / 32, 64));
+    double best_cost = 0.0;
+    c->rows = 256;
+    c->split = 1;
+    for (int rows = 2048; rows >= 256; rows >>= 1) {
+        const MMPlan p = mm_plan(kq, kk, rows);
+        if (!p.srb) continue;
+        const int64_t tiles = ctiles * ((m + p.TM - 1) / p.TM);
+        for (int64_t split = 1; split <= max_split; split *= 2) {
+            if (tiles == 0 && split > 1) break;          // m or n = 0: no tiles
+            const int64_t rounds = (tiles * split + 255) / 256;
+            const double steps = (double)((S + split - 1) / split + 2);
+            const double cost = (double)rounds * p.TM * steps * (1.0 + (double)(1 << kk) / p.TM);
+            if (best_cost == 0.0 || cost < best_cost * 0.98) {
+                best_cost = cost;
+                c->rows = rows;
+                c->split = (int)split;
+            }
+        }
+    }
 }
 
 int check_config(int q, const gfq_config &c) {
@@ -240,34 +273,12 @@ int gfq_choose_config(int q, int64_t m, int64_t l, int64_t n, gfq_config *out) {
     if (!out) return GFQ_ENULL;
     if (m < 0 || l < 0 || n < 0) return GFQ_EDIM;
     if (m > 0 && n > 0 && l > 0 && gfq_tune_lookup(q, m, l, n, 0, out) == GFQ_OK) return GFQ_OK;
-    gfq_config best = {};
-    double best_cost = 0.0;
     // k = 7: the widest slab whose two tables fit LDS with 128-bit reads that conflict at
     // most two ways (measured best or near-best for every field on the large products).
-    // Then the tallest tile (the table build is amortised over its rows) and just enough
-    // slices of the inner dimension to give every compute unit a workgroup.
-    const int kk = (l > 0 && l < 7) ? (int)l : 7;
-    const int twd = twd_of(srb_for(q, kk));
-    const int64_t ctiles = (words_of(n) + twd - 1) / twd;
-    const int64_t S = l > 0 ? (l + kk - 1) / kk : 1;
-    for (int rows = 2048; rows >= 256; rows >>= 1) {
-        const MMPlan p = mm_plan(q, kk, rows);
-        if (!p.srb) continue;
-        const int64_t tiles = ctiles * ((m + p.TM - 1) / p.TM);
-        int64_t split = (tiles >= 256 || tiles == 0) ? 1 : (256 + tiles - 1) / tiles;   // m or n = 0: no tiles
-        split = std::max<int64_t>(1, std::min<int64_t>({split, std::max<int64_t>(1, S / 32), 64}));
-        const int64_t rounds = (tiles * split + 255) / 256;
-        // relative time: rounds x rows x slabs per slice x (accumulate + table build)
-        const double slabs = (double)((S + split - 1) / split);
-        const double cost = (double)rounds * p.TM * slabs * (1.0 + (double)(1 << kk) / p.TM);
-        if (best_cost == 0.0 || cost < best_cost * 0.999) {
-            best_cost = cost;
-            best.k = kk;
-            best.rows = rows;
-            best.split = (int)split;
-        }
-    }
+    gfq_config best = {};
+    best.k = (l > 0 && l < 7) ? (int)l : 7;
     best.variant = GFQ_VARIANT_ROWWISE;
+    fit_tiles(q, m, l, n, &best);
     *out = best;
     return GFQ_OK;
 }
@@ -326,6 +337,115 @@ int gfq_matmul_config(int q, int64_t m, int64_t l, int64_t n, const void *A, con
 
 int gfq_matmul(int q, int64_t m, int64_t l, int64_t n, const void *A, const void *B, void *C) {
     return gfq_matmul_config(q, m, l, n, A, B, C, nullptr);
+}
+
+int gfq_matmul_sw(int q, int64_t m, int64_t l, int64_t n, const void *A, const void *B, void *C, int levels,
+                  const gfq_config *leaf) {
+    int st = validate_mm(q, m, l, n, A, B, C);
+    if (st != GFQ_OK) return st;
+    if (levels < 0 || levels > GFQ_SW_MAX_LEVELS) return GFQ_EINVAL;
+    if (leaf) {
+        st = check_config(q, *leaf);
+        if (st != GFQ_OK) return st;
+    }
+    if (levels == 0) return gfq_matmul_config(q, m, l, n, A, B, C, leaf);
+    if (m == 0 || n == 0) return GFQ_OK;
+    if (l == 0) {
+        hipError_t e = launch_fill_zero(C, gfq_packed_bytes(q, m, n), t_stream);
+        return e == hipSuccess ? GFQ_OK : hip_fail(e, "zero fill");
+    }
+    // dimensions per level (level 0 is the product itself) and the workspace of levels
+    // 1..L: 7^i left operands, right operands and products of level i's shape
+    int64_t dm[GFQ_SW_MAX_LEVELS + 1], dl[GFQ_SW_MAX_LEVELS + 1], dn[GFQ_SW_MAX_LEVELS + 1];
+    size_t offA[GFQ_SW_MAX_LEVELS + 1] = {}, offB[GFQ_SW_MAX_LEVELS + 1] = {}, offC[GFQ_SW_MAX_LEVELS + 1] = {};
+    size_t szA[GFQ_SW_MAX_LEVELS + 1] = {}, szB[GFQ_SW_MAX_LEVELS + 1] = {}, szC[GFQ_SW_MAX_LEVELS + 1] = {};
+    dm[0] = m, dl[0] = l, dn[0] = n;
+    size_t total = 0, count = 1;
+    for (int i = 1; i <= levels; i++) {
+        dm[i] = sw_half_rows(dm[i - 1]);
+        dl[i] = sw_half_cols(dl[i - 1]);
+        dn[i] = sw_half_cols(dn[i - 1]);
+        count *= 7;
+        szA[i] = gfq_packed_bytes(q, dm[i], dl[i]);
+        szB[i] = gfq_packed_bytes(q, dl[i], dn[i]);
+        szC[i] = gfq_packed_bytes(q, dm[i], dn[i]);
+        offA[i] = total, total += count * szA[i];
+        offB[i] = total, total += count * szB[i];
+        offC[i] = total, total += count * szC[i];
+    }
+    // the leaves: one strided launch of count products.  Without a given configuration the
+    // slab width and route are those chosen for one leaf, and the tile height and slices
+    // are fitted to all the leaves' tiles together (count leaves stacked as one tall
+    // product).
+    gfq_config c;
+    if (leaf) {
+        c = *leaf;
+    } else {
+        gfq_choose_config(q, dm[levels], dl[levels], dn[levels], &c);
+        fit_tiles(q, (int64_t)count * dm[levels], dl[levels], dn[levels], &c);
+    }
+    const int kq = kernel_field(q, c);
+    const MMPlan plan = mm_plan(kq, c.k, c.rows);
+    if (!plan.srb) return GFQ_EINVAL;
+    MMArgs a;
+    a.m = (int)dm[levels];
+    a.l = (int)dl[levels];
+    a.n = (int)dn[levels];
+    a.Wl = words_of(a.l);
+    a.Wn = words_of(a.n);
+    a.k = c.k;
+    a.S = (a.l + a.k - 1) / a.k;
+    int split = std::min(c.split, a.S);
+    if ((int64_t)count * a.m >= ((int64_t)1 << 31)) split = 1;   // the partial sums run as one tall matrix
+    a.slabs_per_split = (a.S + split - 1) / split;
+    split = (a.S + a.slabs_per_split - 1) / a.slabs_per_split;
+    // slice s of every leaf goes to a region of its own: the leaves' partial products of a
+    // slice form one tall (count * m) x n matrix, summed by one partial-sum launch
+    const size_t part_off = total;
+    a.split_stride = count * szC[levels] / 4;
+    if (split > 1) total += split * count * szC[levels];
+    void *wsv = nullptr;
+    st = workspace(total, t_stream, &wsv);
+    if (st != GFQ_OK) return st;
+    char *ws = (char *)wsv;
+    hipError_t e = hipSuccess;
+    size_t parents = 1;
+    for (int i = 0; i < levels && e == hipSuccess; i++, parents *= 7) {
+        const u32 *inA = i == 0 ? (const u32 *)A : (const u32 *)(ws + offA[i]);
+        const u32 *inB = i == 0 ? (const u32 *)B : (const u32 *)(ws + offB[i]);
+        e = timed(1, [&] {
+            return launch_sw_split(q, true, inA, szA[i] / 4, (u32 *)(ws + offA[i + 1]), szA[i + 1] / 4, (int)parents,
+                                   (int)dm[i], (int)dl[i], (int)dm[i + 1], (int)dl[i + 1], t_stream);
+        });
+        if (e == hipSuccess)
+            e = timed(1, [&] {
+                return launch_sw_split(q, false, inB, szB[i] / 4, (u32 *)(ws + offB[i + 1]), szB[i + 1] / 4,
+                                       (int)parents, (int)dl[i], (int)dn[i], (int)dl[i + 1], (int)dn[i + 1], t_stream);
+            });
+    }
+    if (e != hipSuccess) return hip_fail(e, "Strassen-Winograd split");
+    a.A = (const u32 *)(ws + offA[levels]);
+    a.B = (const u32 *)(ws + offB[levels]);
+    a.out = (u32 *)(ws + (split > 1 ? part_off : offC[levels]));
+    const MMStrides sd = {(int)count, szA[levels] / 4, szB[levels] / 4, szC[levels] / 4};
+    e = timed(0, [&] { return launch_matmul_strided(kq, a, plan, sd, t_stream); });
+    if (e != hipSuccess) return hip_fail(e, "matmul launch");
+    if (split > 1) {
+        e = timed(1, [&] {
+            return launch_reduce(q, (const u32 *)(ws + part_off), (u32 *)(ws + offC[levels]), (int)(count * a.m), a.n,
+                                 a.Wn, split, a.split_stride, t_stream);
+        });
+        if (e != hipSuccess) return hip_fail(e, "reduce launch");
+    }
+    parents = count / 7;
+    for (int i = levels - 1; i >= 0 && e == hipSuccess; i--, parents /= 7) {
+        u32 *out = i == 0 ? (u32 *)C : (u32 *)(ws + offC[i]);
+        e = timed(1, [&] {
+            return launch_sw_merge(q, (const u32 *)(ws + offC[i + 1]), szC[i + 1] / 4, out, szC[i] / 4, (int)parents,
+                                   (int)dm[i], (int)dn[i], (int)dm[i + 1], (int)dn[i + 1], t_stream);
+        });
+    }
+    return e == hipSuccess ? GFQ_OK : hip_fail(e, "Strassen-Winograd merge");
 }
 
 

@@ -46,6 +46,7 @@ template <> struct FT<3> {
         F3v z = f3_add(F3v{a[0], a[1]}, F3v{b[0], b[1]});
         r[0] = z.u; r[1] = z.s;
     }
+    __device__ static void sneg(const u32 *a, u32 *r) { F3v z = f3_neg(F3v{a[0], a[1]}); r[0] = z.u; r[1] = z.s; }
     __device__ static void scanon(u32 *) {}
 };
 
@@ -79,6 +80,7 @@ template <> struct FT<7> {
         out[0] = z.b0; out[1] = z.b1; out[2] = z.b2;
     }
     __device__ static void sadd(const u32 *a, const u32 *b, u32 *r) { tadd(a, b, r); }
+    __device__ static void sneg(const u32 *a, u32 *r) { r[0] = ~a[0]; r[1] = ~a[1]; r[2] = ~a[2]; }
     __device__ static void scanon(u32 *v) {
         P3v z = f7_reduce(P3v{v[0], v[1], v[2]});
         v[0] = z.b0; v[1] = z.b1; v[2] = z.b2;
@@ -114,6 +116,10 @@ template <> struct FT<5> {
         out[0] = z.b0; out[1] = z.b1; out[2] = z.b2;
     }
     __device__ static void sadd(const u32 *a, const u32 *b, u32 *r) { tadd(a, b, r); }
+    __device__ static void sneg(const u32 *a, u32 *r) {
+        P3v z = f5_neg(P3v{a[0], a[1], a[2]});
+        r[0] = z.b0; r[1] = z.b1; r[2] = z.b2;
+    }
     __device__ static void scanon(u32 *v) {
         P3v z = f5_reduce(P3v{v[0], v[1], v[2]});
         v[0] = z.b0; v[1] = z.b1; v[2] = z.b2;
@@ -137,6 +143,7 @@ template <> struct FT<4> {
     }
     __device__ static void finish(const u32 *c, u32 *out) { out[0] = c[0]; out[1] = c[1]; }
     __device__ static void sadd(const u32 *a, const u32 *b, u32 *r) { tadd(a, b, r); }
+    __device__ static void sneg(const u32 *a, u32 *r) { r[0] = a[0]; r[1] = a[1]; }
     __device__ static void scanon(u32 *) {}
 };
 
@@ -182,6 +189,7 @@ template <> struct FT<8> {
     __device__ static void accumulate(u32 *c, const u32 (*t)[P]) { g8_acc(c, t[0], t[1], t[2]); }
     __device__ static void finish(const u32 *c, u32 *out) { out[0] = c[0]; out[1] = c[1]; out[2] = c[2]; }
     __device__ static void sadd(const u32 *a, const u32 *b, u32 *r) { tadd(a, b, r); }
+    __device__ static void sneg(const u32 *a, u32 *r) { r[0] = a[0]; r[1] = a[1]; r[2] = a[2]; }
     __device__ static void scanon(u32 *) {}
 };
 
@@ -221,6 +229,10 @@ template <> struct FT<9> {
     __device__ static void sadd(const u32 *a, const u32 *b, u32 *r) {
         F3v re = f3_add(F3v{a[0], a[1]}, F3v{b[0], b[1]});
         F3v im = f3_add(F3v{a[2], a[3]}, F3v{b[2], b[3]});
+        r[0] = re.u; r[1] = re.s; r[2] = im.u; r[3] = im.s;
+    }
+    __device__ static void sneg(const u32 *a, u32 *r) {
+        F3v re = f3_neg(F3v{a[0], a[1]}), im = f3_neg(F3v{a[2], a[3]});
         r[0] = re.u; r[1] = re.s; r[2] = im.u; r[3] = im.s;
     }
     __device__ static void scanon(u32 *) {}

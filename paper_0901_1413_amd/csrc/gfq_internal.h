@@ -112,7 +112,25 @@ inline MMPlan mm_plan(int q, int k, int rowsTile) {
     return p;
 }
 
+// count products of one shape in one launch: product p reads A + p * A_stride and
+// B + p * B_stride and writes out + p * out_stride (strides in 32-bit words)
+struct MMStrides {
+    int count;
+    size_t A, B, out;
+};
+
 hipError_t launch_matmul(int q, const MMArgs &a, const MMPlan &plan, hipStream_t st);
+hipError_t launch_matmul_strided(int q, const MMArgs &a, const MMPlan &plan, const MMStrides &sd, hipStream_t st);
+
+// Strassen–Winograd levels: the seven signed quadrant sums of every one of `parents`
+// packed matrices (stride in_stride words, rows x cols) into 7 * parents matrices (stride
+// out_stride, hrows x hcols, hcols a multiple of 32); `left` selects the coefficients of
+// the left or the right operand.  merge: quadrants of every parent product (rows x cols)
+// from its seven half-size products.
+hipError_t launch_sw_split(int q, bool left, const u32 *in, size_t in_stride, u32 *out, size_t out_stride,
+                           int parents, int rows, int cols, int hrows, int hcols, hipStream_t st);
+hipError_t launch_sw_merge(int q, const u32 *prods, size_t prod_stride, u32 *out, size_t out_stride, int parents,
+                           int rows, int cols, int hrows, int hcols, hipStream_t st);
 hipError_t launch_reduce(int q, const u32 *part, u32 *C, int m, int n, int Wn, int splits, size_t stride, hipStream_t st);
 // One pack (uint8 -> planes) or unpack (planes -> uint8) job of a conversion list.  The
 // uint8 side has leading dimension ld; the packed side has W words per plane row.  Jobs are

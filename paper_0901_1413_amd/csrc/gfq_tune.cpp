@@ -128,7 +128,6 @@ int gfq_tune(int q, int64_t m, int64_t l, int64_t n, int mode, gfq_config *out) 
     hipStream_t st = current_stream();
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return GFQ_EHIP;
-    const int P = planes_of(q);
     gfq_config best = {};
     double best_rate = 0.0;
     int status = GFQ_OK;

@@ -71,6 +71,8 @@ _SIGS = {
     "gfq_matmul_config": (ctypes.c_int, [ctypes.c_int, _I64, _I64, _I64, _VP, _VP, _VP,
                                          ctypes.POINTER(Config)]),
     "gfq_choose_config": (ctypes.c_int, [ctypes.c_int, _I64, _I64, _I64, ctypes.POINTER(Config)]),
+    "gfq_matmul_sw": (ctypes.c_int, [ctypes.c_int, _I64, _I64, _I64, _VP, _VP, _VP, ctypes.c_int,
+                                     ctypes.POINTER(Config)]),
     "gfq_matmul_batched": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(Problem)]),
     "gfq_batch_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(Problem), ctypes.POINTER(_VP)]),
     "gfq_batch_launch": (ctypes.c_int, [_VP]),
@@ -200,6 +202,33 @@ def matmul(q: int, A, B, m: int, l: int, n: int, out=None, k: int = 0, rows: int
     else:
         _check(load().gfq_matmul(q, m, l, n, _VP(A.data_ptr()), _VP(B.data_ptr()), _VP(out.data_ptr())),
                "gfq_matmul")
+    return out
+
+
+SW_MAX_LEVELS = 4
+
+
+def matmul_sw(q: int, A, B, m: int, l: int, n: int, levels: int, out=None, k: int = 0, rows: int = 0,
+              variant=None):
+    """C = A B by `levels` levels of Strassen-Winograd over the Four-Russians product
+    (gfq_matmul_sw); k, rows and variant override the leaf configuration."""
+    if out is None:
+        out = empty_packed(q, m, n, A.device)
+    _bind_stream()
+    cp = None
+    if k or rows or variant is not None:
+        c = Config()
+        _check(load().gfq_choose_config(q, m, l, n, ctypes.byref(c)), "gfq_choose_config")
+        if k:
+            c.k = k
+        if rows:
+            c.rows = rows
+        if variant is not None:
+            c.variant = variant
+        c.split = 1
+        cp = ctypes.byref(c)
+    _check(load().gfq_matmul_sw(q, m, l, n, _VP(A.data_ptr()), _VP(B.data_ptr()), _VP(out.data_ptr()), levels, cp),
+           "gfq_matmul_sw")
     return out
 
 
