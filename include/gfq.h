@@ -101,13 +101,22 @@ int gfq_matmul(int q, int64_t m, int64_t l, int64_t n, const void *A, const void
  *          F_9 are capped by their register use; the library covers what fits)
  *   split  number of slices of the inner dimension computed by separate workgroups and
  *          summed afterwards, 1..64
- *   variant how GF(4) products are formed (other fields: GFQ_VARIANT_ROWWISE only):
- *          GFQ_VARIANT_ROWWISE  row-wise additive basis {1, x}: two table rows of two
- *                               planes per slab (Section 2 with the encoding of 4.3);
- *          GFQ_VARIANT_KARATSUBA matrix-level Karatsuba over F_2 (Section 4.3): three F_2
- *                               products, C0 = A0 B0 + A1 B1 and C1 = (A0 + A1)(B0 + B1) +
- *                               A0 B0, on three-plane tables (one plane read per product)
- *          Both give the same packed product; batches use the row-wise form. */
+ *   variant how extension-field products are formed (F_3, F_5, F_7: GFQ_VARIANT_ROWWISE
+ *          only):
+ *          GFQ_VARIANT_ROWWISE  row-wise additive basis (Section 2 with the encodings of
+ *                               4.3): GF(4) {1, x}, GF(8) {1, x, x^2}, F_9 {1, -1, i, -i};
+ *          GFQ_VARIANT_KARATSUBA matrix-level products over the prime subfield (Section 4.3),
+ *                               one plane-table per subfield product:
+ *                               GF(4): three F_2 products, C0 = A0 B0 + A1 B1,
+ *                                 C1 = (A0 + A1)(B0 + B1) + A0 B0;
+ *                               GF(8): six F_2 products by the trinomial formula,
+ *                                 P_ii = Ai Bi, P_ij = (Ai + Aj)(Bi + Bj), reduced by
+ *                                 x^3 + x + 1: C0 = P00 + P11 + P12 + P22,
+ *                                 C1 = P00 + P01 + P12, C2 = P00 + P02 + P11;
+ *                               F_9: three F_3 products, C0 = A0 B0 - A1 B1,
+ *                                 C1 = (A0 + A1)(B0 + B1) - A0 B0 - A1 B1.
+ *          Both give the same packed product; batches use the row-wise form.  The GF(8) and
+ *          F_9 matrix routes hold six planes per table entry and take k <= 9. */
 #define GFQ_VARIANT_ROWWISE 0
 #define GFQ_VARIANT_KARATSUBA 1
 typedef struct { int k; int rows; int split; int variant; } gfq_config;

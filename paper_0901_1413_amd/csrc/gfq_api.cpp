@@ -92,7 +92,7 @@ bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
 
 // Kernel field of a product over API field q in configuration c.
 int kernel_field(int q, const gfq_config &c) {
-    return (q == 4 && c.variant == GFQ_VARIANT_KARATSUBA) ? GF4_KARATSUBA : q;
+    return route_field(q, c.variant);
 }
 
 // Tile height and inner-dimension slices for slab width c->k (kernel field of c) on an
@@ -131,7 +131,8 @@ int check_config(int q, const gfq_config &c) {
     if (c.k < 1 || c.k > KMAX) return GFQ_EINVAL;
     if (c.rows != 256 && c.rows != 512 && c.rows != 1024 && c.rows != 2048) return GFQ_EINVAL;
     if (c.split < 1 || c.split > 64) return GFQ_EINVAL;
-    if (c.variant != GFQ_VARIANT_ROWWISE && !(c.variant == GFQ_VARIANT_KARATSUBA && q == 4)) return GFQ_EINVAL;
+    if (c.variant != GFQ_VARIANT_ROWWISE && !(c.variant == GFQ_VARIANT_KARATSUBA && has_matrix_route(q)))
+        return GFQ_EINVAL;
     if (mm_plan(kernel_field(q, c), c.k, c.rows).srb == 0) return GFQ_EINVAL;
     return GFQ_OK;
 }

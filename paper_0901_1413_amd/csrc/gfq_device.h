@@ -238,4 +238,83 @@ template <> struct FT<9> {
     __device__ static void scanon(u32 *) {}
 };
 
+// GF(8) by the trinomial formula of Section 4.3, at matrix level over F_2: with A = A0 +
+// x A1 + x^2 A2 and B alike, the six F_2 products P_ii = Ai Bi and P_ij = (Ai + Aj)(Bi + Bj)
+// give the coefficients of A B before reduction; modulo x^3 + x + 1,
+//   C0 = P00 + P11 + P12 + P22,  C1 = P00 + P01 + P12,  C2 = P00 + P02 + P11.
+// A table entry holds the six F_2 tables of the slab (planes B0, B1, B2, B0 + B1,
+// B0 + B2, B1 + B2); a row gathers one plane of six entries.  Same operands and product as
+// FT<8>; selected by the configuration.
+template <> struct FT<GF8_TRINOMIAL> {
+    static constexpr int P = 3, PT = 6, D = 6, GP = 1, PA = 3;
+    static constexpr bool SPLIT_PREFIX = false;
+    static constexpr int gplane(int d, int) { return d; }
+    __device__ static void phis(const u32 *x, u32 *f) {
+        f[0] = x[0]; f[1] = x[1]; f[2] = x[2]; f[3] = x[0] ^ x[1]; f[4] = x[0] ^ x[2]; f[5] = x[1] ^ x[2];
+    }
+    __device__ static void to_table(const u32 *x, u32 *t) { phis(x, t); }
+    __device__ static void tadd(const u32 *a, const u32 *b, u32 *r) {
+        for (int i = 0; i < PT; i++) r[i] = a[i] ^ b[i];
+    }
+    __device__ static void tsub(const u32 *a, const u32 *b, u32 *r) { tadd(a, b, r); }
+    __device__ static void acc_init(u32 *c, int) { c[0] = c[1] = c[2] = 0u; }
+    // t[d][0]: P00, P11, P22, P01, P02, P12
+    __device__ static void accumulate(u32 *c, const u32 (*t)[GP]) {
+        const u32 u = t[0][0] ^ t[5][0], v = t[1][0] ^ t[2][0], w = t[0][0] ^ t[1][0];
+        c[0] = xor3(c[0], u, v);          // P00 + P12 + P11 + P22
+        c[1] = xor3(c[1], u, t[3][0]);    // P00 + P12 + P01
+        c[2] = xor3(c[2], w, t[4][0]);    // P00 + P11 + P02
+    }
+    __device__ static void finish(const u32 *c, u32 *out) { out[0] = c[0]; out[1] = c[1]; out[2] = c[2]; }
+};
+
+// F_9 by Karatsuba at matrix level over F_3 (Section 4.3): with A = A0 + i A1 and B = B0 +
+// i B1, A B = (P00 - P11) + i (Pss - P00 - P11) for the three F_3 products P00 = A0 B0,
+// P11 = A1 B1, Pss = (A0 + A1)(B0 + B1).  A table entry holds the slab's three F_3 tables
+// (rows B0, B1, B0 + B1 as binary residues mod 3, two planes each); a row gathers, per
+// product, the entries of its coefficient's [= 1] and [= -1] bits (two planes each) into
+// that product's own carry-save pair; the products are combined once, at the end.  Same
+// operands and product as FT<9>; selected by the configuration.
+template <> struct FT<F9_KARATSUBA> {
+    static constexpr int P = 4, PT = 6, D = 6, GP = 2, PA = 12;
+    static constexpr bool SPLIT_PREFIX = false;
+    static constexpr int gplane(int d, int p) { return (d >> 1) * 2 + p; }
+    __device__ static void phis(const u32 *x, u32 *f) {
+        const F3v s = f3_add(F3v{x[0], x[1]}, F3v{x[2], x[3]});   // a0 + a1
+        f[0] = x[0] ^ x[1]; f[1] = x[1];
+        f[2] = x[2] ^ x[3]; f[3] = x[3];
+        f[4] = s.u ^ s.s; f[5] = s.s;
+    }
+    __device__ static void to_table(const u32 *x, u32 *t) {
+        f3_to_bin(x[0], x[1], t);
+        f3_to_bin(x[2], x[3], t + 2);
+        f3b_add(t, t + 2, t + 4);
+    }
+    __device__ static void tadd(const u32 *a, const u32 *b, u32 *r) {
+        f3b_add(a, b, r); f3b_add(a + 2, b + 2, r + 2); f3b_add(a + 4, b + 4, r + 4);
+    }
+    __device__ static void tsub(const u32 *a, const u32 *b, u32 *r) {
+        f3b_sub(a, b, r); f3b_sub(a + 2, b + 2, r + 2); f3b_sub(a + 4, b + 4, r + 4);
+    }
+    __device__ static void acc_init(u32 *c, int) { for (int i = 0; i < PA; i++) c[i] = 0u; }
+    __device__ static void accumulate(u32 *c, const u32 (*t)[GP]) {
+#pragma unroll
+        for (int j = 0; j < 3; j++) {                     // P00, P11, Pss
+            csa_step<2>(c + 4 * j, c + 4 * j + 2, t[2 * j]);
+            csa_step_neg<2>(c + 4 * j, c + 4 * j + 2, t[2 * j + 1]);
+        }
+    }
+    __device__ static void finish(const u32 *c, u32 *out) {
+        u32 p00[2], p11[2], pss[2], re[2], im[2], t[2];
+        f3b_add(c, c + 2, p00);
+        f3b_add(c + 4, c + 6, p11);
+        f3b_add(c + 8, c + 10, pss);
+        f3b_sub(p00, p11, re);
+        f3b_sub(pss, p00, t);
+        f3b_sub(t, p11, im);
+        f3_from_bin(re, &out[0], &out[1]);
+        f3_from_bin(im, &out[2], &out[3]);
+    }
+};
+
 }  // namespace gfq

@@ -27,17 +27,34 @@ struct MMArgs {
     u32 tb1;               // LDS offset of the second table (set by the launcher)
 };
 
-// Kernel field of GF(4) products computed by matrix-level Karatsuba over F_2 (the API
-// field is q = 4, chosen by gfq_config.variant).
+// Kernel fields of the matrix-level product routes (chosen by gfq_config.variant for the
+// API fields q = 4, 8, 9): GF(4) by Karatsuba over F_2, GF(8) by the trinomial formula over
+// F_2, F_9 by Karatsuba over F_3.
 constexpr int GF4_KARATSUBA = 40;
+constexpr int GF8_TRINOMIAL = 80;
+constexpr int F9_KARATSUBA = 90;
+
+// API fields with a matrix-level product route (gfq_config.variant 1), and the kernel
+// field of a product over API field q in route `variant` (0: row-wise)
+inline bool has_matrix_route(int q) { return q == 4 || q == 8 || q == 9; }
+inline int route_field(int q, int variant) {
+    if (variant != 1) return q;
+    return q == 4 ? GF4_KARATSUBA : (q == 8 ? GF8_TRINOMIAL : (q == 9 ? F9_KARATSUBA : q));
+}
 
 // fields of the C ABI: F_3, F_5, F_7, GF(4) (q = 4), GF(8) (q = 8) and F_9 (q = 9)
 inline bool valid_field(int q) { return q == 3 || q == 4 || q == 5 || q == 7 || q == 8 || q == 9; }
 
 // planes per packed row; planes per table entry; table rows gathered per slab
-inline int planes_of(int q) { return (q == 3 || q == 4 || q == GF4_KARATSUBA) ? 2 : (q == 9 ? 4 : 3); }
-inline int table_planes(int q) { return q == GF4_KARATSUBA ? 3 : planes_of(q); }
-inline int gathers_of(int q) { return (q == 3 || q == 4) ? 2 : (q == 9 ? 4 : 3); }
+inline int planes_of(int q) {
+    return (q == 3 || q == 4 || q == GF4_KARATSUBA) ? 2 : ((q == 9 || q == F9_KARATSUBA) ? 4 : 3);
+}
+inline int table_planes(int q) {
+    return q == GF4_KARATSUBA ? 3 : ((q == GF8_TRINOMIAL || q == F9_KARATSUBA) ? 6 : planes_of(q));
+}
+inline int gathers_of(int q) {
+    return (q == 3 || q == 4) ? 2 : (q == 9 ? 4 : ((q == GF8_TRINOMIAL || q == F9_KARATSUBA) ? 6 : 3));
+}
 inline bool split_prefix(int q) { return q == 5 || q == 7; }   // FT<q>::SPLIT_PREFIX
 inline int words_of(int64_t cols) { return (int)(((cols + 127) / 128) * 4); }
 // Rows of C per lane: bounded by the accumulator registers (8 planes per word for F_5 and
@@ -45,7 +62,7 @@ inline int words_of(int64_t cols) { return (int)(((cols + 127) / 128) * 4); }
 // flight (F_9: two rows of 16 128-bit reads).  The work-list kernels of batches use at
 // most 8.
 inline int max_rows_per_lane(int q) {
-    return q == 9 ? 2 : (q == 5 || q == 7 ? 4 : (q == 4 || q == GF4_KARATSUBA ? 16 : 8));
+    return (q == 9 || q == F9_KARATSUBA) ? 2 : (q == 5 || q == 7 ? 4 : (q == 4 || q == GF4_KARATSUBA ? 16 : 8));
 }
 inline int max_rows_per_lane_batch(int q) { return q == 5 || q == 9 ? 2 : (q == 7 ? 4 : 8); }
 
@@ -101,7 +118,7 @@ inline MMPlan mm_plan(int q, int k, int rowsTile) {
     r = r <= 2 ? 2 : (r <= 4 ? 4 : (r <= 8 ? 8 : 16));
     if (r > max_rows_per_lane(q)) r = max_rows_per_lane(q);
     if (r > 8 && p.twd < 16) r = 8;              // narrow tiles: 16 rows per lane would spill
-    if (r > 4 && p.twd < 16 && q == 8) r = 4;    // ... and for GF(8) eight would
+    if (r > 4 && p.twd < 16 && (q == 8 || q == GF8_TRINOMIAL)) r = 4;    // ... and for GF(8) eight would
     for (; r >= 2; r /= 2) {
         p.R = r;
         p.TM = NT_MM / lpr * r;

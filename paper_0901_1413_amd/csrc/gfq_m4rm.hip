@@ -50,10 +50,11 @@ static hipError_t launch_mm(const MMArgs &a0, const MMPlan &plan, const MMStride
 
 template <int Q, int TWD, int REP>
 static hipError_t launch_mm_rows(const MMArgs &a, const MMPlan &plan, const MMStrides &sd, hipStream_t st) {
-    if (plan.R == 2 || Q == 9) return launch_mm<Q, TWD, REP, 2>(a, plan, sd, st);   // F_9: two only
-    if constexpr (Q == 9) {
+    constexpr bool two_only = Q == 9 || Q == F9_KARATSUBA;   // F_9: two rows per lane only
+    if (plan.R == 2 || two_only) return launch_mm<Q, TWD, REP, 2>(a, plan, sd, st);
+    if constexpr (two_only) {
         return hipErrorInvalidValue;
-    } else if constexpr (Q == 5 || Q == 7 || (Q == 8 && TWD < 16)) {
+    } else if constexpr (Q == 5 || Q == 7 || ((Q == 8 || Q == GF8_TRINOMIAL) && TWD < 16)) {
         return launch_mm<Q, TWD, REP, 4>(a, plan, sd, st);       // eight rows per lane would spill
     } else {
         if (plan.R == 4) return launch_mm<Q, TWD, REP, 4>(a, plan, sd, st);
@@ -89,6 +90,8 @@ hipError_t launch_matmul_strided(int q, const MMArgs &a, const MMPlan &plan, con
     case 5: return launch_mm_q<5>(a, plan, sd, st);
     case 8: return launch_mm_q<8>(a, plan, sd, st);
     case 9: return launch_mm_q<9>(a, plan, sd, st);
+    case GF8_TRINOMIAL: return launch_mm_q<GF8_TRINOMIAL>(a, plan, sd, st);
+    case F9_KARATSUBA: return launch_mm_q<F9_KARATSUBA>(a, plan, sd, st);
     default: return launch_mm_q<7>(a, plan, sd, st);
     }
 }

@@ -142,11 +142,11 @@ int gfq_tune(int q, int64_t m, int64_t l, int64_t n, int mode, gfq_config *out) 
             char *A = (char *)base, *B = A + ba, *C = B + bb;
             const int reps = ops < 1e10 ? 7 : 3;
             // GF(4) also tries its Karatsuba form
-            const int nvar = q == 4 ? 2 : 1;
+            const int nvar = has_matrix_route(q) ? 2 : 1;
             for (int var = 0; var < nvar; var++)
             for (int k = 3; k <= KMAX; k++) {
                 if (k > l) break;
-                const int kq = var == GFQ_VARIANT_KARATSUBA ? GF4_KARATSUBA : q;
+                const int kq = route_field(q, var);
                 for (int rows = 256; rows <= 2048; rows *= 2) {
                     const MMPlan pl = mm_plan(kq, k, rows);
                     if (!pl.srb) continue;
@@ -248,9 +248,9 @@ int gfq_tune_load(const char *path) {
             continue;
         }
         gfq_config c = {k, rows, split, variant};
-        const bool var_ok = variant == GFQ_VARIANT_ROWWISE || (variant == GFQ_VARIANT_KARATSUBA && q == 4);
+        const bool var_ok = variant == GFQ_VARIANT_ROWWISE || (variant == GFQ_VARIANT_KARATSUBA && has_matrix_route(q));
         if (k < 1 || k > KMAX || !var_ok ||
-            mm_plan(variant == GFQ_VARIANT_KARATSUBA ? GF4_KARATSUBA : q, k, rows).srb == 0 || split < 1 ||
+            mm_plan(route_field(q, variant), k, rows).srb == 0 || split < 1 ||
             split > 64) {
             status = GFQ_EINVAL;
             continue;

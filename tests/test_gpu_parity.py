@@ -208,41 +208,68 @@ def test_more_row_tiles_than_one_grid_holds(gfq_gpu):
     assert np.array_equal(got, oracle.matmul(q, A[rows], B))
 
 
-# GF(4) by matrix-level Karatsuba over F_2 (the second way to form GF(4) products): every
+# The matrix-level routes (gfq_config.variant = VARIANT_KARATSUBA): GF(4) by Karatsuba over
+# F_2, GF(8) by the trinomial formula over F_2, F_9 by Karatsuba over F_3.  Every
 # configuration gives the oracle's product, byte for byte in packed form.
+MATRIX_ROUTE_FIELDS = (4, 8, 9)
+
+
+@pytest.mark.parametrize("q", MATRIX_ROUTE_FIELDS)
 @pytest.mark.parametrize("shape", [(1, 1, 1), (5, 7, 3), (33, 65, 129), (130, 259, 1057), (257, 33, 4099),
                                    (600, 1000, 70)])
-def test_gf4_karatsuba_shapes(gfq_gpu, shape):
+def test_matrix_route_shapes(gfq_gpu, q, shape):
     m, l, n = shape
-    A, B = inputs.pair(4, m, l, n, cfg=210, idx=m * 7 + n)
-    check(gfq_gpu, 4, A, B, variant=gfq_gpu.VARIANT_KARATSUBA)
+    A, B = inputs.pair(q, m, l, n, cfg=210, idx=m * 7 + n)
+    check(gfq_gpu, q, A, B, variant=gfq_gpu.VARIANT_KARATSUBA)
 
 
+@pytest.mark.parametrize("q", MATRIX_ROUTE_FIELDS)
 @pytest.mark.parametrize("k", list(range(1, 11)))
-def test_gf4_karatsuba_every_k(gfq_gpu, k):
-    A, B = inputs.pair(4, 97, 301, 1100, cfg=211, idx=k)
-    check(gfq_gpu, 4, A, B, k=k, variant=gfq_gpu.VARIANT_KARATSUBA)
+def test_matrix_route_every_k(gfq_gpu, q, k):
+    A, B = inputs.pair(q, 97, 301, 1100, cfg=211, idx=k)
+    if q in (8, 9) and k == 10:
+        # six-plane tables: two of 2^10 entries do not fit LDS even at 16-byte super-rows
+        with pytest.raises(gfq_gpu.GfqError) as e:
+            check(gfq_gpu, q, A, B, k=k, variant=gfq_gpu.VARIANT_KARATSUBA)
+        assert e.value.status == -1
+        return
+    check(gfq_gpu, q, A, B, k=k, variant=gfq_gpu.VARIANT_KARATSUBA)
 
 
+@pytest.mark.parametrize("q", MATRIX_ROUTE_FIELDS)
 @pytest.mark.parametrize("rows,split", [(256, 1), (512, 1), (1024, 1), (2048, 1), (256, 3), (2048, 7), (1024, 64)])
-def test_gf4_karatsuba_tiles_and_splits(gfq_gpu, rows, split):
-    A, B = inputs.pair(4, 600, 700, 300, cfg=212, idx=rows + split)
-    check(gfq_gpu, 4, A, B, rows=rows, split=split, variant=gfq_gpu.VARIANT_KARATSUBA)
+def test_matrix_route_tiles_and_splits(gfq_gpu, q, rows, split):
+    A, B = inputs.pair(q, 600, 700, 300, cfg=212, idx=rows + split)
+    check(gfq_gpu, q, A, B, rows=rows, split=split, variant=gfq_gpu.VARIANT_KARATSUBA)
 
 
-def test_gf4_karatsuba_sparse_and_identity(gfq_gpu):
-    A, B = inputs.pair(4, 300, 513, 257, cfg=213, idx=0, density=0.1)
-    check(gfq_gpu, 4, A, B, variant=gfq_gpu.VARIANT_KARATSUBA)
+@pytest.mark.parametrize("q", MATRIX_ROUTE_FIELDS)
+def test_matrix_route_sparse_and_identity(gfq_gpu, q):
+    A, B = inputs.pair(q, 300, 513, 257, cfg=213, idx=0, density=0.1)
+    check(gfq_gpu, q, A, B, variant=gfq_gpu.VARIANT_KARATSUBA)
     eye = np.eye(513, dtype=np.uint8)
-    check(gfq_gpu, 4, eye, B, variant=gfq_gpu.VARIANT_KARATSUBA)
+    check(gfq_gpu, q, eye, B, variant=gfq_gpu.VARIANT_KARATSUBA)
+
+
+@pytest.mark.parametrize("q", MATRIX_ROUTE_FIELDS)
+def test_matrix_route_equals_rowwise_2048(gfq_gpu, q):
+    """2048^3: the two routes give the same packed product byte for byte."""
+    import torch
+    g = gfq_gpu
+    N = 2048
+    A, B = inputs.pair(q, N, N, N, cfg=214, idx=q)
+    Ap, Bp = g.pack(q, dev(A)), g.pack(q, dev(B))
+    rw = g.matmul(q, Ap, Bp, N, N, N, variant=g.VARIANT_ROWWISE)
+    mr = g.matmul(q, Ap, Bp, N, N, N, variant=g.VARIANT_KARATSUBA)
+    assert torch.equal(rw, mr)
 
 
 def test_variant_validation(gfq_gpu):
     import torch
     g = gfq_gpu
     Ap, Bp = g.pack(3, dev(np.zeros((64, 64), np.uint8))), g.pack(3, dev(np.zeros((64, 64), np.uint8)))
-    for q, var in ((3, g.VARIANT_KARATSUBA), (5, g.VARIANT_KARATSUBA), (8, g.VARIANT_KARATSUBA),
-                   (9, g.VARIANT_KARATSUBA), (4, 2), (4, -1)):
+    for q, var in ((3, g.VARIANT_KARATSUBA), (5, g.VARIANT_KARATSUBA), (7, g.VARIANT_KARATSUBA), (4, 2), (4, -1),
+                   (8, 2), (9, -1)):
         with pytest.raises(g.GfqError) as e:
             g.matmul(q, Ap, Bp, 64, 64, 64, variant=var)
         assert e.value.status == -1, (q, var)
