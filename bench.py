@@ -56,7 +56,7 @@ C_ADD_PAPER = {3: 6, 4: 2, 5: 20, 7: 17}
 # HBM traffic of the product kernels from rocprofv3 FETCH_SIZE / WRITE_SIZE passes on this
 # workload, scaled by the same counters on a 1 GiB device copy (reads x 2.0, writes x 1.0);
 # valid only while the kernel sources hash to `src` (otherwise the roofline reports null).
-KERNEL_SOURCES = ("gfq_m4rm.hip", "gfq_m4rm_tile.h", "gfq_device.h", "gfq_field.h", "gfq_internal.h")
+KERNEL_SOURCES = ("gfq_m4rm_launch.h", "gfq_m4rm_tile.h", "gfq_device.h", "gfq_field.h", "gfq_internal.h")
 MEASURED_TRAFFIC = {
     3: {"src": "49f8073743fdc0e6", "read_mib": 655.1, "write_mib": 64.0},
     5: {"src": "49f8073743fdc0e6", "read_mib": 243.1, "write_mib": 24.0},

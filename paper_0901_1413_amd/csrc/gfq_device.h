@@ -63,8 +63,8 @@ template <> struct FT<7> {
         r[0] = z.b0; r[1] = z.b1; r[2] = z.b2;
     }
     __device__ static void tsub(const u32 *a, const u32 *b, u32 *r) {
-        const u32 nb[3] = {~b[0], ~b[1], ~b[2]};
-        tadd(a, nb, r);
+        P3v z = f7_sub(P3v{a[0], a[1], a[2]}, P3v{b[0], b[1], b[2]});
+        r[0] = z.b0; r[1] = z.b1; r[2] = z.b2;
     }
     __device__ static void acc_init(u32 *c, int) { for (int i = 0; i < PA; i++) c[i] = 0u; }
     __device__ static void accumulate(u32 *c, const u32 (*t)[P]) {

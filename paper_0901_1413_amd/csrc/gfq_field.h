@@ -33,6 +33,27 @@ GFQ_HD u32 xor3n(u32 a, u32 b, u32 c) { return a ^ b ^ ~c; }
 GFQ_HD u32 maj3n(u32 a, u32 b, u32 c) { return (a & b) | (~c & (a | b)); }
 #endif
 
+// Any three-input function as one instruction: bit (4a + 2b + c) of IMM is the result for
+// operand bits (a, b, c), the same truth-table order as above.
+template <int IMM> GFQ_HD u32 lut3(u32 a, u32 b, u32 c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_bitop3_b32(a, b, c, IMM);
+#else
+    u32 r = 0;
+    for (int v = 0; v < 8; v++)
+        if ((IMM >> v) & 1) r |= ((v & 4) ? a : ~a) & ((v & 2) ? b : ~b) & ((v & 1) ? c : ~c);
+    return r;
+#endif
+}
+// The table of the same function with the operands selected by mask m (4: a, 2: b, 1: c)
+// complemented.
+constexpr int lut3_flip(int imm, int m) {
+    int r = 0;
+    for (int v = 0; v < 8; v++)
+        if ((imm >> (v ^ m)) & 1) r |= 1 << v;
+    return r;
+}
+
 // ---------------------------------------------------------------------------------------
 // F_3 (Section 4.1).  Planes (x0, x1): x0 marks a unit, x1 the sign; 0 = 00, 1 = 10,
 // -1 = 11.  The code 01 never occurs.
@@ -85,6 +106,9 @@ GFQ_HD P4v add3x3(P3v a, P3v b) {
 
 // F_7 addition (17 two-input operations): add, then add the carry back in (8 = 1 mod 7).
 // The second addition never carries out: the sum is at most 14, so s0..s3 are never all 1.
+// (A carry-lookahead form that adds the end-around carry in one ripple pass takes 8
+// three-input instructions instead of 11, but measured slower in the table build, whose
+// Gray-code walk is one long dependency chain.)
 GFQ_HD P3v f7_add(P3v a, P3v b) {
     P4v s = add3x3(a, b);
     P3v r;
@@ -95,6 +119,8 @@ GFQ_HD P3v f7_add(P3v a, P3v b) {
     r.b2 = s.b2 ^ d2;
     return r;
 }
+// F_7 subtraction: addition of the complement (7 - b = -b mod 7).
+GFQ_HD P3v f7_sub(P3v a, P3v b) { return f7_add(a, P3v{~b.b0, ~b.b1, ~b.b2}); }
 
 // F_7 doubling: a rotation of the planes, no operations.
 GFQ_HD P3v f7_dbl(P3v a) { P3v r; r.b0 = a.b2; r.b1 = a.b0; r.b2 = a.b1; return r; }
@@ -217,21 +243,23 @@ template <int NB> GFQ_HD void csa_step_neg(u32 *S, u32 *K, const u32 *X) {
 // From the storage code (unit x0, sign x1): 1 = 10 -> 01 and -1 = 11 -> 10.
 GFQ_HD void f3_to_bin(u32 x0, u32 x1, u32 *b) { b[0] = x0 ^ x1; b[1] = x1; }
 
-// Addition modulo 3 of two 2-bit residues with the end-around carry.
-GFQ_HD void f3b_add(const u32 *a, const u32 *b, u32 *r) {
-    const u32 c1 = a[0] & b[0];
-    const u32 s0 = a[0] ^ b[0];
-    const u32 s1 = xor3(a[1], b[1], c1);
-    const u32 c2 = maj3(a[1], b[1], c1);          // carry of weight 4 = 1 (mod 3)
-    r[0] = s0 ^ c2;
-    r[1] = s1 ^ (s0 & c2);
+// Addition modulo 3 of two 2-bit residues (either of 0 and 3 may stand for 0) in four
+// three-input instructions, the fewest possible: an exhaustive search over programs of
+// arbitrary three-input gates (the paper's search for minimal programs on 2-bit fields,
+// Section 4, re-run with the instruction gfx950 has; search/f3b_add_search.cpp) finds none
+// of three and this one of four.  Over operands (a, b, c) weighted 4, 2, 1:
+//   h1 = [at most one of b0, a1, a0 set],  h2 = lut 0x49 (b0, a1, a0),
+//   r0 = a1 ^ b1 ^ h1,                     r1 = lut 0x49 (r0, h2, b1).
+// B_NEG adds the complement of b (3 - b = -b mod 3), i.e. subtracts b: the complemented
+// operands are folded into the truth tables.
+template <bool B_NEG> GFQ_HD void f3b_add_t(const u32 *a, const u32 *b, u32 *r) {
+    const u32 h1 = lut3<lut3_flip(0x17, B_NEG ? 4 : 0)>(b[0], a[1], a[0]);
+    const u32 h2 = lut3<lut3_flip(0x49, B_NEG ? 4 : 0)>(b[0], a[1], a[0]);
+    r[0] = lut3<lut3_flip(0x96, B_NEG ? 1 : 0)>(a[1], h1, b[1]);
+    r[1] = lut3<lut3_flip(0x49, B_NEG ? 1 : 0)>(r[0], h2, b[1]);
 }
-
-// Negation modulo 2^NB - 1 is the complement: (2^NB - 1) - x.
-GFQ_HD void f3b_sub(const u32 *a, const u32 *b, u32 *r) {
-    const u32 nb[2] = {~b[0], ~b[1]};
-    f3b_add(a, nb, r);
-}
+GFQ_HD void f3b_add(const u32 *a, const u32 *b, u32 *r) { f3b_add_t<false>(a, b, r); }
+GFQ_HD void f3b_sub(const u32 *a, const u32 *b, u32 *r) { f3b_add_t<true>(a, b, r); }
 
 // Back to the storage code: residue 0 (00 or 11) -> 00, 1 -> 10, 2 -> 11.
 GFQ_HD void f3_from_bin(const u32 *b, u32 *x0, u32 *x1) { *x0 = b[0] ^ b[1]; *x1 = b[1] & ~b[0]; }

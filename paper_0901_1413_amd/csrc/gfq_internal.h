@@ -136,6 +136,10 @@ struct MMStrides {
     size_t A, B, out;
 };
 
+// product launches for kernel field Q (explicitly instantiated in gfq_m4rm_<field>.hip)
+template <bool STRIDED, int Q>
+hipError_t launch_mm_q(const MMArgs &a, const MMPlan &plan, const MMStrides &sd, hipStream_t st);
+
 hipError_t launch_matmul(int q, const MMArgs &a, const MMPlan &plan, hipStream_t st);
 hipError_t launch_matmul_strided(int q, const MMArgs &a, const MMPlan &plan, const MMStrides &sd, hipStream_t st);
 

@@ -1,0 +1,94 @@
+// gfq_m4rm_launch.h -- the Four-Russians product kernels and their launch templates: the
+// single-product kernel (grid.z = slab slices) and the strided kernel for many products of
+// one shape (grid.z = product x slab slices).  Included only by the gfq_m4rm_<field>.hip
+// units, each of which instantiates launch_mm_q for its fields (so the kernels of
+// different fields compile in parallel); gfq_m4rm.hip holds the field switch.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "gfq_m4rm_tile.h"
+
+namespace gfq {
+
+// grid (column tiles, row tiles, slab slices); row tile ty0 + blockIdx.y
+template <int Q, int TWD, int REP, int R, int NT>
+__global__ __launch_bounds__(NT) void m4rm_kernel(MMArgs a, int ty0) {
+    m4rm_tile<Q, TWD, REP, R, NT>(a, blockIdx.x, ty0 + (int)blockIdx.y, blockIdx.z);
+}
+
+// many products of one shape: grid.z = product x slab slices, operands at uniform strides
+// (a kernel of its own, so that the single-product kernel keeps its plain argument use)
+template <int Q, int TWD, int REP, int R, int NT>
+__global__ __launch_bounds__(NT) void m4rm_strided_kernel(MMArgs a, int ty0, int splits, MMStrides sd) {
+    const int prod = (int)blockIdx.z / splits;
+    const int bz = (int)blockIdx.z - prod * splits;
+    a.A += (size_t)prod * sd.A;
+    a.B += (size_t)prod * sd.B;
+    a.out += (size_t)prod * sd.out;
+    m4rm_tile<Q, TWD, REP, R, NT>(a, blockIdx.x, ty0 + (int)blockIdx.y, bz);
+}
+
+// ---------------------------------------------------------------------------------------
+// Launch: layout (super-row bytes) and rows-per-lane variants.
+// ---------------------------------------------------------------------------------------
+template <bool STRIDED, int Q, int TWD, int REP, int R>
+static hipError_t launch_mm(const MMArgs &a0, const MMPlan &plan, const MMStrides &sd, hipStream_t st) {
+    constexpr int LPR = TWD / 4;
+    constexpr int TM = (NT_MM / LPR) * R;
+    if (plan.TM != TM || plan.lds > 163840) return hipErrorInvalidValue;
+    MMArgs a = a0;
+    a.tb1 = plan.tb1;
+    const int row_tiles = (a.m + TM - 1) / TM;
+    const void *kern = STRIDED ? (const void *)m4rm_strided_kernel<Q, TWD, REP, R, NT_MM>
+                               : (const void *)m4rm_kernel<Q, TWD, REP, R, NT_MM>;
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)plan.lds);
+    if (e != hipSuccess) return e;
+    const int splits = (a.S + a.slabs_per_split - 1) / a.slabs_per_split;
+    if ((int64_t)splits * sd.count > 65535) return hipErrorInvalidValue;
+    // a grid's y extent is at most 65535: taller products take several launches
+    for (int ty0 = 0; ty0 < row_tiles; ty0 += 65535) {
+        dim3 grid((a.Wn + TWD - 1) / TWD, std::min(65535, row_tiles - ty0), splits * sd.count);
+        if constexpr (STRIDED)
+            hipLaunchKernelGGL((m4rm_strided_kernel<Q, TWD, REP, R, NT_MM>), grid, dim3(NT_MM), plan.lds, st, a, ty0,
+                               splits, sd);
+        else
+            hipLaunchKernelGGL((m4rm_kernel<Q, TWD, REP, R, NT_MM>), grid, dim3(NT_MM), plan.lds, st, a, ty0);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <bool STRIDED, int Q, int TWD, int REP>
+static hipError_t launch_mm_rows(const MMArgs &a, const MMPlan &plan, const MMStrides &sd, hipStream_t st) {
+    constexpr bool two_only = Q == 9 || Q == F9_KARATSUBA;   // F_9: two rows per lane only
+    if (plan.R == 2 || two_only) return launch_mm<STRIDED, Q, TWD, REP, 2>(a, plan, sd, st);
+    if constexpr (two_only) {
+        return hipErrorInvalidValue;
+    } else if constexpr (Q == 5 || Q == 7 || ((Q == 8 || Q == GF8_TRINOMIAL) && TWD < 16)) {
+        return launch_mm<STRIDED, Q, TWD, REP, 4>(a, plan, sd, st);       // eight rows per lane would spill
+    } else {
+        if (plan.R == 4) return launch_mm<STRIDED, Q, TWD, REP, 4>(a, plan, sd, st);
+        if constexpr ((Q == 4 || Q == GF4_KARATSUBA) && TWD == 16) {
+            if (plan.R == 16) return launch_mm<STRIDED, Q, TWD, REP, 16>(a, plan, sd, st);   // two planes per word
+        }
+        return launch_mm<STRIDED, Q, TWD, REP, 8>(a, plan, sd, st);
+    }
+}
+
+template <bool STRIDED, int Q>
+hipError_t launch_mm_q(const MMArgs &a, const MMPlan &plan, const MMStrides &sd, hipStream_t st) {
+    switch (plan.srb) {
+    case 256: return launch_mm_rows<STRIDED, Q, 16, 4>(a, plan, sd, st);
+    case 128: return launch_mm_rows<STRIDED, Q, 16, 2>(a, plan, sd, st);
+    case 64: return launch_mm_rows<STRIDED, Q, 16, 1>(a, plan, sd, st);
+    case 32: return launch_mm_rows<STRIDED, Q, 8, 1>(a, plan, sd, st);
+    case 16: return launch_mm_rows<STRIDED, Q, 4, 1>(a, plan, sd, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace gfq

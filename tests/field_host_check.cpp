@@ -17,7 +17,8 @@ int main() {
     }
     for (int i = 0; i < 3; i++) { F3v n = f3_neg(f3(codes[i][0], codes[i][1])); printf("f3neg %u %u %u %u\n", codes[i][0], codes[i][1], bit(n.u), bit(n.s)); }
     for (unsigned a = 0; a < 8; a++) for (unsigned b = 0; b < 8; b++)
-        printf("p3 %u %u f7add %u f5add %u\n", a, b, v3(f7_add(p3(a), p3(b))), v3(f5_add(p3(a), p3(b))));
+        printf("p3 %u %u f7add %u f5add %u f7sub %u\n", a, b, v3(f7_add(p3(a), p3(b))), v3(f5_add(p3(a), p3(b))),
+               v3(f7_sub(p3(a), p3(b))));
     for (unsigned a = 0; a < 8; a++)
         printf("p1 %u f7dbl %u f7neg %u f7red %u f5dbl %u f5neg %u f5red %u\n", a, v3(f7_dbl(p3(a))), v3(f7_neg(p3(a))) & 7,
                v3(f7_reduce(p3(a))), v3(f5_dbl(p3(a))), v3(f5_neg(p3(a))), v3(f5_reduce(p3(a))));

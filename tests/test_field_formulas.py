@@ -42,9 +42,10 @@ def test_f5_f7_binary(table):
     rows = [r for r in table if r[0] == "p3"]
     assert len(rows) == 64
     for r in rows:
-        a, b, f7, f5 = int(r[1]), int(r[2]), int(r[4]), int(r[6])
+        a, b, f7, f5, f7s = int(r[1]), int(r[2]), int(r[4]), int(r[6]), int(r[8])
         assert f7 % 7 == (a + b) % 7, r
         assert f5 % 5 == (a + b) % 5, r
+        assert f7s % 7 == (a - b) % 7, r
     for r in (r for r in table if r[0] == "p1"):
         a = int(r[1])
         f7dbl, f7neg, f7red, f5dbl, f5neg, f5red = (int(r[i]) for i in (3, 5, 7, 9, 11, 13))
@@ -132,3 +133,18 @@ def test_f5_slab_step(table):
     for r in inits:
         n, so, ko, full = map(int, r[1:])
         assert (so + ko + 7 * n) % 15 == 0 and ko == 0 and full == 1, r
+
+
+def test_f3_binary_add_is_shortest(tmp_path):
+    """The F_3 table addition (f3b_add) takes four three-input instructions; the committed
+    exhaustive search shows that no program of three or fewer exists and checks the
+    four-gate program."""
+    exe = str(tmp_path / "f3b_add_search")
+    subprocess.check_call(["g++", "-O2", "-std=c++17",
+                           os.path.join(ROOT, "paper_0901_1413_amd", "search", "f3b_add_search.cpp"), "-o", exe])
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stdout + out.stderr
+    lines = out.stdout.splitlines()
+    for L in (1, 2, 3):
+        assert f"length {L}: 0 programs" in lines, out.stdout
+    assert "four-gate program: correct" in lines
