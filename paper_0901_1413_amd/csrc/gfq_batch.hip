@@ -36,16 +36,16 @@ __global__ void batch_stamp_kernel(unsigned long long *t) {
     if (threadIdx.x == 0) t[0] = __builtin_amdgcn_s_memrealtime();
 }
 
-template <int Q, int R>
+template <int Q, int R, int REP = 4>
 static const void *list_kernel_ptr() {
-    return (const void *)m4rm_list_kernel<Q, 16, 4, R, NT_MM>;
+    return (const void *)m4rm_list_kernel<Q, 16, REP, R, NT_MM>;
 }
 
 const void *batched_kernel(int q, int R) {
     switch (q) {
     case 3: return R == 2 ? list_kernel_ptr<3, 2>() : list_kernel_ptr<3, 8>();
     case 4: return R == 2 ? list_kernel_ptr<4, 2>() : list_kernel_ptr<4, 8>();
-    case 5: return list_kernel_ptr<5, 2>();      // four rows per lane would spill here
+    case 5: return R == 2 ? list_kernel_ptr<5, 2>() : list_kernel_ptr<5, 4, 1>();   // batch_srb: 64 at R = 4
     case 8: return R == 2 ? list_kernel_ptr<8, 2>() : list_kernel_ptr<8, 8>();
     case 9: return list_kernel_ptr<9, 2>();      // four rows per lane would spill here
     default: return R == 2 ? list_kernel_ptr<7, 2>() : list_kernel_ptr<7, 4>();

@@ -38,12 +38,12 @@ void gfq::plan_batch(int count, const gfq_problem *problems, const gfq_config *c
         else if (gfq_tune_lookup(p.q, p.m, p.l, p.n, GFQ_TUNE_BATCH, &c) != GFQ_OK)
             gfq_choose_config(p.q, p.m, p.l, p.n, &c);
         const int P = planes_of(p.q);
-        // the batched kernels use 256-byte super-rows: k <= 7 (two planes), 6 (three or four)
-        const int kcap = kmax_wide(p.q);
-        int k = std::min(c.k, kcap);
+        // the batched kernels' super-rows (batch_srb) bound the slab width
+        const int R = c.rows <= 256 ? 2 : max_rows_per_lane_batch(p.q);
+        const int srb = batch_srb(p.q, R);
+        int k = std::min(c.k, batch_kmax(p.q, R));
         if (p.l > 0 && p.l < k) k = (int)p.l;
         if (k < 1) k = 1;
-        const int R = c.rows <= 256 ? 2 : max_rows_per_lane_batch(p.q);
         const int TM = NT_MM / 4 * R;
         MMArgs &a = bp.a;
         a.A = (const u32 *)p.A;
@@ -58,7 +58,7 @@ void gfq::plan_batch(int count, const gfq_problem *problems, const gfq_config *c
         a.S = p.l > 0 ? (int)((p.l + k - 1) / k) : 0;
         a.slabs_per_split = std::max(a.S, 1);
         a.split_stride = 0;
-        mm_lds_bytes(p.q, k, 256, TM, &a.tb1);
+        mm_lds_bytes(p.q, k, srb, TM, &a.tb1);
         if (p.m == 0 || p.n == 0) continue;
         const int tx = (a.Wn + 15) / 16, ty = (a.m + TM - 1) / TM;
         bp.tiles = (u32)(tx * ty);
@@ -88,7 +88,7 @@ void gfq::plan_batch(int count, const gfq_problem *problems, const gfq_config *c
         gr.cost.clear();
         gr.item_off = n;
         n += gr.items.size();
-        gr.lds = mm_lds_bytes(gr.q, gr.kmax, 256, NT_MM / 4 * gr.R, nullptr);
+        gr.lds = mm_lds_bytes(gr.q, gr.kmax, batch_srb(gr.q, gr.R), NT_MM / 4 * gr.R, nullptr);
         groups->push_back(std::move(gr));
     }
     *nitems = n;
@@ -102,7 +102,7 @@ size_t gfq::batch_tiles_bound(int64_t m, int64_t n) {
 hipError_t gfq::set_batched_lds_limits() {
     for (int q : {3, 4, 5, 7, 8, 9})
         for (int R : {2, max_rows_per_lane_batch(q)}) {
-            const size_t lds = mm_lds_bytes(q, kmax_wide(q), 256, NT_MM / 4 * R, nullptr);
+            const size_t lds = mm_lds_bytes(q, batch_kmax(q, R), batch_srb(q, R), NT_MM / 4 * R, nullptr);
             hipError_t e = hipFuncSetAttribute(batched_kernel(q, R), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
         }

@@ -64,7 +64,7 @@ inline int words_of(int64_t cols) { return (int)(((cols + 127) / 128) * 4); }
 inline int max_rows_per_lane(int q) {
     return (q == 9 || q == F9_KARATSUBA) ? 2 : (q == 5 || q == 7 ? 4 : (q == 4 || q == GF4_KARATSUBA ? 16 : 8));
 }
-inline int max_rows_per_lane_batch(int q) { return q == 5 || q == 9 ? 2 : (q == 7 ? 4 : 8); }
+inline int max_rows_per_lane_batch(int q) { return q == 9 ? 2 : (q == 5 || q == 7 ? 4 : 8); }
 
 // Table super-row bytes for field q and slab width k: the widest of 256, 128, 64, 32, 16
 // such that both table buffers fit TABLES_LDS (0 if none does).
@@ -74,10 +74,17 @@ inline int srb_for(int q, int k) {
     return 0;
 }
 inline int twd_of(int srb) { return srb >= 64 ? 16 : srb / 4; }   // tile words per plane
-// largest slab width whose tables keep 256-byte super-rows (the batched kernels' layout)
-inline int kmax_wide(int q) {
+
+// Super-row bytes of the batched (work-list) kernels of field q at R rows per lane: 256 (four
+// copies of the 16-word tile row, conflict-free reads), except F_5 at four rows per lane,
+// which fits its registers only with one copy (64 bytes; reads may conflict, but its tables
+// then hold slabs up to k = 8).
+inline int batch_srb(int q, int R) { return (q == 5 && R == 4) ? 64 : 256; }
+// largest slab width whose two tables fit LDS with super-rows of batch_srb(q, R) bytes
+inline int batch_kmax(int q, int R) {
+    const int srb = batch_srb(q, R);
     int k = 1;
-    while (k < KMAX && srb_for(q, k + 1) == 256) k++;
+    while (k < KMAX && 2 * ((size_t)1 << (k + 1)) * table_planes(q) * srb <= TABLES_LDS) k++;
     return k;
 }
 

@@ -165,7 +165,7 @@ int gfq_tune(int q, int64_t m, int64_t l, int64_t n, int mode, gfq_config *out) 
     } else {
         // a batch of identical products of the class's shape, enough of them for ~1024 tiles
         const int64_t nb = 512;
-        const int kcap = kmax_wide(q);
+        const int kcap = std::max(batch_kmax(q, 2), batch_kmax(q, max_rows_per_lane_batch(q)));
         const int64_t items_per = std::max<int64_t>(1, (m + 255) / 256);
         const int count = (int)std::max<int64_t>(16, std::min<int64_t>(2048, 1024 / items_per));
         const size_t ba = rup(gfq_packed_bytes(q, m, l)), bb = rup(gfq_packed_bytes(q, l, nb));
@@ -179,6 +179,7 @@ int gfq_tune(int q, int64_t m, int64_t l, int64_t n, int mode, gfq_config *out) 
             const double bops = ops / (double)n * (double)nb * count;
             for (int k = 3; k <= std::min<int64_t>(kcap, l); k++) {
                 for (int rows : {256, 2048}) {
+                    if (k > batch_kmax(q, rows <= 256 ? 2 : max_rows_per_lane_batch(q))) continue;
                     std::vector<gfq_config> cfg(count, gfq_config{k, rows, 1, 0});
                     gfq_batch *b = nullptr;
                     if (batch_create_with(count, probs.data(), cfg.data(), &b) != GFQ_OK) continue;
