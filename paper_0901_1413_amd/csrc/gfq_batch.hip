@@ -48,7 +48,7 @@ const void *batched_kernel(int q, int R) {
     case 5: return R == 2 ? list_kernel_ptr<5, 2>() : list_kernel_ptr<5, 4, 1>();   // batch_srb: 64 at R = 4
     case 8: return R == 2 ? list_kernel_ptr<8, 2>() : list_kernel_ptr<8, 8>();
     case 9: return list_kernel_ptr<9, 2>();      // four rows per lane would spill here
-    default: return R == 2 ? list_kernel_ptr<7, 2>() : list_kernel_ptr<7, 4>();
+    default: return R == 2 ? list_kernel_ptr<7, 2>() : list_kernel_ptr<7, 4, 1>();   // batch_srb: 64 at R = 4
     }
 }
 

@@ -76,10 +76,11 @@ inline int srb_for(int q, int k) {
 inline int twd_of(int srb) { return srb >= 64 ? 16 : srb / 4; }   // tile words per plane
 
 // Super-row bytes of the batched (work-list) kernels of field q at R rows per lane: 256 (four
-// copies of the 16-word tile row, conflict-free reads), except F_5 at four rows per lane,
-// which fits its registers only with one copy (64 bytes; reads may conflict, but its tables
-// then hold slabs up to k = 8).
-inline int batch_srb(int q, int R) { return (q == 5 && R == 4) ? 64 : 256; }
+// copies of the 16-word tile row, conflict-free reads), except F_5 and F_7 at four rows per
+// lane: one copy (64 bytes; reads may conflict, but the tables then hold slabs up to k = 8,
+// and F_5 fits its registers only so).  Measured on the 4096-product batch: F_5 4.06 -> 3.14
+// ms, F_7 3.81 -> 3.41 ms; F_3 at 128 bytes gained nothing.
+inline int batch_srb(int q, int R) { return ((q == 5 || q == 7) && R == 4) ? 64 : 256; }
 // largest slab width whose two tables fit LDS with super-rows of batch_srb(q, R) bytes
 inline int batch_kmax(int q, int R) {
     const int srb = batch_srb(q, R);
