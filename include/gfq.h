@@ -198,7 +198,7 @@ int gfq_batch_destroy(gfq_batch *batch);
  * gfq_tune_lookup returns GFQ_OK and the entry if the class is cached, GFQ_EAGAIN if not.
  * gfq_tune_save / gfq_tune_load write / merge the cache as text, one entry per line.
  * gfq_tune_clear empties it.
- * gfq_tune: each of m, l, n in 1 .. 65536 (else GFQ_EDIM); q in {3,4,5,7} (GFQ_EFIELD);
+ * gfq_tune: each of m, l, n in 1 .. 65536 (else GFQ_EDIM); q in {3,4,5,7,8,9} (GFQ_EFIELD);
  * mode 0 or GFQ_TUNE_BATCH (GFQ_EINVAL).  It runs on the calling thread's stream, waits for
  * its own launches, and keeps its scratch operands (one device buffer, filled with
  * pseudo-random words) until the process ends; GFQ_ENOMEM if that buffer cannot be had.

@@ -306,3 +306,20 @@ def test_f9_2048_sampled(gfq_gpu, k):
     sample = np.unique(np.concatenate([np.arange(0, N, 61), np.arange(N - 5, N)]))
     got = C[torch.from_numpy(sample).cuda()].cpu().numpy()
     assert np.array_equal(got, oracle.matmul(q, A[sample], B))
+
+
+@pytest.mark.parametrize("q", [5, 9])
+def test_longest_inner_dimension(gfq_gpu, q):
+    """l = 2^24 - 1, the largest inner dimension the library accepts (m = 3, n = 40: B is
+    the large operand), against the oracle; l = 2^24 is rejected before any launch."""
+    import torch
+    g = gfq_gpu
+    m, l, n = 3, (1 << 24) - 1, 40
+    A, B = inputs.pair(q, m, l, n, cfg=250, idx=q)
+    check(g, q, A, B)
+    Ap = g.empty_packed(q, m, 1 << 24)
+    Bp = g.empty_packed(q, 1 << 24, n)
+    with pytest.raises(g.GfqError) as e:
+        g.matmul(q, Ap, Bp, m, 1 << 24, n)
+    assert e.value.status == -3
+    torch.cuda.synchronize()
