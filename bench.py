@@ -628,6 +628,8 @@ def section_c4(ctx, count=4096, reps=5, pool=2048):
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
+        b.launch()                     # an eager launch on the capture stream first: the
+        side.synchronize()             # library's side streams for it exist before capture
         with torch.cuda.graph(graph, stream=side):
             b.launch()
     torch.cuda.current_stream().wait_stream(side)

@@ -1,12 +1,16 @@
 // gfq_batch_host.cpp -- building, launching and timing batches of products (the host side
 // of gfq_batch.hip): per-product launch parameters, work lists ordered longest first and
 // one device allocation for all descriptors.  A launch is a start stamp and one work-list
-// kernel per (field, tile height) on the caller's stream; it allocates nothing, so a
-// caller may capture it into a graph.
+// kernel per (field, tile height): the first on the caller's stream, the others forked onto
+// side streams and joined back, so that one group's last workgroups overlap the others'; it
+// allocates nothing, so a caller may capture it into a graph (the fork becomes parallel
+// branches of the graph).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "gfq.h"
@@ -16,6 +20,44 @@
 using namespace gfq;
 
 namespace {
+
+// Side streams (default priority) and their events for the batch launches made on one
+// caller stream, created on first need and kept until the process ends.  They are never
+// created while the caller's stream is being captured: a capture without them launches the
+// groups one after another on the caller's stream.
+struct SidePool {
+    hipEvent_t fork = nullptr;
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> done;
+};
+std::mutex g_side_mu;
+std::map<std::pair<int, hipStream_t>, SidePool> g_side;
+
+SidePool *side_pool(hipStream_t st, size_t n) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    SidePool &p = g_side[std::make_pair(dev, st)];
+    if (p.fork && p.streams.size() >= n) return &p;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
+    if (!p.fork && hipEventCreateWithFlags(&p.fork, hipEventDisableTiming) != hipSuccess) {
+        p.fork = nullptr;
+        return nullptr;
+    }
+    while (p.streams.size() < n) {
+        hipStream_t s = nullptr;
+        hipEvent_t d = nullptr;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+        if (hipEventCreateWithFlags(&d, hipEventDisableTiming) != hipSuccess) {
+            (void)hipStreamDestroy(s);
+            return nullptr;
+        }
+        p.streams.push_back(s);
+        p.done.push_back(d);
+    }
+    return &p;
+}
 
 int group_index(int q, int R) {
     const int qi = q == 3 ? 0 : (q == 4 ? 1 : (q == 5 ? 2 : (q == 7 ? 3 : (q == 8 ? 4 : 5))));
@@ -182,15 +224,23 @@ int gfq_batch_launch(gfq_batch *b) {
     if (!b) return GFQ_ENULL;
     hipStream_t st = current_stream();
     hipError_t e = launch_batch_stamp(b->times, st);
-    for (size_t j = 0; e == hipSuccess && j < b->groups.size(); j++) {
+    const size_t ng = b->groups.size();
+    SidePool *sp = ng > 1 ? side_pool(st, ng - 1) : nullptr;
+    if (e == hipSuccess && sp) e = hipEventRecord(sp->fork, st);
+    for (size_t j = 0; e == hipSuccess && j < ng; j++) {
         const BatchGroup &gr = b->groups[j];
+        const bool side = sp && j > 0;
+        hipStream_t s = side ? sp->streams[j - 1] : st;
+        if (side) e = hipStreamWaitEvent(s, sp->fork, 0);
         BatchList l;
         l.prods = b->prods;
         l.items = b->items + gr.item_off;
         l.prod_done = b->prod_done;
         l.prod_time = b->times + 1;
-        e = launch_batched(gr.q, gr.R, l, (int)gr.items.size(), gr.lds, st);
+        if (e == hipSuccess) e = launch_batched(gr.q, gr.R, l, (int)gr.items.size(), gr.lds, s);
+        if (e == hipSuccess && side) e = hipEventRecord(sp->done[j - 1], s);
     }
+    for (size_t j = 1; e == hipSuccess && sp && j < ng; j++) e = hipStreamWaitEvent(st, sp->done[j - 1], 0);
     return e == hipSuccess ? GFQ_OK : hip_fail(e, "batch launch");
 }
 

@@ -101,10 +101,13 @@ def test_c4_shaped_batch_sampled(gfq_gpu):
     check_against_oracle_and_alone(g, probs, host, range(0, 512, 37))
 
 
-def test_batch_graph_capture_replays(gfq_gpu):
+@pytest.mark.parametrize("forked", [False, True])
+def test_batch_graph_capture_replays(gfq_gpu, forked):
     """gfq_batch_launch allocates nothing and makes no synchronising call, so it can be
     captured into a HIP graph; every replay (with eager work in between) equals the eager
-    launch bit for bit."""
+    launch bit for bit.  forked: the capture stream launched the batch eagerly before, so its
+    side streams exist and the capture holds the groups as parallel branches; otherwise the
+    capture launches the groups one after another."""
     import torch
     g = gfq_gpu
     specs = [(3, 300, 200, 100), (5, 64, 64, 64), (7, 1000, 900, 130), (4, 513, 127, 511), (5, 700, 1500, 900)]
@@ -119,6 +122,9 @@ def test_batch_graph_capture_replays(gfq_gpu):
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
+        if forked:
+            b.launch()
+            side.synchronize()
         with torch.cuda.graph(graph, stream=side):
             b.launch()
     torch.cuda.current_stream().wait_stream(side)
