@@ -26,9 +26,12 @@ struct BatchList {
     unsigned long long *prod_time;     // completion time per product (100 MHz clock)
 };
 
-// Work-list kernel for field q with R rows per lane (256-byte super-rows, 16-word tiles).
-const void *batched_kernel(int q, int R);
-hipError_t launch_batched(int q, int R, const BatchList &bl, int items, size_t lds, hipStream_t st);
+// Work-list kernel for field q with R rows per lane and tiles TWD words wide per plane: 16
+// (512 columns; super-rows of batch_srb(q, R) bytes), or 8 and 4 (256 and 128 columns, two
+// rows per lane, 8 and 16 copies per 256-byte super-row) for products narrower than a wide
+// tile.
+const void *batched_kernel(int q, int R, int twd);
+hipError_t launch_batched(int q, int R, int twd, const BatchList &bl, int items, size_t lds, hipStream_t st);
 hipError_t launch_batch_stamp(unsigned long long *t, hipStream_t st);
 
 }  // namespace gfq

@@ -41,7 +41,23 @@ static const void *list_kernel_ptr() {
     return (const void *)m4rm_list_kernel<Q, 16, REP, R, NT_MM>;
 }
 
-const void *batched_kernel(int q, int R) {
+// narrow tiles: two rows per lane, TWD words per plane, 64 / TWD copies per 256-byte super-row
+template <int Q>
+static const void *narrow_kernel_ptr(int twd) {
+    return twd == 8 ? (const void *)m4rm_list_kernel<Q, 8, 8, 2, NT_MM> : (const void *)m4rm_list_kernel<Q, 4, 16, 2, NT_MM>;
+}
+
+const void *batched_kernel(int q, int R, int twd) {
+    if (twd != 16) {
+        switch (q) {
+        case 3: return narrow_kernel_ptr<3>(twd);
+        case 4: return narrow_kernel_ptr<4>(twd);
+        case 5: return narrow_kernel_ptr<5>(twd);
+        case 8: return narrow_kernel_ptr<8>(twd);
+        case 9: return twd == 8 ? (const void *)m4rm_list_kernel<9, 8, 8, 2, NT_MM> : nullptr;   // 4 words would spill
+        default: return narrow_kernel_ptr<7>(twd);
+        }
+    }
     switch (q) {
     case 3: return R == 2 ? list_kernel_ptr<3, 2>() : list_kernel_ptr<3, 8>();
     case 4: return R == 2 ? list_kernel_ptr<4, 2>() : list_kernel_ptr<4, 8>();
@@ -52,8 +68,9 @@ const void *batched_kernel(int q, int R) {
     }
 }
 
-hipError_t launch_batched(int q, int R, const BatchList &bl, int items, size_t lds, hipStream_t st) {
-    const void *k = batched_kernel(q, R);
+hipError_t launch_batched(int q, int R, int twd, const BatchList &bl, int items, size_t lds, hipStream_t st) {
+    const void *k = batched_kernel(q, R, twd);
+    if (!k) return hipErrorInvalidValue;
     void *args[] = {(void *)&bl};
     return hipLaunchKernel(k, dim3(items), dim3(NT_MM), args, lds, st);
 }

@@ -59,9 +59,9 @@ SidePool *side_pool(hipStream_t st, size_t n) {
     return &p;
 }
 
-int group_index(int q, int R) {
+int group_index(int q, int R, int twd) {
     const int qi = q == 3 ? 0 : (q == 4 ? 1 : (q == 5 ? 2 : (q == 7 ? 3 : (q == 8 ? 4 : 5))));
-    return qi * 2 + (R == 2 ? 0 : 1);
+    return qi * 4 + (twd == 8 ? 2 : (twd == 4 ? 3 : (R == 2 ? 0 : 1)));
 }
 
 }  // namespace
@@ -70,7 +70,7 @@ int group_index(int q, int R) {
 // ordered longest first within a group.
 void gfq::plan_batch(int count, const gfq_problem *problems, const gfq_config *cfgs, BatchProd *prods,
                      std::vector<BatchGroup> *groups, size_t *nitems) {
-    std::vector<BatchGroup> g(12);
+    std::vector<BatchGroup> g(24);
     for (int i = 0; i < count; i++) {
         const gfq_problem &p = problems[i];
         BatchProd &bp = prods[i];
@@ -80,13 +80,19 @@ void gfq::plan_batch(int count, const gfq_problem *problems, const gfq_config *c
         else if (gfq_tune_lookup(p.q, p.m, p.l, p.n, GFQ_TUNE_BATCH, &c) != GFQ_OK)
             gfq_choose_config(p.q, p.m, p.l, p.n, &c);
         const int P = planes_of(p.q);
-        // the batched kernels' super-rows (batch_srb) bound the slab width
-        const int R = c.rows <= 256 ? 2 : max_rows_per_lane_batch(p.q);
-        const int srb = batch_srb(p.q, R);
-        int k = std::min(c.k, batch_kmax(p.q, R));
+        // Tile shape: 16-word tiles with the configured rows per lane; a product taller than
+        // 256 rows and at most 256 (128) columns wide is one narrow tile column of 8 (4) words
+        // and 512 (1024) rows per tile instead, which pads it less.  The super-rows of the
+        // kernel bound the slab width.
+        int R = c.rows <= 256 ? 2 : max_rows_per_lane_batch(p.q);
+        int twd = 16;
+        if (p.m > 256 && p.n <= 128 && p.q != 9) twd = 4, R = 2;   // F_9: 4-word tiles would spill
+        else if (p.m > 256 && p.n <= 256) twd = 8, R = 2;
+        const int srb = twd == 16 ? batch_srb(p.q, R) : 256;
+        int k = std::min(c.k, batch_kmax(p.q, twd == 16 ? R : 2));
         if (p.l > 0 && p.l < k) k = (int)p.l;
         if (k < 1) k = 1;
-        const int TM = NT_MM / 4 * R;
+        const int TM = NT_MM / (twd / 4) * R;
         MMArgs &a = bp.a;
         a.A = (const u32 *)p.A;
         a.B = (const u32 *)p.B;
@@ -102,16 +108,17 @@ void gfq::plan_batch(int count, const gfq_problem *problems, const gfq_config *c
         a.split_stride = 0;
         mm_lds_bytes(p.q, k, srb, TM, &a.tb1);
         if (p.m == 0 || p.n == 0) continue;
-        const int tx = (a.Wn + 15) / 16, ty = (a.m + TM - 1) / TM;
+        const int tx = (a.Wn + twd - 1) / twd, ty = (a.m + TM - 1) / TM;
         bp.tiles = (u32)(tx * ty);
-        BatchGroup &gr = g[group_index(p.q, R)];
+        BatchGroup &gr = g[group_index(p.q, R, twd)];
         gr.q = p.q;
         gr.R = R;
+        gr.twd = twd;
         gr.kmax = std::max(gr.kmax, k);
         for (int y = 0; y < ty; y++)
             for (int x = 0; x < tx; x++) {
                 const double rows = std::min<int64_t>(TM, p.m - (int64_t)y * TM);
-                const double words = std::min(16, a.Wn - x * 16);
+                const double words = std::min(twd, a.Wn - x * twd);
                 gr.items.push_back(BatchItem{(u32)i, (uint16_t)x, (uint16_t)y});
                 // relative tile cost: rows x words x slabs (plus the tables it builds)
                 gr.cost.push_back((rows + (double)(1 << k)) * words * std::max(a.S, 1) * (P == 2 ? 1.0 : 3.0));
@@ -130,7 +137,8 @@ void gfq::plan_batch(int count, const gfq_problem *problems, const gfq_config *c
         gr.cost.clear();
         gr.item_off = n;
         n += gr.items.size();
-        gr.lds = mm_lds_bytes(gr.q, gr.kmax, batch_srb(gr.q, gr.R), NT_MM / 4 * gr.R, nullptr);
+        gr.lds = mm_lds_bytes(gr.q, gr.kmax, gr.twd == 16 ? batch_srb(gr.q, gr.R) : 256,
+                              NT_MM / (gr.twd / 4) * gr.R, nullptr);
         groups->push_back(std::move(gr));
     }
     *nitems = n;
@@ -142,12 +150,20 @@ size_t gfq::batch_tiles_bound(int64_t m, int64_t n) {
 }
 
 hipError_t gfq::set_batched_lds_limits() {
-    for (int q : {3, 4, 5, 7, 8, 9})
+    for (int q : {3, 4, 5, 7, 8, 9}) {
         for (int R : {2, max_rows_per_lane_batch(q)}) {
             const size_t lds = mm_lds_bytes(q, batch_kmax(q, R), batch_srb(q, R), NT_MM / 4 * R, nullptr);
-            hipError_t e = hipFuncSetAttribute(batched_kernel(q, R), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            hipError_t e = hipFuncSetAttribute(batched_kernel(q, R, 16), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
         }
+        for (int twd : {8, 4}) {
+            const void *k = batched_kernel(q, 2, twd);
+            if (!k) continue;
+            const size_t lds = mm_lds_bytes(q, batch_kmax(q, 2), 256, NT_MM / (twd / 4) * 2, nullptr);
+            hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+        }
+    }
     return hipSuccess;
 }
 
@@ -237,7 +253,7 @@ int gfq_batch_launch(gfq_batch *b) {
         l.items = b->items + gr.item_off;
         l.prod_done = b->prod_done;
         l.prod_time = b->times + 1;
-        if (e == hipSuccess) e = launch_batched(gr.q, gr.R, l, (int)gr.items.size(), gr.lds, s);
+        if (e == hipSuccess) e = launch_batched(gr.q, gr.R, gr.twd, l, (int)gr.items.size(), gr.lds, s);
         if (e == hipSuccess && side) e = hipEventRecord(sp->done[j - 1], s);
     }
     for (size_t j = 1; e == hipSuccess && sp && j < ng; j++) e = hipStreamWaitEvent(st, sp->done[j - 1], 0);

@@ -19,7 +19,7 @@ hipStream_t current_stream();
 int batch_create_with(int count, const gfq_problem *problems, const gfq_config *cfgs, gfq_batch **out);
 // The tiles of one (field, rows per lane) work list of a batch.
 struct BatchGroup {
-    int q = 0, R = 0, kmax = 1;
+    int q = 0, R = 0, twd = 16, kmax = 1;
     size_t lds = 0;                  // dynamic LDS of the list's launch
     size_t item_off = 0;             // index of the group's first item in the batch's item array
     std::vector<BatchItem> items;    // longest first

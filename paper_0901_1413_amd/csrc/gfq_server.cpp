@@ -184,7 +184,8 @@ hipError_t launch_batch(gfq_server *s, Slot &sl) {
         bl.items = (const BatchItem *)(sl.dev + o_items) + groups[j].item_off;
         bl.prod_done = sl.done;
         bl.prod_time = sl.times + 1;
-        e = launch_batched(groups[j].q, groups[j].R, bl, (int)groups[j].items.size(), groups[j].lds, sl.st);
+        e = launch_batched(groups[j].q, groups[j].R, groups[j].twd, bl, (int)groups[j].items.size(), groups[j].lds,
+                           sl.st);
     }
     if (e == hipSuccess)
         e = launch_conv_list((const ConvJob *)(sl.dev + o_unpack), (int)unpack.size(), unpack_blocks, sl.st);

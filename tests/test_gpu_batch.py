@@ -144,3 +144,16 @@ def test_batch_graph_capture_replays(gfq_gpu, forked):
         times = b.times_us()
         assert all(t > 0 for t in times), (rep, times)
     del graph
+
+
+def test_batch_narrow_tiles(gfq_gpu):
+    """Products taller than 256 rows and at most 256 (128) columns wide run as one column of
+    8-word (4-word) tiles; every field, ragged edges, against the oracle and the plain launch."""
+    g = gfq_gpu
+    specs = []
+    for q in (3, 4, 5, 7, 8, 9):
+        specs += [(q, 1500, 300, 100), (q, 700, 200, 250), (q, 257, 65, 128), (q, 2049, 129, 129), (q, 300, 33, 1)]
+    probs, host = make_batch(g, specs, 320)
+    g.matmul_batched(probs)
+    g.sync()
+    check_against_oracle_and_alone(g, probs, host, range(len(specs)))
