@@ -162,7 +162,7 @@ int gfq_matmul_sw(int q, int64_t m, int64_t l, int64_t n, const void *A, const v
                   const gfq_config *leaf);
 
 /* Run count independent products (fields and shapes may differ) as one launch per
- * (field, tile height) whose workgroups take (product, row tile, column tile) items from a
+ * (field, tile shape) whose workgroups take (product, row tile, column tile) items from a
  * longest-first work list.  problems is a host array.  Each product obeys the gfq_matmul
  * rules; a validation error in any product rejects the whole batch before anything is
  * launched.  Equivalent to gfq_batch_create + gfq_batch_launch; the batch's descriptors are
@@ -173,10 +173,16 @@ int gfq_matmul_batched(int count, const gfq_problem *problems);
  * once for a set of products whose operand pointers stay valid, launch it any number of
  * times.  gfq_batch_create validates every product (any error rejects the batch), chooses
  * each product's slab width and tile height (from the tuning cache when it holds the
- * product's size class), orders each (field, tile height) list of (product, row tile,
+ * product's size class; a product taller than 256 rows and at most 256 columns wide gets
+ * one column of narrow tiles), orders each (field, tile shape) list of (product, row tile,
  * column tile) items longest first and uploads the descriptors; it synchronises.
- * gfq_batch_launch enqueues, on the calling thread's stream, one launch per list (a
- * workgroup per item) and allocates nothing, so it may be captured into a graph.  Launches
+ * gfq_batch_launch enqueues one launch per list (a workgroup per item): the first on the
+ * calling thread's stream, the others on side streams of the library (default priority,
+ * kept per calling stream until the process ends) that fork from and join back into the
+ * calling stream, so the lists overlap.  It allocates nothing, so it may be captured into a
+ * graph (the lists become parallel branches); side streams are never created during a
+ * capture: if the capturing stream has none yet, the lists are captured one after another
+ * (one uncaptured launch on that stream first creates them).  Launches
  * of one batch must not overlap in time (they share its tile counters, completion stamps
  * and outputs): issue them on one stream, or wait for one before issuing the next.
  * gfq_batch_times waits for that stream and writes, per product, the microseconds from the
