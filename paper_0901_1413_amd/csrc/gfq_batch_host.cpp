@@ -144,6 +144,24 @@ void gfq::plan_batch(int count, const gfq_problem *problems, const gfq_config *c
     *nitems = n;
 }
 
+hipError_t gfq::launch_group_lists(const std::vector<BatchGroup> &groups, const BatchList &base, hipStream_t st) {
+    const size_t ng = groups.size();
+    SidePool *sp = ng > 1 ? side_pool(st, ng - 1) : nullptr;
+    hipError_t e = sp ? hipEventRecord(sp->fork, st) : hipSuccess;
+    for (size_t j = 0; e == hipSuccess && j < ng; j++) {
+        const BatchGroup &gr = groups[j];
+        const bool side = sp && j > 0;
+        hipStream_t s = side ? sp->streams[j - 1] : st;
+        if (side) e = hipStreamWaitEvent(s, sp->fork, 0);
+        BatchList l = base;
+        l.items = base.items + gr.item_off;
+        if (e == hipSuccess) e = launch_batched(gr.q, gr.R, gr.twd, l, (int)gr.items.size(), gr.lds, s);
+        if (e == hipSuccess && side) e = hipEventRecord(sp->done[j - 1], s);
+    }
+    for (size_t j = 1; e == hipSuccess && sp && j < ng; j++) e = hipStreamWaitEvent(st, sp->done[j - 1], 0);
+    return e;
+}
+
 size_t gfq::batch_tiles_bound(int64_t m, int64_t n) {
     if (m <= 0 || n <= 0) return 0;
     return (size_t)((m + 255) / 256) * (size_t)((words_of(n) + 15) / 16);
@@ -240,23 +258,12 @@ int gfq_batch_launch(gfq_batch *b) {
     if (!b) return GFQ_ENULL;
     hipStream_t st = current_stream();
     hipError_t e = launch_batch_stamp(b->times, st);
-    const size_t ng = b->groups.size();
-    SidePool *sp = ng > 1 ? side_pool(st, ng - 1) : nullptr;
-    if (e == hipSuccess && sp) e = hipEventRecord(sp->fork, st);
-    for (size_t j = 0; e == hipSuccess && j < ng; j++) {
-        const BatchGroup &gr = b->groups[j];
-        const bool side = sp && j > 0;
-        hipStream_t s = side ? sp->streams[j - 1] : st;
-        if (side) e = hipStreamWaitEvent(s, sp->fork, 0);
-        BatchList l;
-        l.prods = b->prods;
-        l.items = b->items + gr.item_off;
-        l.prod_done = b->prod_done;
-        l.prod_time = b->times + 1;
-        if (e == hipSuccess) e = launch_batched(gr.q, gr.R, gr.twd, l, (int)gr.items.size(), gr.lds, s);
-        if (e == hipSuccess && side) e = hipEventRecord(sp->done[j - 1], s);
-    }
-    for (size_t j = 1; e == hipSuccess && sp && j < ng; j++) e = hipStreamWaitEvent(st, sp->done[j - 1], 0);
+    BatchList base;
+    base.prods = b->prods;
+    base.items = b->items;
+    base.prod_done = b->prod_done;
+    base.prod_time = b->times + 1;
+    if (e == hipSuccess) e = launch_group_lists(b->groups, base, st);
     return e == hipSuccess ? GFQ_OK : hip_fail(e, "batch launch");
 }
 

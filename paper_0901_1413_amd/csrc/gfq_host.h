@@ -29,6 +29,10 @@ struct BatchGroup {
 // consecutive item offsets; *nitems = total tiles.  The problems must be valid.
 void plan_batch(int count, const gfq_problem *problems, const gfq_config *cfgs, BatchProd *prods,
                 std::vector<BatchGroup> *groups, size_t *nitems);
+// Launch every group's work list: the first on st, the others forked onto side streams of
+// st and joined back into it (one after another on st while st is captured and has no side
+// streams yet).  base: the batch's lists with items pointing at item 0.
+hipError_t launch_group_lists(const std::vector<BatchGroup> &groups, const BatchList &base, hipStream_t st);
 // Upper bound of the tiles of an m x n product in any batch (the smallest tile height).
 size_t batch_tiles_bound(int64_t m, int64_t n);
 // Allow every batched work-list kernel the dynamic LDS of its largest slab width.

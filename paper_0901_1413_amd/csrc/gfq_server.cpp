@@ -178,6 +178,9 @@ hipError_t launch_batch(gfq_server *s, Slot &sl) {
     hipError_t e = hipMemcpyAsync(sl.dev, h, used, hipMemcpyHostToDevice, sl.st);
     if (e == hipSuccess)
         e = launch_conv_list((const ConvJob *)sl.dev, (int)pack.size(), pack_blocks, sl.st);
+    // the lists run one after another on the slot's stream: the slots already overlap one
+    // another's batches, and forking each slot's lists onto side streams (as gfq_batch_launch
+    // does) measured slower here (served p99 10.9 -> 13.8 ms)
     for (size_t j = 0; e == hipSuccess && j < groups.size(); j++) {
         BatchList bl;
         bl.prods = (const BatchProd *)(sl.dev + o_prods);
