@@ -397,6 +397,7 @@ int gfq_matmul_sw(int q, int64_t m, int64_t l, int64_t n, const void *A, const v
     a.k = c.k;
     a.S = (a.l + a.k - 1) / a.k;
     int split = std::min(c.split, a.S);
+    split = std::min<int64_t>(split, 65535 / (int64_t)count);      // grid.z = leaves x slices <= 65535
     if ((int64_t)count * a.m >= ((int64_t)1 << 31)) split = 1;   // the partial sums run as one tall matrix
     a.slabs_per_split = (a.S + split - 1) / split;
     split = (a.S + a.slabs_per_split - 1) / a.slabs_per_split;

@@ -209,14 +209,15 @@ SW_MAX_LEVELS = 4
 
 
 def matmul_sw(q: int, A, B, m: int, l: int, n: int, levels: int, out=None, k: int = 0, rows: int = 0,
-              variant=None):
+              variant=None, split: int = 0):
     """C = A B by `levels` levels of Strassen-Winograd over the Four-Russians product
-    (gfq_matmul_sw); k, rows and variant override the leaf configuration."""
+    (gfq_matmul_sw); k, rows, variant and split override the leaf configuration (split
+    defaults to 1 when any of them is given)."""
     if out is None:
         out = empty_packed(q, m, n, A.device)
     _bind_stream()
     cp = None
-    if k or rows or variant is not None:
+    if k or rows or variant is not None or split:
         c = Config()
         _check(load().gfq_choose_config(q, m, l, n, ctypes.byref(c)), "gfq_choose_config")
         if k:
@@ -225,7 +226,7 @@ def matmul_sw(q: int, A, B, m: int, l: int, n: int, levels: int, out=None, k: in
             c.rows = rows
         if variant is not None:
             c.variant = variant
-        c.split = 1
+        c.split = split or 1
         cp = ctypes.byref(c)
     _check(load().gfq_matmul_sw(q, m, l, n, _VP(A.data_ptr()), _VP(B.data_ptr()), _VP(out.data_ptr()), levels, cp),
            "gfq_matmul_sw")

@@ -136,3 +136,12 @@ def test_sw_concurrent_streams(gfq_gpu):
     torch.cuda.synchronize()
     for i, (A, B) in enumerate(pairs):
         assert np.array_equal(g.unpack(q, outs[i], m, n).cpu().numpy(), oracle.matmul(q, A, B)), i
+
+
+def test_sw_four_levels_with_slices(gfq_gpu):
+    """Four levels give 2401 leaves; a leaf configuration with 64 slices of the inner
+    dimension is cut down so that leaves x slices fit one grid (65535)."""
+    g = gfq_gpu
+    A, B = inputs.pair(3, 300, 9000, 200, cfg=239)
+    check_sw(g, 3, A, B, 4, k=4)
+    check_sw(g, 3, A, B, 4, k=4, rows=256, split=64)
