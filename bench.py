@@ -37,7 +37,19 @@ M = L = N = 8192
 FIELDS = (3, 5)
 PEAK_VALU_OPS = 256 * 64 * 2.4e9          # 32-bit VALU lane-operations per second
 PEAK_HBM = 8.0e12
-SECTIONS = ("c1", "c2_k", "mfma", "c3", "ext", "sw", "c4", "c5")
+SECTIONS = ("c1", "c2_k", "mfma", "c3", "ext", "sw", "table1", "c4", "c5")
+
+# The paper's Table 1, its own implementation's column: ms for square n x n products on a
+# 2.6 GHz Opteron (context only; other hardware, not a target).  F_{2^2} and F_{2^3} were
+# computed there through M4RI products over F_2.
+PAPER_TABLE1_MS = {
+    3: {100: 0.032, 500: 1.68, 1000: 12.2, 2500: 199},
+    5: {100: 0.110, 500: 6.47, 1000: 49.4, 2500: 742},
+    7: {100: 0.105, 500: 6.04, 1000: 45.7, 2500: 672},
+    4: {100: 0.091, 500: 1.89, 1000: 9.5, 2500: 132},
+    8: {100: 0.187, 500: 3.85, 1000: 20.6, 2500: 261},
+    9: {100: 0.097, 500: 5.22, 1000: 37.6, 2500: 601},
+}
 
 # Per-unit operation counts of the method on gfx950 (three-input bitwise instructions).
 # A unit is (row of C, slab of k rows of B, 32-column word).  Accumulate: the slab's D
@@ -601,6 +613,41 @@ def section_sw(ctx, reps=5, sizes=(8192, 16384), fields=(3, 5, 4, 8), max_levels
 
 
 # ------------------------------------------------------------------------------------
+# table1: the paper's Table 1 shapes (square n = 100 .. 2500, six fields), for context
+# ------------------------------------------------------------------------------------
+
+def section_table1(ctx, reps=20):
+    import numpy as np
+    torch, gfq, inputs = ctx.torch, ctx.gfq, ctx.inputs
+    res = {}
+    for q, row in PAPER_TABLE1_MS.items():
+        out = {}
+        for n, paper_ms in row.items():
+            A, B = inputs.pair(q, n, n, n, cfg=8, idx=q * 10000 + n)
+            Ap, Bp = gfq.pack(q, ctx.up(A)), gfq.pack(q, ctx.up(B))
+            Cp = gfq.empty_packed(q, n, n)
+            gfq.matmul(q, Ap, Bp, n, n, n, out=Cp)
+            torch.cuda.synchronize()
+            C = gfq.unpack(q, Cp, n, n).cpu().numpy()
+            rows = np.arange(n) if n <= 1000 else np.arange(0, n, 7)
+            ok = bool(np.array_equal(C[rows], ctx.oracle.matmul(q, A[rows], B)))
+            ev = ctx.events(2)
+            ev[0].record()
+            for _ in range(reps):
+                gfq.matmul(q, Ap, Bp, n, n, n, out=Cp)
+            ev[1].record()
+            torch.cuda.synchronize()
+            ms = ev[0].elapsed_time(ev[1]) / reps
+            out[str(n)] = {"product_ms": round(ms, 4), "field_ops_per_s": 2.0 * n ** 3 / (ms * 1e-3),
+                           "paper_opteron_ms": paper_ms, "bit_exact_vs_oracle": ok,
+                           "rows_checked": "all" if n <= 1000 else "every 7th"}
+        res[("GF" if q in (4, 8) else "F_") + str(q)] = out
+    return {"workload": "square n x n products as in the paper's Table 1, uniform entries, one product per "
+                        "launch (tuned configuration); paper_opteron_ms is the paper's own column (2.6 GHz "
+                        "Opteron), context only", **res}
+
+
+# ------------------------------------------------------------------------------------
 # c4: 4096 products of mixed fields and shapes, batched vs plain
 # ------------------------------------------------------------------------------------
 
@@ -861,6 +908,9 @@ def main():
         log("sw")
         res["sw"] = section_sw(ctx)
         torch.cuda.empty_cache()
+    if "table1" in sections:
+        log("table1")
+        res["table1"] = section_table1(ctx)
     if "c4" in sections:
         log("c4")
         res["c4"] = section_c4(ctx)
