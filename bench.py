@@ -285,8 +285,21 @@ def section_c1(ctx, reps=200):
     for _ in range(10):
         path()
     torch.cuda.synchronize()
+    # the same path captured once into a HIP graph (one graph launch instead of five kernel
+    # launches); a first eager pass on the capture stream creates that stream's workspace
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        path()
+        side.synchronize()
+        with torch.cuda.graph(graph, stream=side):
+            path()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
     res = {}
-    for name, fn in (("path", path), ("product", lambda: gfq.matmul(3, Ap, Bp, n, n, n, out=Cp))):
+    for name, fn in (("path", path), ("path_graph", graph.replay),
+                     ("product", lambda: gfq.matmul(3, Ap, Bp, n, n, n, out=Cp))):
         ev = ctx.events(2 * reps)
         for i in range(reps):
             ev[2 * i].record()
@@ -296,13 +309,19 @@ def section_c1(ctx, reps=200):
         xs = [ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(reps)]
         res[name] = {"p50_us": round(percentile(xs, 50) * 1e3, 2), "p99_us": round(percentile(xs, 99) * 1e3, 2),
                      "field_ops_per_s_at_p50": 2.0 * n ** 3 / (percentile(xs, 50) * 1e-3)}
-    path()
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     want = ctx.oracle.matmul(3, A, B)
     t_or = time.perf_counter() - t0
+    Cd.zero_()
+    graph.replay()
+    torch.cuda.synchronize()
+    graph_exact = bool(np.array_equal(Cd.cpu().numpy(), want))
+    path()
+    torch.cuda.synchronize()
+    del graph
     return {"workload": "F_3 A, B 512x512 uniform", "reps": reps, **res,
             "bit_exact_vs_oracle": bool(np.array_equal(Cd.cpu().numpy(), want)),
+            "graph_replay_bit_exact": graph_exact,
             "oracle_ms": round(t_or * 1e3, 2), "oracle_cores": ctx.oracle.max_threads(),
             "config": gfq.choose_config(3, n, n, n)}
 
