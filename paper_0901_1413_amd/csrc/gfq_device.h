@@ -25,7 +25,7 @@ template <int Q> struct FT;
 // receives T[phi_0] and -T[phi_1] (the complement) per slab.
 template <> struct FT<3> {
     static constexpr int P = 2, PT = 2, D = 2, GP = 2, PA = 4;
-    static constexpr bool SPLIT_PREFIX = false;
+    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false;
     static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0] ^ x[1]; f[1] = x[1]; }
     __device__ static void to_table(const u32 *x, u32 *t) { f3_to_bin(x[0], x[1], t); }
@@ -54,7 +54,7 @@ template <> struct FT<3> {
 // planes, so alpha_d T[phi_d] costs nothing; the accumulator is a carry-save pair mod 7.
 template <> struct FT<7> {
     static constexpr int P = 3, PT = 3, D = 3, GP = 3, PA = 6;
-    static constexpr bool SPLIT_PREFIX = true;
+    static constexpr bool SPLIT_PREFIX = true, HALF_ROWS = false;
     static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; f[2] = x[2]; }
     __device__ static void to_table(const u32 *x, u32 *t) { t[0] = x[0]; t[1] = x[1]; t[2] = x[2]; }
@@ -93,7 +93,7 @@ template <> struct FT<7> {
 // scaled rows enter it together (f5_csa_slab).
 template <> struct FT<5> {
     static constexpr int P = 3, PT = 3, D = 3, GP = 3, PA = 8;
-    static constexpr bool SPLIT_PREFIX = true;
+    static constexpr bool SPLIT_PREFIX = true, HALF_ROWS = false;
     static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; f[2] = x[2]; }
     __device__ static void to_table(const u32 *x, u32 *t) { t[0] = x[0]; t[1] = x[1]; t[2] = x[2]; }
@@ -130,7 +130,7 @@ template <> struct FT<5> {
 // T[phi_0] + x T[phi_1]; with x (c0 + c1 x) = c1 + (c0 + c1) x that is two XOR planes.
 template <> struct FT<4> {
     static constexpr int P = 2, PT = 2, D = 2, GP = 2, PA = 2;
-    static constexpr bool SPLIT_PREFIX = false;
+    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false;
     static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; }
     __device__ static void to_table(const u32 *x, u32 *t) { t[0] = x[0]; t[1] = x[1]; }
@@ -154,7 +154,7 @@ template <> struct FT<4> {
 // Same packed operands and product as FT<4>; selected by the configuration.
 template <> struct FT<GF4_KARATSUBA> {
     static constexpr int P = 2, PT = 3, D = 3, GP = 1, PA = 2;
-    static constexpr bool SPLIT_PREFIX = false;
+    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false;
     static constexpr int gplane(int d, int) { return d; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; f[2] = x[0] ^ x[1]; }
     __device__ static void to_table(const u32 *x, u32 *t) { t[0] = x[0]; t[1] = x[1]; t[2] = x[0] ^ x[1]; }
@@ -177,7 +177,7 @@ template <> struct FT<GF4_KARATSUBA> {
 // x^2 T[phi_2] (g8_acc, six operations for three planes).
 template <> struct FT<8> {
     static constexpr int P = 3, PT = 3, D = 3, GP = 3, PA = 3;
-    static constexpr bool SPLIT_PREFIX = false;
+    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false;
     static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; f[2] = x[2]; }
     __device__ static void to_table(const u32 *x, u32 *t) { t[0] = x[0]; t[1] = x[1]; t[2] = x[2]; }
@@ -201,7 +201,9 @@ template <> struct FT<8> {
 // and imaginary += T0.im - T1.im + T2.re - T3.re, into two carry-save pairs mod 3.
 template <> struct FT<9> {
     static constexpr int P = 4, PT = 4, D = 4, GP = 4, PA = 8;
-    static constexpr bool SPLIT_PREFIX = false;
+    // HALF_ROWS: a row's gathers are consumed in two halves (accumulate_half), so only half a
+    // row of 128-bit reads is in flight at a time and four rows per lane fit the registers
+    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = true;
     static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0] ^ x[1]; f[1] = x[1]; f[2] = x[2] ^ x[3]; f[3] = x[3]; }
     __device__ static void to_table(const u32 *x, u32 *t) { f3_to_bin(x[0], x[1], t); f3_to_bin(x[2], x[3], t + 2); }
@@ -218,6 +220,23 @@ template <> struct FT<9> {
         csa_step_neg<2>(Si, Ki, t[1] + 2);
         csa_step<2>(Si, Ki, t[2]);
         csa_step_neg<2>(Si, Ki, t[3]);
+    }
+    // the same additions in two halves: H = 0 takes T[phi_0] - T[phi_1] (t[0], t[1]), H = 1
+    // takes i T[phi_2] - i T[phi_3] (t[0], t[1] holding phi_2, phi_3); the order of carry-save
+    // steps does not change the residue the accumulator resolves to
+    template <int H> __device__ static void accumulate_half(u32 *c, const u32 (*t)[P]) {
+        u32 *Sr = c, *Kr = c + 2, *Si = c + 4, *Ki = c + 6;
+        if (H == 0) {
+            csa_step<2>(Sr, Kr, t[0]);
+            csa_step_neg<2>(Sr, Kr, t[1]);
+            csa_step<2>(Si, Ki, t[0] + 2);
+            csa_step_neg<2>(Si, Ki, t[1] + 2);
+        } else {
+            csa_step_neg<2>(Sr, Kr, t[0] + 2);
+            csa_step<2>(Sr, Kr, t[1] + 2);
+            csa_step<2>(Si, Ki, t[0]);
+            csa_step_neg<2>(Si, Ki, t[1]);
+        }
     }
     __device__ static void finish(const u32 *c, u32 *out) {
         u32 v[2];
@@ -247,7 +266,7 @@ template <> struct FT<9> {
 // FT<8>; selected by the configuration.
 template <> struct FT<GF8_TRINOMIAL> {
     static constexpr int P = 3, PT = 6, D = 6, GP = 1, PA = 3;
-    static constexpr bool SPLIT_PREFIX = false;
+    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false;
     static constexpr int gplane(int d, int) { return d; }
     __device__ static void phis(const u32 *x, u32 *f) {
         f[0] = x[0]; f[1] = x[1]; f[2] = x[2]; f[3] = x[0] ^ x[1]; f[4] = x[0] ^ x[2]; f[5] = x[1] ^ x[2];
@@ -277,7 +296,7 @@ template <> struct FT<GF8_TRINOMIAL> {
 // operands and product as FT<9>; selected by the configuration.
 template <> struct FT<F9_KARATSUBA> {
     static constexpr int P = 4, PT = 6, D = 6, GP = 2, PA = 12;
-    static constexpr bool SPLIT_PREFIX = false;
+    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false;
     static constexpr int gplane(int d, int p) { return (d >> 1) * 2 + p; }
     __device__ static void phis(const u32 *x, u32 *f) {
         const F3v s = f3_add(F3v{x[0], x[1]}, F3v{x[2], x[3]});   // a0 + a1

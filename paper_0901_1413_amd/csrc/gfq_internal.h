@@ -59,10 +59,10 @@ inline bool split_prefix(int q) { return q == 5 || q == 7; }   // FT<q>::SPLIT_P
 inline int words_of(int64_t cols) { return (int)(((cols + 127) / 128) * 4); }
 // Rows of C per lane: bounded by the accumulator registers (8 planes per word for F_5 and
 // F_9, 6 for F_7, 4 for F_3, 3 for GF(8), 2 for GF(4)) and the gathered table rows in
-// flight (F_9: two rows of 16 128-bit reads).  The work-list kernels of batches use at
+// flight (F_9 by Karatsuba: two rows of twelve 128-bit reads and 12 accumulator planes).  The work-list kernels of batches use at
 // most 8.
 inline int max_rows_per_lane(int q) {
-    return (q == 9 || q == F9_KARATSUBA) ? 2 : (q == 5 || q == 7 ? 4 : (q == 4 || q == GF4_KARATSUBA ? 16 : 8));
+    return q == F9_KARATSUBA ? 2 : (q == 5 || q == 7 || q == 9 ? 4 : (q == 4 || q == GF4_KARATSUBA ? 16 : 8));
 }
 inline int max_rows_per_lane_batch(int q) { return q == 9 ? 2 : (q == 5 || q == 7 ? 4 : 8); }
 
@@ -127,6 +127,7 @@ inline MMPlan mm_plan(int q, int k, int rowsTile) {
     if (r > max_rows_per_lane(q)) r = max_rows_per_lane(q);
     if (r > 8 && p.twd < 16) r = 8;              // narrow tiles: 16 rows per lane would spill
     if (r > 4 && p.twd < 16 && (q == 8 || q == GF8_TRINOMIAL)) r = 4;    // ... and for GF(8) eight would
+    if (r > 2 && p.twd < 16 && q == 9) r = 2;                             // ... and for F_9 four would
     for (; r >= 2; r /= 2) {
         p.R = r;
         p.TM = NT_MM / lpr * r;

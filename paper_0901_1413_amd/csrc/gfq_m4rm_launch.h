@@ -64,11 +64,12 @@ static hipError_t launch_mm(const MMArgs &a0, const MMPlan &plan, const MMStride
 
 template <bool STRIDED, int Q, int TWD, int REP>
 static hipError_t launch_mm_rows(const MMArgs &a, const MMPlan &plan, const MMStrides &sd, hipStream_t st) {
-    constexpr bool two_only = Q == 9 || Q == F9_KARATSUBA;   // F_9: two rows per lane only
+    // two rows per lane only: F_9 by Karatsuba, and F_9 on narrow tiles (four would spill)
+    constexpr bool two_only = Q == F9_KARATSUBA || (Q == 9 && TWD < 16);
     if (plan.R == 2 || two_only) return launch_mm<STRIDED, Q, TWD, REP, 2>(a, plan, sd, st);
     if constexpr (two_only) {
         return hipErrorInvalidValue;
-    } else if constexpr (Q == 5 || Q == 7 || ((Q == 8 || Q == GF8_TRINOMIAL) && TWD < 16)) {
+    } else if constexpr (Q == 5 || Q == 7 || Q == 9 || ((Q == 8 || Q == GF8_TRINOMIAL) && TWD < 16)) {
         return launch_mm<STRIDED, Q, TWD, REP, 4>(a, plan, sd, st);       // eight rows per lane would spill
     } else {
         if (plan.R == 4) return launch_mm<STRIDED, Q, TWD, REP, 4>(a, plan, sd, st);

@@ -43,6 +43,8 @@ __device__ __forceinline__ u32 comp4(const uint4 &v, int i) {
     return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
 }
 
+template <int H> struct half_tag { static constexpr int value = H; };
+
 // One tile of the product: column tile bx, row tile by, slab slice bz of the problem `a`.
 // Called by every thread of an NT-thread workgroup; uses the workgroup's dynamic LDS.
 template <int Q, int TWD, int REP, int R, int NT>
@@ -352,6 +354,37 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
             F::accumulate(acc[r][i], ti);
         }
     };
+    // half a row's gathers (HALF_ROWS fields): D / 2 table rows starting at d = h * D / 2
+    constexpr int DH = D / 2 > 0 ? D / 2 : 1;
+    auto fetch_half = [&](const u32 *iw, int r, int h, u32 lo, uint4 (&t)[DH][GP]) {
+#pragma unroll
+        for (int dd = 0; dd < DH; dd++) {
+            const int d = h * DH + dd;
+            const u32 x = iw[r * IBW + (d >> 1)];
+            const u32 off = ((d & 1) ? (x >> 16) : (x & 0xffffu)) | lo;
+            lds_u32x4 *row = (lds_u32x4 *)(uintptr_t)off;
+#pragma unroll
+            for (int p = 0; p < GP; p++) {
+                const u32x4 v = row[F::gplane(d, p) * (SRB / 16)];
+                t[dd][p] = make_uint4(v.x, v.y, v.z, v.w);
+            }
+        }
+    };
+    auto consume_half_impl = [&](auto hc, int r, const uint4 (&t)[DH][GP]) {
+        constexpr int H = decltype(hc)::value;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            u32 ti[DH][GP];
+#pragma unroll
+            for (int dd = 0; dd < DH; dd++)
+#pragma unroll
+                for (int p = 0; p < GP; p++) ti[dd][p] = comp4(t[dd][p], i);
+            if constexpr (F::HALF_ROWS) F::template accumulate_half<H>(acc[r][i], ti);
+        }
+    };
+    auto consume_half0 = [&](int r, const uint4 (&t)[DH][GP]) { consume_half_impl(half_tag<0>{}, r, t); };
+    auto consume_half1 = [&](int r, const uint4 (&t)[DH][GP]) { consume_half_impl(half_tag<1>{}, r, t); };
+
     // software-pipelined: the reads of row r+1 are issued before row r is accumulated
     auto gather = [&](int s) {
         const u32 lo = laneoff | ((s & 1) ? TB1 : 0u);
@@ -370,14 +403,28 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
                 iw[w] = v.x; iw[w + 1] = v.y;
             }
         }
-        uint4 ta[D][GP], tb[D][GP];
-        fetch(iw, 0, lo, ta);
+        if constexpr (F::HALF_ROWS) {
+            // half rows: the second half of row r is read while the first is added, and the
+            // first half of row r+1 while the second is added
+            uint4 h0[D / 2][GP], h1[D / 2][GP];
+            fetch_half(iw, 0, 0, lo, h0);
 #pragma unroll
-        for (int r = 0; r < R; r += 2) {
-            if (r + 1 < R) fetch(iw, r + 1, lo, tb);
-            consume(r, ta);
-            if (r + 2 < R) fetch(iw, r + 2, lo, ta);
-            if (r + 1 < R) consume(r + 1, tb);
+            for (int r = 0; r < R; r++) {
+                fetch_half(iw, r, 1, lo, h1);
+                consume_half0(r, h0);
+                if (r + 1 < R) fetch_half(iw, r + 1, 0, lo, h0);
+                consume_half1(r, h1);
+            }
+        } else {
+            uint4 ta[D][GP], tb[D][GP];
+            fetch(iw, 0, lo, ta);
+#pragma unroll
+            for (int r = 0; r < R; r += 2) {
+                if (r + 1 < R) fetch(iw, r + 1, lo, tb);
+                consume(r, ta);
+                if (r + 2 < R) fetch(iw, r + 2, lo, ta);
+                if (r + 1 < R) consume(r + 1, tb);
+            }
         }
     };
 
