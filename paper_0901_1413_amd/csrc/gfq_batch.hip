@@ -54,7 +54,7 @@ const void *batched_kernel(int q, int R, int twd) {
         case 4: return narrow_kernel_ptr<4>(twd);
         case 5: return narrow_kernel_ptr<5>(twd);
         case 8: return narrow_kernel_ptr<8>(twd);
-        case 9: return twd == 8 ? (const void *)m4rm_list_kernel<9, 8, 8, 2, NT_MM> : nullptr;   // 4 words would spill
+        case 9: return narrow_kernel_ptr<9>(twd);
         default: return narrow_kernel_ptr<7>(twd);
         }
     }
@@ -63,7 +63,7 @@ const void *batched_kernel(int q, int R, int twd) {
     case 4: return R == 2 ? list_kernel_ptr<4, 2>() : list_kernel_ptr<4, 8>();
     case 5: return R == 2 ? list_kernel_ptr<5, 2>() : list_kernel_ptr<5, 4, 1>();   // batch_srb: 64 at R = 4
     case 8: return R == 2 ? list_kernel_ptr<8, 2>() : list_kernel_ptr<8, 8>();
-    case 9: return list_kernel_ptr<9, 2>();      // four rows per lane would spill here
+    case 9: return R == 2 ? list_kernel_ptr<9, 2>() : list_kernel_ptr<9, 4>();
     default: return R == 2 ? list_kernel_ptr<7, 2>() : list_kernel_ptr<7, 4, 1>();   // batch_srb: 64 at R = 4
     }
 }

@@ -86,7 +86,7 @@ void gfq::plan_batch(int count, const gfq_problem *problems, const gfq_config *c
         // kernel bound the slab width.
         int R = c.rows <= 256 ? 2 : max_rows_per_lane_batch(p.q);
         int twd = 16;
-        if (p.m > 256 && p.n <= 128 && p.q != 9) twd = 4, R = 2;   // F_9: 4-word tiles would spill
+        if (p.m > 256 && p.n <= 128) twd = 4, R = 2;
         else if (p.m > 256 && p.n <= 256) twd = 8, R = 2;
         const int srb = twd == 16 ? batch_srb(p.q, R) : 256;
         int k = std::min(c.k, batch_kmax(p.q, twd == 16 ? R : 2));

@@ -64,7 +64,7 @@ inline int words_of(int64_t cols) { return (int)(((cols + 127) / 128) * 4); }
 inline int max_rows_per_lane(int q) {
     return q == F9_KARATSUBA ? 2 : (q == 5 || q == 7 || q == 9 ? 4 : (q == 4 || q == GF4_KARATSUBA ? 16 : 8));
 }
-inline int max_rows_per_lane_batch(int q) { return q == 9 ? 2 : (q == 5 || q == 7 ? 4 : 8); }
+inline int max_rows_per_lane_batch(int q) { return q == 5 || q == 7 || q == 9 ? 4 : 8; }
 
 // Table super-row bytes for field q and slab width k: the widest of 256, 128, 64, 32, 16
 // such that both table buffers fit TABLES_LDS (0 if none does).
@@ -94,7 +94,7 @@ struct MMPlan {
     int srb;      // table super-row bytes
     int twd;      // tile width in words per plane
     int rep;      // copies of the tile row per super-row
-    int R;        // rows of C per lane (2, 4 or 8)
+    int R;        // rows of C per lane (2, 4, 8 or 16)
     int TM;       // rows of C per workgroup
     u32 tb1;      // LDS offset of the second table
     size_t lds;   // dynamic LDS bytes
