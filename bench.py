@@ -621,6 +621,19 @@ def section_sw(ctx, reps=5, sizes=(8192, 16384), fields=(3, 5, 4, 8), max_levels
                 ms = ev[0].elapsed_time(ev[1]) / reps
                 row[f"levels{levels}"] = {"ms": round(ms, 4), "field_ops_per_s": 2.0 * N ** 3 / (ms * 1e-3),
                                           "equals_plain": same}
+            # the tuner's choice for this size class (GFQ_SW_AUTO; 0 levels without an entry)
+            gfq.matmul_sw(q, Ap, Bp, N, N, N, gfq.SW_AUTO, out=Cp)
+            torch.cuda.synchronize()
+            same = bool(torch.equal(Cp, ref))
+            ev = ctx.events(2)
+            ev[0].record()
+            for _ in range(reps):
+                gfq.matmul_sw(q, Ap, Bp, N, N, N, gfq.SW_AUTO, out=Cp)
+            ev[1].record()
+            torch.cuda.synchronize()
+            ms = ev[0].elapsed_time(ev[1]) / reps
+            row["auto"] = {"levels": gfq.tune_sw_lookup(q, N, N, N), "ms": round(ms, 4),
+                           "field_ops_per_s": 2.0 * N ** 3 / (ms * 1e-3), "equals_plain": same}
             base = row["levels0"]["ms"]
             for v in row.values():
                 v["speedup"] = round(base / v["ms"], 3)

@@ -150,7 +150,9 @@ typedef struct {
  * to a multiple of 32; the missing rows and columns of the second halves are zero.  The
  * arithmetic is exact, so C is the same packed product as gfq_matmul's, byte for byte.
  * levels  0..GFQ_SW_MAX_LEVELS; 0 is gfq_matmul_config(..., leaf).  All 7^levels leaf
- *         products run in one launch of the product kernel.
+ *         products run in one launch of the product kernel.  GFQ_SW_AUTO takes the number
+ *         of levels the tuner cached for the product's size class (gfq_tune with
+ *         GFQ_TUNE_SW), 0 when there is none.
  * leaf    configuration of the leaf products (NULL: the slab width and route chosen for
  *         one leaf, the tile height and inner-dimension slices fitted to all leaves together);
  *         with more than one slice, the leaves' partial products are summed by one launch.
@@ -158,6 +160,7 @@ typedef struct {
  * every level live in the per-(device, stream) workspace (about (7/4)^levels times the
  * packed sizes of A, B and C together, summed over the levels). */
 #define GFQ_SW_MAX_LEVELS 4
+#define GFQ_SW_AUTO (-1)
 int gfq_matmul_sw(int q, int64_t m, int64_t l, int64_t n, const void *A, const void *B, void *C, int levels,
                   const gfq_config *leaf);
 
@@ -200,18 +203,23 @@ int gfq_batch_destroy(gfq_batch *batch);
  * chosen configuration.  Modes: 0 = single products (k, tile height and split for this
  * shape's size class, where the class rounds m, l, n up to powers of two from 64 to 16384);
  * GFQ_TUNE_BATCH = products inside batches (k and tile height for the class of (m, l); n is
- * ignored).  gfq_choose_config and gfq_batch_create use cached entries when they exist.
+ * ignored); GFQ_TUNE_SW = the number of Strassen-Winograd levels, 0 .. GFQ_SW_MAX_LEVELS - 1,
+ * for gfq_matmul_sw with GFQ_SW_AUTO (timed with the default leaf choice; the entry holds
+ * the levels in its k field, the other fields 0; more levels are chosen only when 2% faster
+ * than the fastest with fewer).  gfq_choose_config, gfq_batch_create and gfq_matmul_sw (GFQ_SW_AUTO) use cached
+ * entries when they exist.
  * gfq_tune_lookup returns GFQ_OK and the entry if the class is cached, GFQ_EAGAIN if not.
  * gfq_tune_save / gfq_tune_load write / merge the cache as text, one entry per line.
  * gfq_tune_clear empties it.
  * gfq_tune: each of m, l, n in 1 .. 65536 (else GFQ_EDIM); q in {3,4,5,7,8,9} (GFQ_EFIELD);
- * mode 0 or GFQ_TUNE_BATCH (GFQ_EINVAL).  It runs on the calling thread's stream, waits for
+ * mode 0, GFQ_TUNE_BATCH or GFQ_TUNE_SW (GFQ_EINVAL).  It runs on the calling thread's stream, waits for
  * its own launches, and keeps its scratch operands (one device buffer, filled with
  * pseudo-random words) until the process ends; GFQ_ENOMEM if that buffer cannot be had.
  * Concurrent calls on one device measure each other: tune from one thread at a time.
  * gfq_tune_load returns GFQ_EINVAL if the file cannot be read or holds a malformed or
  * out-of-range entry (the valid entries are merged all the same). */
 #define GFQ_TUNE_BATCH 1
+#define GFQ_TUNE_SW 2
 int gfq_tune(int q, int64_t m, int64_t l, int64_t n, int mode, gfq_config *out);
 int gfq_tune_lookup(int q, int64_t m, int64_t l, int64_t n, int mode, gfq_config *out);
 int gfq_tune_save(const char *path);

@@ -344,6 +344,10 @@ int gfq_matmul_sw(int q, int64_t m, int64_t l, int64_t n, const void *A, const v
                   const gfq_config *leaf) {
     int st = validate_mm(q, m, l, n, A, B, C);
     if (st != GFQ_OK) return st;
+    if (levels == GFQ_SW_AUTO) {
+        gfq_config t;
+        levels = (m > 0 && l > 0 && n > 0 && gfq_tune_lookup(q, m, l, n, GFQ_TUNE_SW, &t) == GFQ_OK) ? t.k : 0;
+    }
     if (levels < 0 || levels > GFQ_SW_MAX_LEVELS) return GFQ_EINVAL;
     if (leaf) {
         st = check_config(q, *leaf);

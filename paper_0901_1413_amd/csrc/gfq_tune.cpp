@@ -4,7 +4,8 @@
 // Single products (mode 0) are tuned on their own shape over slab width k, tile height and
 // inner-dimension split; products inside batches (GFQ_TUNE_BATCH) over k and tile height,
 // timed as a batch of identical products of the class's shape, since a batch supplies the
-// parallelism that split supplies to a single product.
+// parallelism that split supplies to a single product; Strassen-Winograd products
+// (GFQ_TUNE_SW) over the number of levels (its entry keeps the levels in the k field).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -106,9 +107,11 @@ int gfq_tune_lookup(int q, int64_t m, int64_t l, int64_t n, int mode, gfq_config
     std::string arch;
     if (!arch_name(&arch)) return GFQ_EAGAIN;
     std::lock_guard<std::mutex> lk(g_mu);
-    auto it = g_cache.find(make_key(arch, mode == GFQ_TUNE_BATCH ? GFQ_TUNE_BATCH : 0, q, m, l, n));
+    const int md = (mode == GFQ_TUNE_BATCH || mode == GFQ_TUNE_SW) ? mode : 0;
+    auto it = g_cache.find(make_key(arch, md, q, m, l, n));
     if (it == g_cache.end()) return GFQ_EAGAIN;
     *out = it->second;
+    if (md == GFQ_TUNE_SW) return GFQ_OK;             // k holds the number of levels
     // the cached split belongs to the class; never split further than the slabs allow
     if (l > 0) {
         const int64_t S = (l + out->k - 1) / out->k;
@@ -122,7 +125,7 @@ int gfq_tune(int q, int64_t m, int64_t l, int64_t n, int mode, gfq_config *out) 
     if (!out) return GFQ_ENULL;
     if (!valid_field(q)) return GFQ_EFIELD;
     if (m <= 0 || l <= 0 || n <= 0 || m > (1 << 16) || l > (1 << 16) || n > (1 << 16)) return GFQ_EDIM;
-    if (mode != 0 && mode != GFQ_TUNE_BATCH) return GFQ_EINVAL;
+    if (mode != 0 && mode != GFQ_TUNE_BATCH && mode != GFQ_TUNE_SW) return GFQ_EINVAL;
     std::string arch;
     if (!arch_name(&arch)) return GFQ_EHIP;
     hipStream_t st = current_stream();
@@ -133,7 +136,37 @@ int gfq_tune(int q, int64_t m, int64_t l, int64_t n, int mode, gfq_config *out) 
     int status = GFQ_OK;
     const double ops = 2.0 * (double)m * (double)l * (double)n;
 
-    if (mode == 0) {
+    if (mode == GFQ_TUNE_SW) {
+        // levels 0 .. GFQ_SW_MAX_LEVELS - 1 with the default leaf choice, median of 3
+        const size_t ba = rup(gfq_packed_bytes(q, m, l)), bb = rup(gfq_packed_bytes(q, l, n));
+        const size_t bc = rup(gfq_packed_bytes(q, m, n));
+        void *base = nullptr;
+        status = scratch(ba + bb + bc, &base, st);
+        if (status == GFQ_OK) {
+            char *A = (char *)base, *B = A + ba, *C = B + bb;
+            for (int lev = 0; lev < GFQ_SW_MAX_LEVELS; lev++) {
+                if (gfq_matmul_sw(q, m, l, n, A, B, C, lev, nullptr) != GFQ_OK) continue;
+                std::vector<double> t;
+                bool ok = true;
+                for (int r = 0; ok && r < 3; r++) {
+                    (void)hipEventRecord(e0, st);
+                    ok = gfq_matmul_sw(q, m, l, n, A, B, C, lev, nullptr) == GFQ_OK;
+                    (void)hipEventRecord(e1, st);
+                    ok = ok && hipEventSynchronize(e1) == hipSuccess;
+                    float ms = 0.f;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    t.push_back(ms);
+                }
+                if (!ok) continue;
+                std::sort(t.begin(), t.end());
+                const double ms = t[t.size() / 2];
+                if (ms > 0 && ops / ms > best_rate * 1.02) {      // a level must win by 2%
+                    best_rate = ops / ms;
+                    best = gfq_config{lev, 0, 0, 0};
+                }
+            }
+        }
+    } else if (mode == 0) {
         const size_t ba = rup(gfq_packed_bytes(q, m, l)), bb = rup(gfq_packed_bytes(q, l, n));
         const size_t bc = rup(gfq_packed_bytes(q, m, n));
         void *base = nullptr;
@@ -249,6 +282,14 @@ int gfq_tune_load(const char *path) {
             continue;
         }
         gfq_config c = {k, rows, split, variant};
+        if (mode == GFQ_TUNE_SW) {                     // k holds the number of levels
+            if (k < 0 || k > GFQ_SW_MAX_LEVELS) {
+                status = GFQ_EINVAL;
+                continue;
+            }
+            g_cache[Key(arch, mode, q, bm, bl, bn)] = gfq_config{k, 0, 0, 0};
+            continue;
+        }
         const bool var_ok = variant == GFQ_VARIANT_ROWWISE || (variant == GFQ_VARIANT_KARATSUBA && has_matrix_route(q));
         if (k < 1 || k > KMAX || !var_ok ||
             mm_plan(route_field(q, variant), k, rows).srb == 0 || split < 1 ||

@@ -206,6 +206,8 @@ def matmul(q: int, A, B, m: int, l: int, n: int, out=None, k: int = 0, rows: int
 
 
 SW_MAX_LEVELS = 4
+SW_AUTO = -1          # levels from the tuner's cache (tune_sw), else 0
+TUNE_SW = 2
 
 
 def matmul_sw(q: int, A, B, m: int, l: int, n: int, levels: int, out=None, k: int = 0, rows: int = 0,
@@ -294,6 +296,21 @@ def tune_lookup(q: int, m: int, l: int, n: int, batch: bool = False):
     c = Config()
     st = load().gfq_tune_lookup(q, m, l, n, TUNE_BATCH if batch else 0, ctypes.byref(c))
     return c.as_dict() if st == GFQ_OK else None
+
+
+def tune_sw(q: int, m: int, l: int, n: int) -> int:
+    """Time Strassen-Winograd levels 0 .. SW_MAX_LEVELS - 1 for this size class; cache and
+    return the fastest (matmul_sw(..., SW_AUTO) then uses it)."""
+    c = Config()
+    _bind_stream()
+    _check(load().gfq_tune(q, m, l, n, TUNE_SW, ctypes.byref(c)), "gfq_tune")
+    return c.k
+
+
+def tune_sw_lookup(q: int, m: int, l: int, n: int):
+    c = Config()
+    st = load().gfq_tune_lookup(q, m, l, n, TUNE_SW, ctypes.byref(c))
+    return c.k if st == GFQ_OK else None
 
 
 def tune_save(path: str):

@@ -86,7 +86,8 @@ def test_tune_cache_text_roundtrip(tmp_path):
     f.write_text("# arch mode q m_class l_class n_class k rows split variant\n"
                  "gfx950 0 3 13 13 13 7 2048 2\n"                # an entry without the variant column
                  "gfx950 1 5 9 10 0 6 256 1 0\n"
-                 "gfx950 0 4 12 11 12 6 2048 1 1\n")             # GF(4) by Karatsuba
+                 "gfx950 0 4 12 11 12 6 2048 1 1\n"              # GF(4) by Karatsuba
+                 "gfx950 2 5 13 13 13 3 0 0 0\n")                # Strassen-Winograd: 3 levels
     gfq.tune_clear()
     gfq.tune_load(str(f))
     out = tmp_path / "out.txt"
@@ -94,10 +95,12 @@ def test_tune_cache_text_roundtrip(tmp_path):
     lines = [l.split() for l in out.read_text().splitlines() if not l.startswith("#")]
     assert sorted(lines) == sorted([["gfx950", "0", "3", "13", "13", "13", "7", "2048", "2", "0"],
                                     ["gfx950", "1", "5", "9", "10", "0", "6", "256", "1", "0"],
-                                    ["gfx950", "0", "4", "12", "11", "12", "6", "2048", "1", "1"]])
+                                    ["gfx950", "0", "4", "12", "11", "12", "6", "2048", "1", "1"],
+                                    ["gfx950", "2", "5", "13", "13", "13", "3", "0", "0", "0"]])
     for bad_line in ("gfx950 0 3 13 13 13 11 2048 2\n",       # k = 11 is out of range
-                     "gfx950 0 3 13 13 13 7 2048 2 1\n",      # Karatsuba is for GF(4) only
-                     "gfx950 0 4 13 13 13 7 2048 2 2\n"):     # no such variant
+                     "gfx950 0 3 13 13 13 7 2048 2 1\n",      # no matrix route for F_3
+                     "gfx950 0 4 13 13 13 7 2048 2 2\n",      # no such variant
+                     "gfx950 2 5 13 13 13 5 0 0 0\n"):        # more levels than the maximum
         bad = tmp_path / "bad.txt"
         bad.write_text(bad_line)
         with pytest.raises(gfq.GfqError):

@@ -100,7 +100,7 @@ def test_sw_degenerate_and_validation(gfq_gpu):
         assert not C.cpu().numpy()[:g.packed_bytes(q, 5, 40)].any()
         g.matmul_sw(q, g.empty_packed(q, 0, 3), g.empty_packed(q, 3, 4), 0, 3, 4, 1)
     A = g.empty_packed(3, 64, 64)
-    for bad in (-1, g.SW_MAX_LEVELS + 1):
+    for bad in (-2, g.SW_MAX_LEVELS + 1):                   # -1 is SW_AUTO
         with pytest.raises(g.GfqError) as e:
             g.matmul_sw(3, A, A, 64, 64, 64, bad, out=g.empty_packed(3, 64, 64))
         assert e.value.status == -1
@@ -145,3 +145,45 @@ def test_sw_four_levels_with_slices(gfq_gpu):
     A, B = inputs.pair(3, 300, 9000, 200, cfg=239)
     check_sw(g, 3, A, B, 4, k=4)
     check_sw(g, 3, A, B, 4, k=4, rows=256, split=64)
+
+
+def test_sw_ignores_pad_bits_of_inputs(gfq_gpu):
+    """Every pad bit of packed A and B set: the recursion's quadrant splits read those words
+    (A's pad columns only ever meet zero rows of B, B's land in C's masked columns)."""
+    g = gfq_gpu
+    for q in (3, 7, 9):
+        m, l, n = 300, 333, 270
+        A, B = inputs.pair(q, m, l, n, cfg=243, idx=q)
+        Ap, Bp = oracle.pack(q, A), oracle.pack(q, B)
+
+        def dirty(w, cols):
+            w = w.copy().reshape(w.shape[0], oracle.planes(q), -1)
+            bits = np.unpackbits(w.view(np.uint8), axis=2, bitorder="little")
+            bits[:, :, cols:] = 1
+            return np.packbits(bits, axis=2, bitorder="little").view("<u4").reshape(w.shape[0], -1)
+
+        Ad, Bd = dirty(Ap, l), dirty(Bp, n)
+        for levels in (1, 2):
+            Cp = g.matmul_sw(q, dev(Ad.view(np.uint8).reshape(-1)), dev(Bd.view(np.uint8).reshape(-1)), m, l, n, levels)
+            C = g.unpack(q, Cp, m, n).cpu().numpy()
+            assert np.array_equal(C, oracle.matmul(q, A, B)), (q, levels)
+            got = Cp.cpu().numpy()[:g.packed_bytes(q, m, n)]
+            assert np.array_equal(got, oracle.pack(q, C).view(np.uint8).reshape(-1)), (q, levels)
+
+
+def test_sw_auto_levels_from_the_tuner(gfq_gpu):
+    """GFQ_SW_AUTO: levels from the tuner's cache for the size class (0 without an entry);
+    the product is the same at every level."""
+    import torch
+    g = gfq_gpu
+    q, N = 5, 2048
+    A, B = inputs.pair(q, N, N, N, cfg=244)
+    Ap, Bp = g.pack(q, dev(A)), g.pack(q, dev(B))
+    plain = g.matmul(q, Ap, Bp, N, N, N)
+    g.tune_clear()
+    assert g.tune_sw_lookup(q, N, N, N) is None
+    assert torch.equal(g.matmul_sw(q, Ap, Bp, N, N, N, g.SW_AUTO), plain)     # no entry: plain
+    lev = g.tune_sw(q, N, N, N)
+    assert 0 <= lev < g.SW_MAX_LEVELS and g.tune_sw_lookup(q, N, N, N) == lev
+    assert torch.equal(g.matmul_sw(q, Ap, Bp, N, N, N, g.SW_AUTO), plain)
+    g.tune_clear()
