@@ -88,11 +88,11 @@ template <> struct FT<7> {
 };
 
 // F_5 (Section 4.2).  Basis {1, 2, 4}, phi_d = plane d; table entries are 3-bit
-// representatives (4-bit sum, then fold5).  The accumulator works modulo 15 (4 planes per
-// half of the carry-save pair) and is reduced mod 5 once, at the end; a slab's three
-// scaled rows enter it together (f5_csa_slab).
+// representatives (4-bit sum, then fold5).  The accumulator is a carry-save value modulo 5
+// in three planes (f5_nc_slab): a slab's three scaled rows enter it together, and its value
+// is already canonical at the end.
 template <> struct FT<5> {
-    static constexpr int P = 3, PT = 3, D = 3, GP = 3, PA = 8;
+    static constexpr int P = 3, PT = 3, D = 3, GP = 3, PA = 3;
     static constexpr bool SPLIT_PREFIX = true, HALF_ROWS = false;
     static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; f[2] = x[2]; }
@@ -106,13 +106,11 @@ template <> struct FT<5> {
         const u32 n[3] = {nb.b0, nb.b1, nb.b2};
         tadd(a, n, r);
     }
-    // the accumulator starts at -7 x slabs (mod 15): each slab adds 4 T[phi_2] as 7 - T[phi_2]
-    __device__ static void acc_init(u32 *c, int slabs) { f5_csa_init(c, c + 4, slabs); }
-    __device__ static void accumulate(u32 *c, const u32 (*t)[P]) { f5_csa_slab(c, c + 4, t[0], t[1], t[2]); }
+    // the accumulator starts at -2 x slabs (mod 5): each slab step adds 2 beyond its rows
+    __device__ static void acc_init(u32 *c, int slabs) { f5_nc_init(c, slabs); }
+    __device__ static void accumulate(u32 *c, const u32 (*t)[P]) { f5_nc_slab(c, t[0], t[1], t[2]); }
     __device__ static void finish(const u32 *c, u32 *out) {
-        P3v s = fold5(c[0], c[1], c[2], c[3]);
-        P3v k = fold5(c[4], c[5], c[6], c[7]);
-        P3v z = f5_reduce(f5_add(s, k));
+        P3v z = f5_nc_value(c);
         out[0] = z.b0; out[1] = z.b1; out[2] = z.b2;
     }
     __device__ static void sadd(const u32 *a, const u32 *b, u32 *r) { tadd(a, b, r); }

@@ -206,7 +206,8 @@ GFQ_HD void g8_acc(u32 *c, const u32 *t, const u32 *u, const u32 *v) {
 // Binary residues modulo 2^NB - 1.  A value is an NB-bit integer taken modulo M = 2^NB - 1,
 // so the all-ones word also means 0 and a carry out of the top bit re-enters at bit 0
 // (2^NB = 1 mod M).  F_3 is worked modulo 3 = 2^2 - 1 and F_7 modulo 7 = 2^3 - 1; F_5 is
-// worked modulo 15 = 2^4 - 1, which 5 divides, and reduced mod 5 only at the end.
+// worked modulo 5 = 2^2 + 1, where a carry out of the top bit re-enters at bit 0
+// complemented (f5_nc_slab).
 //
 // Carry-save accumulation: a running sum is kept as two such integers (S, K) whose sum is
 // the value; adding one more integer X costs one full adder per bit, i.e. a three-input
@@ -264,39 +265,56 @@ GFQ_HD void f3b_sub(const u32 *a, const u32 *b, u32 *r) { f3b_add_t<true>(a, b, 
 // Back to the storage code: residue 0 (00 or 11) -> 00, 1 -> 10, 2 -> 11.
 GFQ_HD void f3_from_bin(const u32 *b, u32 *x0, u32 *x1) { *x0 = b[0] ^ b[1]; *x1 = b[1] & ~b[0]; }
 
-// F_5 addends in the modulo-15 working form: alpha * t for a 3-bit representative t and
-// alpha in {1, 2, 4}.  Doubling modulo 15 is a rotation of the four planes.
-// One F_5 slab into a carry-save accumulator modulo 15 (S + K, both in 4 planes, bit j of
-// either weighing 2^j; 5 divides 15, so the value is reduced mod 5 at the end).  The slab's
-// three table rows are t = T[phi_0] (scale 1), v = T[phi_1] (scale 2) and w = T[phi_2]
-// (scale 4 = -1 mod 5, added as the complement ~w = 7 - w, so every slab also adds 7; the
-// caller starts the accumulator at -7 x slabs).  Nine addend bits sit in the columns as
-//   col 0: t0, ~w0    col 1: t1, v0, ~w1    col 2: t2, v1, ~w2    col 3: v2
-// and nine full adders plus one half adder bring every column back to two bits (carries out
-// of column 3 re-enter column 0 because 16 = 1 mod 15): 20 instructions, where adding the
-// three scaled rows one at a time costs 24.
-GFQ_HD void f5_csa_slab(u32 *S, u32 *K, const u32 *t, const u32 *v, const u32 *w) {
-    const u32 s3a = xor3(S[3], K[3], v[2]), c3a = maj3(S[3], K[3], v[2]);     // -> col 0
-    const u32 s0a = xor3(S[0], K[0], t[0]), c0a = maj3(S[0], K[0], t[0]);     // -> col 1
-    const u32 s0b = xor3n(s0a, c3a, w[0]), c0b = maj3n(s0a, c3a, w[0]);
-    const u32 s1a = xor3(S[1], K[1], t[1]), c1a = maj3(S[1], K[1], t[1]);     // -> col 2
-    const u32 s1b = xor3n(v[0], c0a, w[1]), c1b = maj3n(v[0], c0a, w[1]);
-    const u32 s1c = s1a ^ s1b, c1c = s1a & s1b;
-    const u32 s2a = xor3(S[2], K[2], t[2]), c2a = maj3(S[2], K[2], t[2]);     // -> col 3
-    const u32 s2b = xor3n(v[1], c1a, w[2]), c2b = maj3n(v[1], c1a, w[2]);
-    const u32 s2c = xor3(s2a, s2b, c1b), c2c = maj3(s2a, s2b, c1b);
-    const u32 s3b = xor3(s3a, c2a, c2b), c3b = maj3(s3a, c2a, c2b);          // -> col 0
-    S[0] = s0b; S[1] = s1c; S[2] = s2c; S[3] = s3b;
-    K[0] = c3b; K[1] = c0b; K[2] = c1c; K[3] = c2c;
+// One F_5 slab into a carry-save accumulator modulo 5 of three planes (a, b, c): its value
+// is a + b + 2c, between 0 and 4.  A bit of weight 4 = -1 (mod 5) re-enters the weight-1
+// column complemented (-x = ~x - 1), so the accumulator needs only two columns (weights 1
+// and 2).  The slab's table rows are t = T[phi_0], v = T[phi_1] (scale 2), w = T[phi_2]
+// (scale 4), each any 3-bit representative; their nine bits sit in the columns as
+//   weight 1: t0, ~t2, ~v1, ~w0, w2        weight 2: t1, v0, ~v2, ~w1
+// (t2, v1, w0 weigh 4 = -1; v2, w1 weigh 8 = -2; w2 weighs 16 = 1).  Nine full adders and
+// one half adder bring the columns back to two bits and one bit; the five carries out of
+// the weight-2 column re-enter complemented.  The constants dropped by the complements sum
+// to -12, so every slab adds 12 = 2 (mod 5) beyond t + 2v + 4w, which the starting value
+// cancels: 20 instructions, three accumulator planes.
+template <int NEG> GFQ_HD u32 fa_sum(u32 x, u32 y, u32 z) { return lut3<lut3_flip(0x96, NEG)>(x, y, z); }
+template <int NEG> GFQ_HD u32 fa_carry(u32 x, u32 y, u32 z) { return lut3<lut3_flip(0xE8, NEG)>(x, y, z); }
+
+GFQ_HD void f5_nc_slab(u32 *s, const u32 *t, const u32 *v, const u32 *w) {
+    // weight 1: a, b, t0, ~t2, ~v1, ~w0, w2
+    const u32 s1 = fa_sum<0>(s[0], s[1], t[0]), k1 = fa_carry<0>(s[0], s[1], t[0]);
+    const u32 s2 = fa_sum<7>(t[2], v[1], w[0]), k2 = fa_carry<7>(t[2], v[1], w[0]);
+    const u32 s3 = fa_sum<0>(w[2], s1, s2), k3 = fa_carry<0>(w[2], s1, s2);
+    // weight 2: c, t1, v0, ~v2, ~w1 and the carries k1, k2, k3
+    const u32 u1 = fa_sum<0>(s[2], t[1], v[0]), m1 = fa_carry<0>(s[2], t[1], v[0]);
+    const u32 u2 = fa_sum<6>(v[2], w[1], k1), m2 = fa_carry<6>(v[2], w[1], k1);
+    const u32 u3 = fa_sum<0>(k2, k3, u1), m3 = fa_carry<0>(k2, k3, u1);
+    // weight 1: s3, ~m1, ~m2, ~m3; weight 2: u2, u3 and the carries
+    const u32 s4 = fa_sum<3>(s3, m1, m2), k4 = fa_carry<3>(s3, m1, m2);
+    const u32 u4 = fa_sum<0>(u2, u3, k4), m4 = fa_carry<0>(u2, u3, k4);
+    const u32 s5 = fa_sum<6>(m3, m4, s4), k5 = fa_carry<6>(m3, m4, s4);
+    // half adder on weight 2 (u4, k5): its carry re-enters weight 1 complemented
+    s[0] = s5;
+    s[1] = lut3<0x3F>(u4, k5, k5);          // ~(u4 & k5)
+    s[2] = u4 ^ k5;
 }
 
-// Starting value of that accumulator for `slabs` slabs: -7 x slabs mod 15 in S, zero K.
-GFQ_HD void f5_csa_init(u32 *S, u32 *K, int slabs) {
-    const int c = (8 * (slabs > 0 ? slabs : 0)) % 15;
-    for (int j = 0; j < 4; j++) {
-        S[j] = ((c >> j) & 1) ? 0xffffffffu : 0u;
-        K[j] = 0u;
-    }
+// Starting value for `slabs` slabs: a + b + 2c = -2 x slabs (mod 5), every plane all-zero
+// or all-one.
+GFQ_HD void f5_nc_init(u32 *s, int slabs) {
+    const int r = (3 * (slabs > 0 ? slabs % 5 : 0)) % 5;
+    const u32 one = 0xffffffffu;
+    s[0] = (r & 1) || r == 4 ? one : 0u;      // 1 = a, 2 = c, 3 = a + c, 4 = a + b + c
+    s[1] = r == 4 ? one : 0u;
+    s[2] = r >= 2 ? one : 0u;
+}
+
+// The accumulator's value a + b + 2c (at most 4, so already the canonical code).
+GFQ_HD P3v f5_nc_value(const u32 *s) {
+    P3v z;
+    z.b0 = s[0] ^ s[1];
+    z.b1 = s[2] ^ (s[0] & s[1]);
+    z.b2 = s[0] & s[1] & s[2];
+    return z;
 }
 
 }  // namespace gfq

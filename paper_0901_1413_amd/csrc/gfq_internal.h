@@ -62,7 +62,7 @@ inline int words_of(int64_t cols) { return (int)(((cols + 127) / 128) * 4); }
 // flight (F_9 by Karatsuba: two rows of twelve 128-bit reads and 12 accumulator planes).  The work-list kernels of batches use at
 // most 8.
 inline int max_rows_per_lane(int q) {
-    return q == F9_KARATSUBA ? 2 : (q == 5 || q == 7 || q == 9 ? 4 : (q == 4 || q == GF4_KARATSUBA ? 16 : 8));
+    return q == F9_KARATSUBA ? 2 : (q == 7 || q == 9 ? 4 : (q == 4 || q == GF4_KARATSUBA ? 16 : 8));
 }
 inline int max_rows_per_lane_batch(int q) { return q == 5 || q == 7 || q == 9 ? 4 : 8; }
 
@@ -126,7 +126,7 @@ inline MMPlan mm_plan(int q, int k, int rowsTile) {
     r = r <= 2 ? 2 : (r <= 4 ? 4 : (r <= 8 ? 8 : 16));
     if (r > max_rows_per_lane(q)) r = max_rows_per_lane(q);
     if (r > 8 && p.twd < 16) r = 8;              // narrow tiles: 16 rows per lane would spill
-    if (r > 4 && p.twd < 16 && (q == 8 || q == GF8_TRINOMIAL)) r = 4;    // ... and for GF(8) eight would
+    if (r > 4 && p.twd < 16 && (q == 5 || q == 8 || q == GF8_TRINOMIAL)) r = 4;   // ... for F_5, GF(8) eight would
     if (r > 2 && p.twd < 16 && q == 9) r = 2;                             // ... and for F_9 four would
     for (; r >= 2; r /= 2) {
         p.R = r;

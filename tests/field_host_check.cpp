@@ -68,24 +68,25 @@ int main() {
         unsigned vns = bit(n2s[0]) | bit(n2s[1]) << 1, vnk = bit(n2k[0]) | bit(n2k[1]) << 1;
         printf("csa %u %u %u  %u %u  %u %u  %u %u  %u %u\n", S, K, X, v4s, v4k, v3s, v3k, v2s, v2k, vns, vnk);
     }
-    // F_5 slab step of the mod-15 carry-save accumulator: every (S, K, t, v, w)
-    for (unsigned S = 0; S < 16; S++) for (unsigned K = 0; K < 16; K++)
+    // F_5 slab step of the three-plane carry-save accumulator modulo 5: every (a, b, c, t, v, w)
+    for (unsigned st = 0; st < 8; st++)
         for (unsigned t = 0; t < 8; t++) for (unsigned v = 0; v < 8; v++) for (unsigned w = 0; w < 8; w++) {
-            u32 s4[4], k4[4], t3[3], v3[3], w3[3];
-            for (int i = 0; i < 4; i++) { s4[i] = (S >> i) & 1; k4[i] = (K >> i) & 1; }
-            for (int i = 0; i < 3; i++) { t3[i] = (t >> i) & 1; v3[i] = (v >> i) & 1; w3[i] = (w >> i) & 1; }
-            f5_csa_slab(s4, k4, t3, v3, w3);
-            unsigned so = 0, ko = 0;
-            for (int i = 0; i < 4; i++) { so |= bit(s4[i]) << i; ko |= bit(k4[i]) << i; }
-            printf("f5slab %u %u %u %u %u %u %u\n", S, K, t, v, w, so, ko);
+            u32 s3[3], t3[3], v3[3], w3[3];
+            for (int i = 0; i < 3; i++) { s3[i] = (st >> i) & 1; t3[i] = (t >> i) & 1; v3[i] = (v >> i) & 1; w3[i] = (w >> i) & 1; }
+            f5_nc_slab(s3, t3, v3, w3);
+            printf("f5slab %u %u %u %u %u %u %u %u\n", st & 1, (st >> 1) & 1, st >> 2, t, v, w,
+                   bit(s3[0]) | bit(s3[1]) << 1 | bit(s3[2]) << 2, 0u);
         }
     for (int slabs = 0; slabs < 40; slabs++) {
-        u32 s4[4], k4[4];
-        f5_csa_init(s4, k4, slabs);
-        unsigned so = 0, ko = 0;
-        for (int i = 0; i < 4; i++) { so |= (s4[i] & 1u) << i; ko |= (k4[i] & 1u) << i; }
-        const bool full = (s4[0] == 0u || s4[0] == 0xffffffffu) && (s4[3] == 0u || s4[3] == 0xffffffffu);
-        printf("f5init %d %u %u %d\n", slabs, so, ko, full ? 1 : 0);
+        u32 s3[3];
+        f5_nc_init(s3, slabs);
+        bool full = true;
+        for (int i = 0; i < 3; i++) full = full && (s3[i] == 0u || s3[i] == 0xffffffffu);
+        printf("f5init %d %u %u %u %d\n", slabs, bit(s3[0]), bit(s3[1]), bit(s3[2]), full ? 1 : 0);
+    }
+    for (unsigned st = 0; st < 8; st++) {
+        u32 s3[3] = {st & 1, (st >> 1) & 1, st >> 2};
+        printf("f5val %u %u\n", st, v3(f5_nc_value(s3)));
     }
     return 0;
 }
