@@ -208,8 +208,14 @@ int gfq_batch_destroy(gfq_batch *batch);
  * the levels in its k field, the other fields 0; more levels are chosen only when 2% faster
  * than the fastest with fewer).  gfq_choose_config, gfq_batch_create and gfq_matmul_sw (GFQ_SW_AUTO) use cached
  * entries when they exist.
- * gfq_tune_lookup returns GFQ_OK and the entry if the class is cached, GFQ_EAGAIN if not.
- * gfq_tune_save / gfq_tune_load write / merge the cache as text, one entry per line.
+ * gfq_tune_lookup returns GFQ_OK and the entry if the class is cached, GFQ_EAGAIN if not; a
+ * single-product entry keeps the shape it was timed on, and a product of the class with
+ * fewer tiles than that shape (so fewer workgroups at the cached split) gets the cached k and
+ * tile height with the split chosen again for its own shape by the library's cost model
+ * (never fewer slices than cached).
+ * gfq_tune_save / gfq_tune_load write / merge the cache as text, one entry per line:
+ * "arch mode q m_class l_class n_class k rows split variant", and for mode 0 the rows and
+ * columns of the shape timed (absent: the class's largest, 2^m_class x 2^n_class).
  * gfq_tune_clear empties it.
  * gfq_tune: each of m, l, n in 1 .. 65536 (else GFQ_EDIM); q in {3,4,5,7,8,9} (GFQ_EFIELD);
  * mode 0, GFQ_TUNE_BATCH or GFQ_TUNE_SW (GFQ_EINVAL).  It runs on the calling thread's stream, waits for

@@ -95,21 +95,26 @@ int kernel_field(int q, const gfq_config &c) {
     return route_field(q, c.variant);
 }
 
+}  // namespace
+
 // Tile height and inner-dimension slices for slab width c->k (kernel field of c) on an
 // m x l x n product: the fewest slab steps on the busiest compute unit, i.e. ceil(workgroups
 // / 256) rounds of (slabs per slice + 2) steps of a TM-row tile (the 2 stand for a slice's
 // prologue and store), each step weighted by the table it builds; among near-equal choices
-// the tallest tile and the fewest slices (least partial-sum traffic) win.
-void fit_tiles(int q, int64_t m, int64_t l, int64_t n, gfq_config *c) {
+// the tallest tile and the fewest slices (least partial-sum traffic) win; a slice holds at
+// least min_slabs slabs.  keep_rows: the tile height c->rows stays and only the slices are
+// chosen.
+void gfq::fit_tiles(int q, int64_t m, int64_t l, int64_t n, gfq_config *c, bool keep_rows, int min_slabs) {
     const int kq = kernel_field(q, *c), kk = c->k;
     const int twd = twd_of(srb_for(kq, kk));
     const int64_t ctiles = (words_of(n) + twd - 1) / twd;
     const int64_t S = l > 0 ? (l + kk - 1) / kk : 1;
-    const int64_t max_split = std::max<int64_t>(1, std::min<int64_t>(S / 32, 64));
+    const int64_t max_split = std::max<int64_t>(1, std::min<int64_t>(S / std::max(1, min_slabs), 64));
     double best_cost = 0.0;
-    c->rows = 256;
+    const int rows_hi = keep_rows ? c->rows : 2048, rows_lo = keep_rows ? c->rows : 256;
+    c->rows = rows_lo;
     c->split = 1;
-    for (int rows = 2048; rows >= 256; rows >>= 1) {
+    for (int rows = rows_hi; rows >= rows_lo; rows >>= 1) {
         const MMPlan p = mm_plan(kq, kk, rows);
         if (!p.srb) continue;
         const int64_t tiles = ctiles * ((m + p.TM - 1) / p.TM);
@@ -126,6 +131,8 @@ void fit_tiles(int q, int64_t m, int64_t l, int64_t n, gfq_config *c) {
         }
     }
 }
+
+namespace {
 
 int check_config(int q, const gfq_config &c) {
     if (c.k < 1 || c.k > KMAX) return GFQ_EINVAL;

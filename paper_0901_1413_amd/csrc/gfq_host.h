@@ -39,6 +39,10 @@ size_t batch_tiles_bound(int64_t m, int64_t n);
 hipError_t set_batched_lds_limits();
 // Fill n words with pseudo-random bits (a hash of the index and the seed); timing data only.
 hipError_t launch_fill_random(u32 *p, size_t n, u32 seed, hipStream_t st);
+// Tile height and inner-dimension slices of an m x l x n product for slab width c->k, by a
+// cost model of slab steps per compute unit, slices of at least min_slabs slabs (keep_rows:
+// only the slices, for c->rows).
+void fit_tiles(int q, int64_t m, int64_t l, int64_t n, gfq_config *c, bool keep_rows = false, int min_slabs = 32);
 // Field, dimension, pointer, alignment and aliasing checks of one product.
 int validate_mm(int q, int64_t m, int64_t l, int64_t n, const void *A, const void *B, void *C);
 

@@ -27,8 +27,15 @@ namespace {
 
 typedef std::tuple<std::string, int, int, int, int, int> Key;   // arch, mode, q, bm, bl, bn
 
+// A cached configuration; a single-product entry also keeps the rows and columns of the
+// shape it was timed on (0 = the class's largest, 2^bucket).
+struct Entry {
+    gfq_config c;
+    int64_t m = 0, n = 0;
+};
+
 std::mutex g_mu;
-std::map<Key, gfq_config> g_cache;
+std::map<Key, Entry> g_cache;
 
 int bucket(int64_t x) {
     int b = 6;
@@ -110,13 +117,33 @@ int gfq_tune_lookup(int q, int64_t m, int64_t l, int64_t n, int mode, gfq_config
     const int md = (mode == GFQ_TUNE_BATCH || mode == GFQ_TUNE_SW) ? mode : 0;
     auto it = g_cache.find(make_key(arch, md, q, m, l, n));
     if (it == g_cache.end()) return GFQ_EAGAIN;
-    *out = it->second;
+    *out = it->second.c;
     if (md == GFQ_TUNE_SW) return GFQ_OK;             // k holds the number of levels
     // the cached split belongs to the class; never split further than the slabs allow
     if (l > 0) {
         const int64_t S = (l + out->k - 1) / out->k;
         if (out->k > l) out->k = (int)l;
         out->split = (int)std::max<int64_t>(1, std::min<int64_t>(out->split, S));
+    }
+    // A product of the class with fewer tiles than the shape the entry was timed on would
+    // leave compute units idle at that shape's split: its split is chosen again by the cost
+    // model, for the tuned k and tile height, with slices down to 16 slabs, and never below
+    // the tuned split (the model alone chose fewer slices than measured best in some fields).
+    if (md == 0 && m > 0 && n > 0 && l >= out->k) {
+        const int64_t tm = it->second.m ? it->second.m : (int64_t)1 << bucket(m);
+        const int64_t tn = it->second.n ? it->second.n : (int64_t)1 << bucket(n);
+        const MMPlan p = mm_plan(route_field(q, out->variant), out->k, out->rows);
+        if (p.srb) {
+            auto tiles = [&](int64_t mm, int64_t nn) {
+                return ((int64_t)words_of(nn) + p.twd - 1) / p.twd * ((mm + p.TM - 1) / p.TM);
+            };
+            if (tiles(m, n) < tiles(tm, tn)) {
+                const int tuned = out->split;
+                fit_tiles(q, m, l, n, out, true, 16);
+                const int64_t S = (l + out->k - 1) / out->k;
+                out->split = (int)std::min<int64_t>(std::max(out->split, tuned), S);
+            }
+        }
     }
     return GFQ_OK;
 }
@@ -242,7 +269,7 @@ int gfq_tune(int q, int64_t m, int64_t l, int64_t n, int mode, gfq_config *out) 
     if (best_rate <= 0.0) return GFQ_EHIP;
     {
         std::lock_guard<std::mutex> lk(g_mu);
-        g_cache[make_key(arch, mode, q, m, l, n)] = best;
+        g_cache[make_key(arch, mode, q, m, l, n)] = mode == 0 ? Entry{best, m, n} : Entry{best, 0, 0};
     }
     *out = best;
     return GFQ_OK;
@@ -253,12 +280,16 @@ int gfq_tune_save(const char *path) {
     FILE *f = fopen(path, "w");
     if (!f) return GFQ_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
-    fprintf(f, "# arch mode q m_class l_class n_class k rows split variant\n");
+    fprintf(f, "# arch mode q m_class l_class n_class k rows split variant [m n: shape timed, mode 0]\n");
     for (const auto &kv : g_cache) {
         const Key &k = kv.first;
-        fprintf(f, "%s %d %d %d %d %d %d %d %d %d\n", std::get<0>(k).c_str(), std::get<1>(k), std::get<2>(k),
-                std::get<3>(k), std::get<4>(k), std::get<5>(k), kv.second.k, kv.second.rows, kv.second.split,
-                kv.second.variant);
+        const gfq_config &c = kv.second.c;
+        fprintf(f, "%s %d %d %d %d %d %d %d %d %d", std::get<0>(k).c_str(), std::get<1>(k), std::get<2>(k),
+                std::get<3>(k), std::get<4>(k), std::get<5>(k), c.k, c.rows, c.split, c.variant);
+        if (std::get<1>(k) == 0)
+            fprintf(f, " %lld %lld", (long long)(kv.second.m ? kv.second.m : (int64_t)1 << std::get<3>(k)),
+                    (long long)(kv.second.n ? kv.second.n : (int64_t)1 << std::get<5>(k)));
+        fprintf(f, "\n");
     }
     fclose(f);
     return GFQ_OK;
@@ -275,9 +306,12 @@ int gfq_tune_load(const char *path) {
         if (line[0] == '#' || line[0] == '\n') continue;
         char arch[64];
         int mode, q, bm, bl, bn, k, rows, split, variant = GFQ_VARIANT_ROWWISE;
-        const int got = sscanf(line, "%63s %d %d %d %d %d %d %d %d %d", arch, &mode, &q, &bm, &bl, &bn, &k, &rows,
-                               &split, &variant);
-        if (got != 9 && got != 10) {                  // the variant column may be absent
+        long long tm = 0, tn = 0;
+        const int got = sscanf(line, "%63s %d %d %d %d %d %d %d %d %d %lld %lld", arch, &mode, &q, &bm, &bl, &bn, &k,
+                               &rows, &split, &variant, &tm, &tn);
+        // the variant column may be absent; the shape columns (mode 0 only) too
+        if ((got != 9 && got != 10 && got != 12) || (got == 12 && (mode != 0 || tm < 1 || tn < 1 ||
+                                                                   tm > (1 << 16) || tn > (1 << 16)))) {
             status = GFQ_EINVAL;
             continue;
         }
@@ -287,7 +321,7 @@ int gfq_tune_load(const char *path) {
                 status = GFQ_EINVAL;
                 continue;
             }
-            g_cache[Key(arch, mode, q, bm, bl, bn)] = gfq_config{k, 0, 0, 0};
+            g_cache[Key(arch, mode, q, bm, bl, bn)] = Entry{gfq_config{k, 0, 0, 0}, 0, 0};
             continue;
         }
         const bool var_ok = variant == GFQ_VARIANT_ROWWISE || (variant == GFQ_VARIANT_KARATSUBA && has_matrix_route(q));
@@ -297,7 +331,7 @@ int gfq_tune_load(const char *path) {
             status = GFQ_EINVAL;
             continue;
         }
-        g_cache[Key(arch, mode, q, bm, bl, bn)] = c;
+        g_cache[Key(arch, mode, q, bm, bl, bn)] = Entry{c, tm, tn};
     }
     fclose(f);
     return status;

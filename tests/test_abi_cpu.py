@@ -87,19 +87,25 @@ def test_tune_cache_text_roundtrip(tmp_path):
                  "gfx950 0 3 13 13 13 7 2048 2\n"                # an entry without the variant column
                  "gfx950 1 5 9 10 0 6 256 1 0\n"
                  "gfx950 0 4 12 11 12 6 2048 1 1\n"              # GF(4) by Karatsuba
+                 "gfx950 0 5 12 12 12 8 512 4 0 3000 2500\n"     # timed on a 3000 x . x 2500 product
                  "gfx950 2 5 13 13 13 3 0 0 0\n")                # Strassen-Winograd: 3 levels
     gfq.tune_clear()
     gfq.tune_load(str(f))
     out = tmp_path / "out.txt"
     gfq.tune_save(str(out))
     lines = [l.split() for l in out.read_text().splitlines() if not l.startswith("#")]
-    assert sorted(lines) == sorted([["gfx950", "0", "3", "13", "13", "13", "7", "2048", "2", "0"],
+    # single-product lines gain the shape timed (absent: the class's largest, 2^class)
+    assert sorted(lines) == sorted([["gfx950", "0", "3", "13", "13", "13", "7", "2048", "2", "0", "8192", "8192"],
                                     ["gfx950", "1", "5", "9", "10", "0", "6", "256", "1", "0"],
-                                    ["gfx950", "0", "4", "12", "11", "12", "6", "2048", "1", "1"],
+                                    ["gfx950", "0", "4", "12", "11", "12", "6", "2048", "1", "1", "4096", "4096"],
+                                    ["gfx950", "0", "5", "12", "12", "12", "8", "512", "4", "0", "3000", "2500"],
                                     ["gfx950", "2", "5", "13", "13", "13", "3", "0", "0", "0"]])
     for bad_line in ("gfx950 0 3 13 13 13 11 2048 2\n",       # k = 11 is out of range
                      "gfx950 0 3 13 13 13 7 2048 2 1\n",      # no matrix route for F_3
                      "gfx950 0 4 13 13 13 7 2048 2 2\n",      # no such variant
+                     "gfx950 0 3 13 13 13 7 2048 2 0 0 8192\n",      # a timed shape of 0 rows
+                     "gfx950 0 3 13 13 13 7 2048 2 0 8192\n",        # half a shape
+                     "gfx950 1 5 9 10 0 6 256 1 0 512 512\n",        # a shape on a batch entry
                      "gfx950 2 5 13 13 13 5 0 0 0\n"):        # more levels than the maximum
         bad = tmp_path / "bad.txt"
         bad.write_text(bad_line)
