@@ -59,7 +59,6 @@ PAPER_TABLE1_MS = {
 # per output word.
 C_ACC = {3: 8, 4: 3, 5: 20, 7: 18, 8: 6, 9: 32}
 C_ADD = {3: 4, 4: 2, 5: 13, 7: 11, 8: 3, 9: 8}
-C_FIN = {3: 8, 4: 0, 5: 30, 7: 15, 8: 0, 9: 16}
 # The paper's two-input operation counts (Sections 4.1 and 4.2) for the same units.
 C_ACC_PAPER = {3: 12, 4: 4, 5: 60, 7: 51}
 C_ADD_PAPER = {3: 6, 4: 2, 5: 20, 7: 17}
@@ -70,8 +69,8 @@ C_ADD_PAPER = {3: 6, 4: 2, 5: 20, 7: 17}
 # valid only while the kernel sources hash to `src` (otherwise the roofline reports null).
 KERNEL_SOURCES = ("gfq_m4rm_launch.h", "gfq_m4rm_tile.h", "gfq_device.h", "gfq_field.h", "gfq_internal.h")
 MEASURED_TRAFFIC = {
-    3: {"src": "3f34fb7ed3fb8aaf", "read_mib": 619.6, "write_mib": 64.0},
-    5: {"src": "3f34fb7ed3fb8aaf", "read_mib": 240.8, "write_mib": 24.0},
+    3: {"src": "8bcc9bd580bc3a98", "read_mib": 615.8, "write_mib": 64.0},
+    5: {"src": "8bcc9bd580bc3a98", "read_mib": 1530.1, "write_mib": 384.0},
 }
 
 
