@@ -4,7 +4,8 @@
 //   storage     the packed format of the C ABI (Section 4 encodings), P planes;
 //   table       how table entries (sums of rows of B) are held in LDS, P planes;
 //   accumulator how a lane keeps its running row of C, PA planes (carry-save pairs of
-//               residues modulo 2^NB - 1 for the prime fields, see gfq_field.h).
+//               residues modulo 2^NB - 1 for F_3 and F_7, a three-plane carry-save value
+//               modulo 5 for F_5, see gfq_field.h).
 // SPLIT_PREFIX: table chunk prefixes are summed one slab ahead by a quarter of the threads
 // (fields whose table addition is long) rather than by every build thread for itself.
 // Every trait works on one 32-bit word per plane (32 columns); the kernels apply it to
