@@ -26,7 +26,34 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const u32 *part, u
         const uint4 x = *reinterpret_cast<const uint4 *>(part + ((size_t)row * P + p) * Wn + w);
         v[0][p] = x.x; v[1][p] = x.y; v[2][p] = x.z; v[3][p] = x.w;
     }
-    for (int z = 1; z < splits; z++) {
+    // partials four at a time: their loads are all in flight before the first addition
+    // (field addition is associative and commutative, so the order of the sums is free)
+    int z = 1;
+    for (; z + 4 <= splits; z += 4) {
+        uint4 x[4][P];
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+#pragma unroll
+            for (int p = 0; p < P; p++)
+                x[j][p] = *reinterpret_cast<const uint4 *>(part + (size_t)(z + j) * split_stride +
+                                                           ((size_t)row * P + p) * Wn + w);
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            u32 y[4][P];
+#pragma unroll
+            for (int p = 0; p < P; p++) {
+                y[0][p] = x[j][p].x; y[1][p] = x[j][p].y; y[2][p] = x[j][p].z; y[3][p] = x[j][p].w;
+            }
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                u32 r[P];
+                F::sadd(v[i], y[i], r);
+#pragma unroll
+                for (int p = 0; p < P; p++) v[i][p] = r[p];
+            }
+        }
+    }
+    for (; z < splits; z++) {
         const u32 *pz = part + z * split_stride;
         u32 y[4][P];
 #pragma unroll
