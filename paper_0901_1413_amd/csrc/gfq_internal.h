@@ -73,7 +73,9 @@ inline int srb_for(int q, int k) {
         if (2 * ((size_t)1 << k) * table_planes(q) * srb <= TABLES_LDS) return srb;
     return 0;
 }
-inline int twd_of(int srb) { return srb >= 64 ? 16 : srb / 4; }   // tile words per plane
+// tile words per plane: 128-byte super-rows hold one 32-word row, 256-byte ones four copies
+// of a 16-word row, 64-byte ones one 16-word row, narrower ones one row of srb / 4 words
+inline int twd_of(int srb) { return srb == 128 ? 32 : (srb >= 64 ? 16 : srb / 4); }
 
 // Super-row bytes of the batched (work-list) kernels of field q at R rows per lane: 256 (four
 // copies of the 16-word tile row, conflict-free reads), except F_5 and F_7 at four rows per
@@ -125,7 +127,7 @@ inline MMPlan mm_plan(int q, int k, int rowsTile) {
     int r = rowsTile * lpr / NT_MM;
     r = r <= 2 ? 2 : (r <= 4 ? 4 : (r <= 8 ? 8 : 16));
     if (r > max_rows_per_lane(q)) r = max_rows_per_lane(q);
-    if (r > 8 && p.twd < 16) r = 8;              // narrow tiles: 16 rows per lane would spill
+    if (r > 8 && p.twd != 16) r = 8;             // 16 rows per lane: 16-word tiles only
     if (r > 4 && p.twd < 16 && (q == 5 || q == 8 || q == GF8_TRINOMIAL)) r = 4;   // ... for F_5, GF(8) eight would
     if (r > 2 && p.twd < 16 && q == 9) r = 2;                             // ... and for F_9 four would
     for (; r >= 2; r /= 2) {

@@ -84,7 +84,7 @@ template <bool STRIDED, int Q>
 hipError_t launch_mm_q(const MMArgs &a, const MMPlan &plan, const MMStrides &sd, hipStream_t st) {
     switch (plan.srb) {
     case 256: return launch_mm_rows<STRIDED, Q, 16, 4>(a, plan, sd, st);
-    case 128: return launch_mm_rows<STRIDED, Q, 16, 2>(a, plan, sd, st);
+    case 128: return launch_mm_rows<STRIDED, Q, 32, 1>(a, plan, sd, st);
     case 64: return launch_mm_rows<STRIDED, Q, 16, 1>(a, plan, sd, st);
     case 32: return launch_mm_rows<STRIDED, Q, 8, 1>(a, plan, sd, st);
     case 16: return launch_mm_rows<STRIDED, Q, 4, 1>(a, plan, sd, st);

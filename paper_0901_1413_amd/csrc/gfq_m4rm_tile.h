@@ -28,8 +28,12 @@
 // the TWD-word tile row.  gfx950 serves a 128-bit LDS read of 16 lanes from 64 four-byte
 // banks in one pass, so a 16-lane group is conflict-free exactly when its 16 reads cover
 // 256 distinct consecutive bytes: with SRB = 256 the REP rows of C gathered by one 16-lane
-// group come from different copies.  Table 0 sits at LDS offset 0 and table 1 at TB1, a
-// power of two not below the table size, so an address is (offset | lane offset | base).
+// group come from different copies.  With SRB = 128 a super-row is one 32-word row and a
+// group serves two rows of C, each in one half of the banks (planes swapped on odd entries
+// when their number is even, so that the half follows the entry); with SRB = 64 and less,
+// four or more rows of C share a group and conflict as their entries fall.  Table 0 sits
+// at LDS offset 0 and table 1 at TB1, a power of two not below the table size, so an
+// address is (offset | lane offset | base).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -62,6 +66,12 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
     constexpr int NCH = NT / TWD;                // build chunks per column word
     constexpr int LOG_NCH = log2_floor(NCH);
     constexpr int IBW = (D + 1) / 2;             // u32 words per row of the offset buffer
+    // 128-byte super-rows hold one 32-word tile row: a 16-lane read pass serves two rows of C,
+    // each reading one half of the 64 banks.  With an even number of table planes every
+    // entry starts on a 256-byte boundary, so plane p of every entry would sit in the same
+    // half and the two rows of a pass would always meet there: planes swap in pairs on odd
+    // entries (plane p of entry e at (p ^ (e & 1)) * SRB), so the halves follow the entries.
+    constexpr bool SWZ = (PT % 2 == 0) && SRB == 128;
     static_assert(KMAX * P * CG <= NT, "one B staging chunk per thread");
     static_assert(REP * LPR <= 16, "super-row wider than a 16-lane read group");
     static_assert(NCH % REP == 0 || REP % NCH == 0, "replica rotation");
@@ -138,7 +148,10 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
                 F::phis(x, f);
                 u32 o[IBW * 2];
 #pragma unroll
-                for (int d = 0; d < IBW * 2; d++) o[d] = d < D ? f[d < D ? d : 0] * (u32)(PT * SRB) : 0u;
+                for (int d = 0; d < IBW * 2; d++) {
+                    const u32 e = d < D ? f[d < D ? d : 0] : 0u;
+                    o[d] = e * (u32)(PT * SRB) + (SWZ ? (e & 1u) * (u32)SRB : 0u);   // plane 0's place
+                }
                 // slot-major: the R rows of one row slot are adjacent, so a lane fetches
                 // all of its offsets with one or two 128-bit reads
                 const int pos = (lr % RS) * R + lr / RS;
@@ -261,11 +274,13 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
         if (ch >= nchunks) return;
         const u32 *bs = Bst + (s % 3) * KMAX * P * TWD + dw;
         unsigned char *T = smem + ((s & 1) ? TB1 : 0u) + dw * 4;
-        auto store = [&](unsigned char *dst, const u32 *v) {
+        // entry of parity b at dst (plane order swapped in pairs on odd entries when SWZ)
+        auto store = [&](unsigned char *dst, const u32 *v, u32 b) {
 #pragma unroll
             for (int i = 0; i < REP; i++)
 #pragma unroll
-                for (int p = 0; p < PT; p++) *reinterpret_cast<u32 *>(dst + p * SRB + rep_off[i]) = v[p];
+                for (int p = 0; p < PT; p++)
+                    *reinterpret_cast<u32 *>(dst + (SWZ ? ((u32)p ^ b) : (u32)p) * SRB + rep_off[i]) = v[p];
         };
         u32 v[PT];
         if constexpr (SPLIT_PREFIX) {
@@ -292,7 +307,7 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
             }
         }
         unsigned char *eb = T + (u32)(ch << G) * (PT * SRB);
-        store(eb, v);
+        store(eb, v, G == 0 ? (u32)(ch & 1) : 0u);
         if constexpr (GMAX > 0) {
             u32 wr[GMAX > 0 ? GMAX : 1][PT];
 #pragma unroll
@@ -308,7 +323,7 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
                 const int b = __builtin_ctz(j);
                 const int g = j ^ (j >> 1);
                 step(v, wr[b], (g >> b) & 1);
-                store(eb + g * (PT * SRB), v);
+                store(eb + g * (PT * SRB), v, (u32)(g & 1));      // j < 2^G: G >= 1, parity of g
             }
         }
     };
@@ -336,9 +351,11 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
             const u32 x = iw[r * IBW + (d >> 1)];
             const u32 off = ((d & 1) ? (x >> 16) : (x & 0xffffu)) | lo;
             lds_u32x4 *row = (lds_u32x4 *)(uintptr_t)off;
+            lds_u32x4 *rowx = (lds_u32x4 *)(uintptr_t)(SWZ ? off ^ (u32)SRB : off);   // odd planes
 #pragma unroll
             for (int p = 0; p < GP; p++) {
-                const u32x4 v = row[F::gplane(d, p) * (SRB / 16)];
+                const int pl = F::gplane(d, p);
+                const u32x4 v = (SWZ && (pl & 1)) ? rowx[(pl & ~1) * (SRB / 16)] : row[(SWZ ? (pl & ~1) : pl) * (SRB / 16)];
                 t[d][p] = make_uint4(v.x, v.y, v.z, v.w);
             }
         }
@@ -363,9 +380,11 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
             const u32 x = iw[r * IBW + (d >> 1)];
             const u32 off = ((d & 1) ? (x >> 16) : (x & 0xffffu)) | lo;
             lds_u32x4 *row = (lds_u32x4 *)(uintptr_t)off;
+            lds_u32x4 *rowx = (lds_u32x4 *)(uintptr_t)(SWZ ? off ^ (u32)SRB : off);   // odd planes
 #pragma unroll
             for (int p = 0; p < GP; p++) {
-                const u32x4 v = row[F::gplane(d, p) * (SRB / 16)];
+                const int pl = F::gplane(d, p);
+                const u32x4 v = (SWZ && (pl & 1)) ? rowx[(pl & ~1) * (SRB / 16)] : row[(SWZ ? (pl & ~1) : pl) * (SRB / 16)];
                 t[dd][p] = make_uint4(v.x, v.y, v.z, v.w);
             }
         }
