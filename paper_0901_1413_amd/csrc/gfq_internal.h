@@ -130,6 +130,8 @@ inline MMPlan mm_plan(int q, int k, int rowsTile) {
     if (r > 8 && p.twd != 16) r = 8;             // 16 rows per lane: 16-word tiles only
     if (r > 4 && p.twd < 16 && (q == 5 || q == 8 || q == GF8_TRINOMIAL)) r = 4;   // ... for F_5, GF(8) eight would
     if (r > 2 && p.twd < 16 && q == 9) r = 2;                             // ... and for F_9 four would
+    if (p.twd == 4 && q == 3 && r > 4) r = 4;            // 4-word tiles stage R * 4 rows per thread:
+    if (p.twd == 4 && q == 7 && r > 2) r = 2;            // F_3 at eight and F_7 at four would spill
     for (; r >= 2; r /= 2) {
         p.R = r;
         p.TM = NT_MM / lpr * r;

@@ -115,6 +115,23 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
     // ---- staging of A: a window of words (w, w+1, w+2) per staged row and plane ----
     u32 aw[ARPT][P][3], apre[ARPT][P];
     int aw_w = (s_begin * k) >> 5;
+    // One staged row per thread and at most three planes: the words entering the window come
+    // from a 16-byte quad per plane (one load per four moves, a quarter of the cache misses
+    // of single-word loads; the rows are far apart, so their lines rarely last between two
+    // moves).  Elsewhere the registers are short and the next word is loaded alone.
+    constexpr bool AQ = ARPT == 1 && P <= 3;
+    uint4 aq[AQ ? P : 1];
+    // the quad holding word wn of this thread's row (clamped into the operand; the words
+    // outside it are masked where they enter the window).  Called only when the slice has
+    // slabs, so l >= 1, Wl >= 4 and m >= 1 (a tile exists).
+    auto load_quad = [&](int wn) {
+        const int qw = min(wn & ~3, a.Wl - 4);
+        const int row = min(row0 + min(tid, TM - 1), a.m - 1);
+#pragma unroll
+        for (int p = 0; p < (AQ ? P : 0); p++)
+            aq[p] = *reinterpret_cast<const uint4 *>(a.A + ((size_t)row * P + p) * a.Wl + qw);
+    };
+    auto quad_word = [](const uint4 &q, int c) -> u32 { return c == 0 ? q.x : (c == 1 ? q.y : (c == 2 ? q.z : q.w)); };
     auto a_word = [&](int j, int p, int w) -> u32 {
         const int lr = tid + j * NT;
         const int row = row0 + lr;
@@ -128,8 +145,12 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
             aw[j][p][0] = a_word(j, p, aw_w);
             aw[j][p][1] = a_word(j, p, aw_w + 1);
             aw[j][p][2] = a_word(j, p, aw_w + 2);
-            apre[j][p] = a_word(j, p, aw_w + 3);
+            apre[j][p] = AQ ? 0u : a_word(j, p, aw_w + 3);
         }
+    // (only with slabs to walk: a tile of an l = 0 product has none, and then Wl = 0)
+    if constexpr (AQ) {
+        if (s_begin < s_end) load_quad(aw_w + 3);
+    }
     auto apre_mask = [&](int j, int w) -> u32 {
         const int lr = tid + j * NT;
         return (lr < TM && row0 + lr < a.m && w < a.Wl) ? 0xffffffffu : 0u;
@@ -163,6 +184,10 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
     // the word the next move brings in: a load from a clamped address, masked when it
     // enters the window
     auto prefetch_a = [&]() {
+        if constexpr (AQ) {
+            if (((aw_w + 3) & 3) == 0) load_quad(aw_w + 3);     // else the held quad has it
+            return;
+        }
         const int w = min(aw_w + 3, a.Wl - 1);
 #pragma unroll
         for (int j = 0; j < ARPT; j++) {
@@ -184,7 +209,7 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
             for (int p = 0; p < P; p++) {
                 aw[j][p][0] = aw[j][p][1];
                 aw[j][p][1] = aw[j][p][2];
-                aw[j][p][2] = apre[j][p] & apre_mask(j, w + 2);
+                aw[j][p][2] = (AQ ? quad_word(aq[p], (w + 2) & 3) : apre[j][p]) & apre_mask(j, w + 2);
             }
         aw_w = w;
         return true;
