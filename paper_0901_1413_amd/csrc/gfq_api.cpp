@@ -286,6 +286,9 @@ int gfq_choose_config(int q, int64_t m, int64_t l, int64_t n, gfq_config *out) {
     gfq_config best = {};
     best.k = (l > 0 && l < 7) ? (int)l : 7;
     best.variant = GFQ_VARIANT_ROWWISE;
+    // where k = 7 means 32-word tiles (three- and four-plane tables), a product at most 16
+    // words wide would leave half of every tile idle: k = 6 keeps 16-word tiles
+    if (best.k == 7 && twd_of(srb_for(kernel_field(q, best), 7)) == 32 && words_of(n) <= 16) best.k = 6;
     fit_tiles(q, m, l, n, &best);
     *out = best;
     return GFQ_OK;
