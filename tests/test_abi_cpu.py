@@ -66,6 +66,18 @@ def test_config_choice_and_checks():
     assert lib.gfq_matmul_config(3, 4, 4, 4, vp(16), vp(4096), vp(8192), ctypes.byref(bad)) == -1
 
 
+def test_untuned_slab_width_keeps_tiles_filled():
+    """Without a tuned entry the slab width is k = 7, except where k = 7 means 32-word
+    (1024-column) tiles, i.e. three- and four-plane tables with 128-byte super-rows, and the
+    product is at most 16 words (512 columns) wide: then k = 6 keeps 16-word tiles."""
+    for q in (5, 7, 8, 9):
+        assert gfq.choose_config(q, 1000, 1000, 512)["k"] == 6
+        assert gfq.choose_config(q, 1000, 1000, 513)["k"] == 7       # 20 words
+        assert gfq.choose_config(q, 1000, 1000, 4096)["k"] == 7
+    for q in (3, 4):                                                   # k = 7: 256-byte rows
+        assert gfq.choose_config(q, 1000, 1000, 200)["k"] == 7
+
+
 def test_strerror():
     lib = gfq.load()
     for s in range(-10, 1):
