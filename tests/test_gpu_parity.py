@@ -323,3 +323,36 @@ def test_longest_inner_dimension(gfq_gpu, q):
         g.matmul(q, Ap, Bp, m, 1 << 24, n)
     assert e.value.status == -3
     torch.cuda.synchronize()
+
+
+# the slab width at which each field's table takes 128-byte super-rows, i.e. one 32-word tile
+# row per entry plane (planes swapped on odd entries for the even plane counts of F_3, GF(4), F_9)
+WIDE_K = {3: 8, 4: 8, 5: 7, 7: 7, 8: 7, 9: 7}
+
+
+@pytest.mark.parametrize("q", FIELDS)
+@pytest.mark.parametrize("rows,split", [(512, 1), (512, 3), (256, 2)])
+def test_wide_tiles(gfq_gpu, q, rows, split):
+    """32-word tiles: three column tiles with a ragged last one (n = 2300 is 72 words), a ragged
+    last row tile and a ragged last slab, at the tile heights and splits the layout runs with;
+    every element and every packed byte against the oracle."""
+    A, B = inputs.pair(q, 1100, 701, 2300, cfg=230, idx=rows + split)
+    check(gfq_gpu, q, A, B, k=WIDE_K[q], rows=rows, split=split)
+
+
+@pytest.mark.parametrize("q", [3, 9])
+def test_wide_tiles_entry_parity(gfq_gpu, q):
+    """B = identity rows in a fixed order and A one-hot, so that every table entry of both
+    parities is gathered and each product row equals one row of B: a plane swap left undone on
+    odd entries would show as swapped planes in those rows."""
+    k = WIDE_K[q]
+    l, n = 2 * k, 1500
+    rng = np.random.default_rng(231)
+    B = rng.integers(0, q, size=(l, n), dtype=np.uint8)
+    m = 1 << k
+    A = np.zeros((m, l), dtype=np.uint8)
+    for e in range(m):                       # row e selects slab-0 rows by the bits of e
+        for t in range(k):
+            A[e, t] = (e >> t) & 1
+        A[e, k + (e % k)] = 1                # and one row of slab 1
+    check(gfq_gpu, q, A, B, k=k)
