@@ -3,9 +3,9 @@
 // Three representations meet in the product kernel:
 //   storage     the packed format of the C ABI (Section 4 encodings), P planes;
 //   table       how table entries (sums of rows of B) are held in LDS, P planes;
-//   accumulator how a lane keeps its running row of C, PA planes (carry-save pairs of
-//               residues modulo 2^NB - 1 for F_3 and F_7, a three-plane carry-save value
-//               modulo 5 for F_5, see gfq_field.h).
+//   accumulator how a lane keeps its running row of C, PA planes (a carry-save pair of
+//               residues modulo 7 for F_7, three-plane carry-save values modulo 3 and 5 for
+//               F_3 and F_5, see gfq_field.h).
 // SPLIT_PREFIX: table chunk prefixes are summed one slab ahead by a quarter of the threads
 // (fields whose table addition is long) rather than by every build thread for itself.
 // Every trait works on one 32-bit word per plane (32 columns); the kernels apply it to
@@ -22,10 +22,10 @@ namespace gfq {
 template <int Q> struct FT;
 
 // F_3 (Section 4.1).  Basis {1, -1}: phi_0 = [a = 1] = x0 ^ x1, phi_1 = [a = -1] = x1.
-// Table entries are binary residues mod 3; the accumulator is a carry-save pair mod 3 and
-// receives T[phi_0] and -T[phi_1] (the complement) per slab.
+// Table entries are binary residues mod 3; the accumulator is a three-plane carry-save value
+// mod 3 and receives T[phi_0] and -T[phi_1] (the complement) per slab.
 template <> struct FT<3> {
-    static constexpr int P = 2, PT = 2, D = 2, GP = 2, PA = 4;
+    static constexpr int P = 2, PT = 2, D = 2, GP = 2, PA = 3;
     static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false;
     static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0] ^ x[1]; f[1] = x[1]; }
@@ -33,14 +33,11 @@ template <> struct FT<3> {
     __device__ static void tadd(const u32 *a, const u32 *b, u32 *r) { f3b_add(a, b, r); }
     __device__ static void tsub(const u32 *a, const u32 *b, u32 *r) { f3b_sub(a, b, r); }
     __device__ static void acc_init(u32 *c, int) { for (int i = 0; i < PA; i++) c[i] = 0u; }
-    __device__ static void accumulate(u32 *c, const u32 (*t)[P]) {
-        u32 *S = c, *K = c + 2;
-        csa_step<2>(S, K, t[0]);
-        csa_step_neg<2>(S, K, t[1]);
-    }
+    // three planes, a + b + 2c modulo 3 (f3_nc_slab): T[phi_0] added, T[phi_1] subtracted
+    __device__ static void accumulate(u32 *c, const u32 (*t)[P]) { f3_nc_slab(c, t[0], t[1]); }
     __device__ static void finish(const u32 *c, u32 *out) {
         u32 v[2];
-        f3b_add(c, c + 2, v);
+        f3_nc_value(c, v);
         f3_from_bin(v, &out[0], &out[1]);
     }
     __device__ static void sadd(const u32 *a, const u32 *b, u32 *r) {

@@ -265,6 +265,31 @@ GFQ_HD void f3b_sub(const u32 *a, const u32 *b, u32 *r) { f3b_add_t<true>(a, b, 
 // Back to the storage code: residue 0 (00 or 11) -> 00, 1 -> 10, 2 -> 11.
 GFQ_HD void f3_from_bin(const u32 *b, u32 *x0, u32 *x1) { *x0 = b[0] ^ b[1]; *x1 = b[1] & ~b[0]; }
 
+// Full adder on three bits, the operands selected by NEG (4: x, 2: y, 1: z) complemented:
+// sum and carry, one three-input instruction each.
+template <int NEG> GFQ_HD u32 fa_sum(u32 x, u32 y, u32 z) { return lut3<lut3_flip(0x96, NEG)>(x, y, z); }
+template <int NEG> GFQ_HD u32 fa_carry(u32 x, u32 y, u32 z) { return lut3<lut3_flip(0xE8, NEG)>(x, y, z); }
+
+// One F_3 slab into a carry-save accumulator modulo 3 of three planes (a, b, c), value
+// a + b + 2c: the slab adds t - v for two binary residues t = T[phi_0], v = T[phi_1] (each
+// b0 + 2 b1, 3 meaning 0), with -v = ~v (mod 3).  Bits of weight 4 = 1 re-enter weight 1, so
+// the columns hold  weight 1: a, b, t0, ~v0  and  weight 2: c, t1, ~v1, and four full adders
+// (8 instructions, as for a carry-save pair) bring them back to two bits and one bit.
+GFQ_HD void f3_nc_slab(u32 *s, const u32 *t, const u32 *v) {
+    const u32 s1 = fa_sum<0>(s[0], s[1], t[0]), k1 = fa_carry<0>(s[0], s[1], t[0]);   // weight 1
+    const u32 u1 = fa_sum<1>(s[2], t[1], v[1]), m1 = fa_carry<1>(s[2], t[1], v[1]);   // weight 2: c, t1, ~v1
+    const u32 s2 = fa_sum<2>(s1, v[0], m1), k2 = fa_carry<2>(s1, v[0], m1);          // weight 1: s1, ~v0, m1
+    s[0] = s2;
+    s[1] = fa_carry<0>(u1, k1, k2);                                                    // weight 4 = 1
+    s[2] = fa_sum<0>(u1, k1, k2);
+}
+
+// The accumulator's value as a binary residue (b0 + 2 b1, 3 meaning 0): (a + 2c) + b.
+GFQ_HD void f3_nc_value(const u32 *s, u32 *r) {
+    const u32 x[2] = {s[0], s[2]}, y[2] = {s[1], 0u};
+    f3b_add(x, y, r);
+}
+
 // One F_5 slab into a carry-save accumulator modulo 5 of three planes (a, b, c): its value
 // is a + b + 2c, between 0 and 4.  A bit of weight 4 = -1 (mod 5) re-enters the weight-1
 // column complemented (-x = ~x - 1), so the accumulator needs only two columns (weights 1
@@ -276,8 +301,6 @@ GFQ_HD void f3_from_bin(const u32 *b, u32 *x0, u32 *x1) { *x0 = b[0] ^ b[1]; *x1
 // the weight-2 column re-enter complemented.  The constants dropped by the complements sum
 // to -12, so every slab adds 12 = 2 (mod 5) beyond t + 2v + 4w, which the starting value
 // cancels: 20 instructions, three accumulator planes.
-template <int NEG> GFQ_HD u32 fa_sum(u32 x, u32 y, u32 z) { return lut3<lut3_flip(0x96, NEG)>(x, y, z); }
-template <int NEG> GFQ_HD u32 fa_carry(u32 x, u32 y, u32 z) { return lut3<lut3_flip(0xE8, NEG)>(x, y, z); }
 
 GFQ_HD void f5_nc_slab(u32 *s, const u32 *t, const u32 *v, const u32 *w) {
     // weight 1: a, b, t0, ~t2, ~v1, ~w0, w2

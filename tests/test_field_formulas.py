@@ -118,6 +118,19 @@ def test_carry_save_steps(table):
         assert (n2 + m2) % 3 == ((S & 3) + (K & 3) - (X & 3)) % 3
 
 
+def test_f3_slab_step(table):
+    """One slab of the three-plane F_3 accumulator (value a + b + 2c modulo 3): the new value
+    is a + b + 2c + t - v (mod 3) for every state and every binary residue t, v in 0..3; its
+    value read out as a binary residue is the same residue."""
+    rows = [r for r in table if r[0] == "f3slab"]
+    assert len(rows) == 8 * 4 * 4
+    for r in rows:
+        a, b, c, t, v, out, val = map(int, r[1:])
+        a2, b2, c2 = out & 1, (out >> 1) & 1, out >> 2
+        assert (a2 + b2 + 2 * c2) % 3 == (a + b + 2 * c + t - v) % 3, r
+        assert val % 3 == (a2 + b2 + 2 * c2) % 3, r
+
+
 def test_f5_slab_step(table):
     """One slab of the F_5 accumulator (value a + b + 2c modulo 5): the new value is
     a + b + 2c + t + 2v + 4w + 2 (mod 5) for every state and every 3-bit representative of
