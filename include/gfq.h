@@ -95,10 +95,13 @@ int gfq_matmul(int q, int64_t m, int64_t l, int64_t n, const void *A, const void
  * sweep).
  *   k      slab width, 1..10: each slab of k rows of B gets a table of its 2^k binary row
  *          combinations.  Two tables live in LDS at once; up to k = 7 (F_3, GF(4)) or
- *          k = 6 (F_5, F_7, GF(8), F_9) their rows are 256 bytes wide, larger k narrows the rows and
- *          lets 128-bit LDS reads conflict.
- *   rows   requested rows of C per workgroup: 256, 512, 1024 or 2048 (F_5, F_7, GF(8) and
- *          F_9 are capped by their register use; the library covers what fits)
+ *          k = 6 (F_5, F_7, GF(8), F_9) their rows are 256 bytes wide (a 512-column tile,
+ *          conflict-free reads), at the next k 128 bytes (a 1024-column tile, two rows of C
+ *          per read pass), beyond that narrower (512 columns and less, reads may conflict).
+ *   rows   requested rows of C per workgroup: 256, 512, 1024 or 2048; the library takes the
+ *          tallest tile up to the request that the field's registers allow (at most 512
+ *          rows on 1024-column tiles, 1024 for F_5, F_3, GF(8) and 2048 for GF(4) on
+ *          512-column tiles, 512 for F_7 and F_9)
  *   split  number of slices of the inner dimension computed by separate workgroups and
  *          summed afterwards, 1..64
  *   variant how extension-field products are formed (F_3, F_5, F_7: GFQ_VARIANT_ROWWISE
