@@ -53,3 +53,24 @@ def test_strassen_winograd_8192_freivalds(gfq_gpu, q):
     A, B = inputs.pair(q, N, N, N, cfg=242, idx=q)
     C = product(gfq_gpu, q, A, B, levels=2)
     assert freivalds(q, A, B, C, seed=100 + q)
+
+
+@pytest.mark.parametrize("q", [3, 5])
+def test_full_size_tuned_configuration(gfq_gpu, q):
+    """The benchmark's launches: the shipped tuning table loaded, the 8192^3 product runs in
+    the configuration the table holds for its class (the one the benchmark times), and every
+    element passes Freivalds' check."""
+    import os
+    g = gfq_gpu
+    N = 8192
+    table = os.path.join(os.path.dirname(g.__file__), "tuning", "gfx950.txt")
+    g.tune_clear()
+    try:
+        g.tune_load(table)
+        c = g.tune_lookup(q, N, N, N)
+        assert c is not None and g.choose_config(q, N, N, N) == c
+        A, B = inputs.pair(q, N, N, N, cfg=243, idx=q)
+        C = product(g, q, A, B)
+        assert freivalds(q, A, B, C, seed=200 + q)
+    finally:
+        g.tune_clear()
