@@ -58,7 +58,7 @@ PAPER_TABLE1_MS = {
 # 6 XORs; F_9 8 bits).  Table build: one field addition per table entry and word.  Finish:
 # per output word.
 C_ACC = {3: 8, 4: 3, 5: 20, 7: 18, 8: 6, 9: 32}
-C_ADD = {3: 4, 4: 2, 5: 13, 7: 11, 8: 3, 9: 8}
+C_ADD = {3: 4, 4: 2, 5: 8, 7: 11, 8: 3, 9: 8}
 # The paper's two-input operation counts (Sections 4.1 and 4.2) for the same units.
 C_ACC_PAPER = {3: 12, 4: 4, 5: 60, 7: 51}
 C_ADD_PAPER = {3: 6, 4: 2, 5: 20, 7: 17}

@@ -86,7 +86,7 @@ template <> struct FT<7> {
 };
 
 // F_5 (Section 4.2).  Basis {1, 2, 4}, phi_d = plane d; table entries are 3-bit
-// representatives (4-bit sum, then fold5).  The accumulator is a carry-save value modulo 5
+// representatives (f5_add8 / f5_sub8, eight instructions each).  The accumulator is a carry-save value modulo 5
 // in three planes (f5_nc_slab): a slab's three scaled rows enter it together, and its value
 // is already canonical at the end.
 template <> struct FT<5> {
@@ -95,15 +95,8 @@ template <> struct FT<5> {
     static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; f[2] = x[2]; }
     __device__ static void to_table(const u32 *x, u32 *t) { t[0] = x[0]; t[1] = x[1]; t[2] = x[2]; }
-    __device__ static void tadd(const u32 *a, const u32 *b, u32 *r) {
-        P3v z = f5_add(P3v{a[0], a[1], a[2]}, P3v{b[0], b[1], b[2]});
-        r[0] = z.b0; r[1] = z.b1; r[2] = z.b2;
-    }
-    __device__ static void tsub(const u32 *a, const u32 *b, u32 *r) {
-        P3v nb = f5_neg(P3v{b[0], b[1], b[2]});
-        const u32 n[3] = {nb.b0, nb.b1, nb.b2};
-        tadd(a, n, r);
-    }
+    __device__ static void tadd(const u32 *a, const u32 *b, u32 *r) { f5_add8(a, b, r); }
+    __device__ static void tsub(const u32 *a, const u32 *b, u32 *r) { f5_sub8(a, b, r); }
     // the accumulator starts at -2 x slabs (mod 5): each slab step adds 2 beyond its rows
     __device__ static void acc_init(u32 *c, int slabs) { f5_nc_init(c, slabs); }
     __device__ static void accumulate(u32 *c, const u32 (*t)[P]) { f5_nc_slab(c, t[0], t[1], t[2]); }

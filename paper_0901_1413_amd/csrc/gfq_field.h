@@ -290,6 +290,33 @@ GFQ_HD void f3_nc_value(const u32 *s, u32 *r) {
     f3b_add(x, y, r);
 }
 
+// F_5 addition and subtraction of 3-bit representatives in eight three-input instructions
+// (against eleven to thirteen for a 4-bit sum folded by fold5).  Bits of weight 4 = -1 enter
+// weight 1 complemented (4x = ~x - 1) and a constant bit fixes the offsets, so that four
+// adders reduce the columns to one bit each, the last carry being bit 2 of the result:
+//   a + b: weight 2 gets a1, b1 and a constant 1 (sum ~(a1 ^ b1), carry a1 | b1, which goes
+//          to weight 1 as ~(a1 | b1)); weight 1 gets a0, b0, ~a2, ~b2 and that bit; the
+//          offsets -2 - 1 - 1 - 1 sum to 0 (mod 5).
+//   a - b: weight 1 gets a0, ~b0, b2, ~a2, weight 2 a1, ~b1 (offsets -1 - 2 - 1); the carry
+//          out of weight 2 enters weight 1 complemented (-1), -5 = 0.
+GFQ_HD void f5_add8(const u32 *a, const u32 *b, u32 *r) {
+    const u32 n = lut3<0x03>(a[1], b[1], b[1]);                 // ~(a1 | b1)
+    const u32 u = lut3<0xC3>(a[1], b[1], b[1]);                 // ~(a1 ^ b1)
+    const u32 s1 = fa_sum<1>(a[0], b[0], a[2]), k1 = fa_carry<1>(a[0], b[0], a[2]);
+    const u32 k2 = fa_carry<4>(b[2], n, s1);
+    r[0] = fa_sum<4>(b[2], n, s1);
+    r[1] = fa_sum<0>(u, k1, k2);
+    r[2] = fa_carry<0>(u, k1, k2);
+}
+GFQ_HD void f5_sub8(const u32 *a, const u32 *b, u32 *r) {
+    const u32 s1 = fa_sum<2>(a[0], b[0], b[2]), k1 = fa_carry<2>(a[0], b[0], b[2]);
+    const u32 u1 = fa_sum<2>(a[1], b[1], k1), c1 = fa_carry<2>(a[1], b[1], k1);
+    const u32 k2 = fa_carry<3>(s1, a[2], c1);
+    r[0] = fa_sum<3>(s1, a[2], c1);
+    r[1] = u1 ^ k2;
+    r[2] = u1 & k2;
+}
+
 // One F_5 slab into a carry-save accumulator modulo 5 of three planes (a, b, c): its value
 // is a + b + 2c, between 0 and 4.  A bit of weight 4 = -1 (mod 5) re-enters the weight-1
 // column complemented (-x = ~x - 1), so the accumulator needs only two columns (weights 1

@@ -78,6 +78,14 @@ int main() {
             printf("f3slab %u %u %u %u %u %u %u\n", st & 1, (st >> 1) & 1, st >> 2, t, v,
                    bit(s3[0]) | bit(s3[1]) << 1 | bit(s3[2]) << 2, bit(r[0]) | bit(r[1]) << 1);
         }
+    // F_5 eight-instruction addition and subtraction on every pair of 3-bit representatives
+    for (unsigned a = 0; a < 8; a++) for (unsigned b = 0; b < 8; b++) {
+        u32 x[3], y[3], r[3], d[3];
+        for (int i = 0; i < 3; i++) { x[i] = (a >> i) & 1; y[i] = (b >> i) & 1; }
+        f5_add8(x, y, r); f5_sub8(x, y, d);
+        printf("f5add8 %u %u %u %u\n", a, b, bit(r[0]) | bit(r[1]) << 1 | bit(r[2]) << 2,
+               bit(d[0]) | bit(d[1]) << 1 | bit(d[2]) << 2);
+    }
     // F_5 slab step of the three-plane carry-save accumulator modulo 5: every (a, b, c, t, v, w)
     for (unsigned st = 0; st < 8; st++)
         for (unsigned t = 0; t < 8; t++) for (unsigned v = 0; v < 8; v++) for (unsigned w = 0; w < 8; w++) {

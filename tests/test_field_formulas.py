@@ -131,6 +131,16 @@ def test_f3_slab_step(table):
         assert val % 3 == (a2 + b2 + 2 * c2) % 3, r
 
 
+def test_f5_eight_instruction_add_sub(table):
+    """The F_5 table addition and subtraction of eight three-input instructions give a + b and
+    a - b (mod 5) for every pair of 3-bit representatives."""
+    rows = [r for r in table if r[0] == "f5add8"]
+    assert len(rows) == 64
+    for r in rows:
+        a, b, s, d = map(int, r[1:])
+        assert s % 5 == (a + b) % 5 and d % 5 == (a - b) % 5, r
+
+
 def test_f5_slab_step(table):
     """One slab of the F_5 accumulator (value a + b + 2c modulo 5): the new value is
     a + b + 2c + t + 2v + 4w + 2 (mod 5) for every state and every 3-bit representative of
