@@ -11,7 +11,7 @@ instructions for a schedule; it models counts only, so its minimum is a bound fo
 of adders, not for arbitrary programs.
 
   accumulate  fewest instructions for one slab step that returns the accumulator to the same
-              column counts (the state sizes it can use), per field
+              column counts (the state sizes it can use), for F_3, F_7 and F_5
   f5add       the F_5 table addition / subtraction of 3-bit representatives, result 3 bits
 """
 import heapq
@@ -101,6 +101,32 @@ def accumulate():
     return res
 
 
+def f5_accumulate():
+    """F_5 slab step t + 2v + 4w over weights 1, 2, 4 (8 = -2 enters weight 2 complemented,
+    16 = 1 weight 1): (2, 4, 3) input bits.  Any fixed offset per slab is allowed (the
+    accumulator's starting value cancels it), so the search stops at the first return to the
+    state's column counts.  Returns (instructions, state bits, state)."""
+    inputs, found = (2, 4, 3), None
+    for state in itertools.product(range(4), repeat=3):
+        if sum(state) < 3:
+            continue
+        start = tuple(s + i for s, i in zip(state, inputs)) + (0,)
+        best, pq = {start: 0}, [(0, start)]
+        while pq:
+            c, st = heapq.heappop(pq)
+            if st[:3] == state:
+                if found is None or (c, sum(state)) < found[:2]:
+                    found = (c, sum(state), state)
+                break
+            if c > best.get(st, 23) or c > 22:
+                continue
+            for nst, cost in f5_moves(st):
+                if best.get(nst, 23) > c + cost:
+                    best[nst] = c + cost
+                    heapq.heappush(pq, (c + cost, nst))
+    return found
+
+
 def f5add():
     # a + b: weights 1, 2, 4 hold (a0, b0), (a1, b1), (a2, b2); a - b: weight 1 a0, ~b0, b2, ~a2
     # and weight 2 a1, ~b1 with offset -4 = 1; the result is one bit in each column
@@ -111,6 +137,8 @@ def f5add():
 if __name__ == "__main__":
     for name, (c, total, state) in accumulate().items():
         print(f"accumulate {name}: {c} instructions, state of {total} bits {state}")
+    c, total, state = f5_accumulate()
+    print(f"accumulate F_5: {c} instructions, state of {total} bits {state}")
     r = f5add()
     print(f"f5add: add {r['add']} instructions, sub {r['sub']} instructions")
     sys.exit(0)

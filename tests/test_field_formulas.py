@@ -182,7 +182,8 @@ def test_f3_binary_add_is_shortest(tmp_path):
 def test_column_schedule_search():
     """The column-count model behind the accumulator states and the F_5 table addition:
     F_3's slab step needs 8 instructions and fits a 3-bit state, F_7's 18 and a 4-bit state
-    (three bits cannot close the cycle), and the F_5 table addition and subtraction 8 each."""
+    (three bits cannot close the cycle), F_5's 20 and a 3-bit state, and the F_5 table addition
+    and subtraction 8 each."""
     import importlib.util
     path = os.path.join(ROOT, "paper_0901_1413_amd", "search", "column_schedules.py")
     spec = importlib.util.spec_from_file_location("column_schedules", path)
@@ -190,4 +191,5 @@ def test_column_schedule_search():
     spec.loader.exec_module(cs)
     acc = cs.accumulate()
     assert acc["F_3"][:2] == (8, 3) and acc["F_7"][:2] == (18, 4)
+    assert cs.f5_accumulate()[:2] == (20, 3)          # nine full adders and a half adder
     assert cs.f5add() == {"add": 8, "sub": 8}
