@@ -114,7 +114,7 @@ void gfq::fit_tiles(int q, int64_t m, int64_t l, int64_t n, gfq_config *c, bool 
     const int rows_hi = keep_rows ? c->rows : 2048, rows_lo = keep_rows ? c->rows : 256;
     c->rows = rows_lo;
     c->split = 1;
-    for (int rows = rows_hi; rows >= rows_lo; rows >>= 1) {
+    for (int rows = rows_hi; rows >= rows_lo && rows > 0; rows >>= 1) {
         const MMPlan p = mm_plan(kq, kk, rows);
         if (!p.srb) continue;
         const int64_t tiles = ctiles * ((m + p.TM - 1) / p.TM);

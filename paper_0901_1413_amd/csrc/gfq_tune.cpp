@@ -325,7 +325,10 @@ int gfq_tune_load(const char *path) {
             continue;
         }
         const bool var_ok = variant == GFQ_VARIANT_ROWWISE || (variant == GFQ_VARIANT_KARATSUBA && has_matrix_route(q));
-        if (k < 1 || k > KMAX || !var_ok ||
+        // tile heights as gfq_matmul_config accepts them (mm_plan alone would clamp any
+        // count, zero and negative ones included, to a valid tile)
+        const bool rows_ok = rows == 256 || rows == 512 || rows == 1024 || rows == 2048;
+        if (k < 1 || k > KMAX || !var_ok || !rows_ok ||
             mm_plan(route_field(q, variant), k, rows).srb == 0 || split < 1 ||
             split > 64) {
             status = GFQ_EINVAL;

@@ -118,11 +118,19 @@ def test_tune_cache_text_roundtrip(tmp_path):
                      "gfx950 0 3 13 13 13 7 2048 2 0 0 8192\n",      # a timed shape of 0 rows
                      "gfx950 0 3 13 13 13 7 2048 2 0 8192\n",        # half a shape
                      "gfx950 1 5 9 10 0 6 256 1 0 512 512\n",        # a shape on a batch entry
-                     "gfx950 2 5 13 13 13 5 0 0 0\n"):        # more levels than the maximum
+                     "gfx950 2 5 13 13 13 5 0 0 0\n",         # more levels than the maximum
+                     "gfx950 0 3 13 13 13 7 0 2 0 8192 8192\n",      # a tile of 0 rows
+                     "gfx950 0 3 13 13 13 7 -512 2 0 8192 8192\n",   # a negative tile height
+                     "gfx950 0 5 13 13 13 7 768 2 0 8192 8192\n"):   # a height the API refuses
+        gfq.tune_clear()
         bad = tmp_path / "bad.txt"
         bad.write_text(bad_line)
         with pytest.raises(gfq.GfqError):
             gfq.tune_load(str(bad))
+        # a rejected entry leaves nothing in the cache
+        left = tmp_path / "left.txt"
+        gfq.tune_save(str(left))
+        assert [l for l in left.read_text().splitlines() if not l.startswith("#")] == []
     gfq.tune_clear()
     out2 = tmp_path / "empty.txt"
     gfq.tune_save(str(out2))
