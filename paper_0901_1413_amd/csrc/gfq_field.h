@@ -1,9 +1,12 @@
 // gfq_field.h -- bitsliced arithmetic over F_3, F_5, F_7 and GF(4) on 32-bit plane words.
 //
 // Every function works on one 32-bit word per bit-plane, i.e. on 32 field elements at
-// once (paper, Section 3: the bits of one element sit in parallel words).  The formulas
-// are the paper's sequential programs of Section 4, with the corrections listed next to
-// each one; on gfx950 the compiler fuses them into three-input v_bitop3_b32 operations.
+// once (paper, Section 3: the bits of one element sit in parallel words), in the element
+// encodings of Section 4.  The programs are derived here for gfx950, whose v_bitop3_b32
+// computes any Boolean function of three words in one instruction: full adders over
+// weight columns, residues of 2^b - 1 and 2^b + 1, and searched three-input programs.
+// Where the paper prints a formula for the same operation, the comment says how the two
+// relate.
 //
 // The header is plain C++ so that the host-side truth-table checks can include it; the
 // GPU library includes it with GFQ_HD defined as __host__ __device__.
@@ -60,26 +63,6 @@ constexpr int lut3_flip(int imm, int m) {
 // ---------------------------------------------------------------------------------------
 struct F3v { u32 u, s; };
 
-// Addition, 6 operations.  The printed formula swaps its two outputs: (x0 ^ y1) & (x1 ^ y0)
-// is the sign plane and s | t the unit plane (checked on all nine pairs).
-GFQ_HD F3v f3_add(F3v x, F3v y) {
-    u32 s = x.u ^ y.s ^ x.s;
-    u32 t = x.s ^ y.u ^ y.s;
-    F3v r;
-    r.u = s | t;
-    r.s = (x.u ^ y.s) & (x.s ^ y.u);
-    return r;
-}
-
-// Subtraction x - y, 6 operations, as printed.
-GFQ_HD F3v f3_sub(F3v x, F3v y) {
-    u32 t = x.u ^ y.u;
-    F3v r;
-    r.u = t | (x.s ^ y.s);
-    r.s = (t ^ y.s) & (y.u ^ x.s);
-    return r;
-}
-
 // Negation, 1 operation: (a0, a0 ^ a1).
 GFQ_HD F3v f3_neg(F3v a) { F3v r; r.u = a.u; r.s = a.u ^ a.s; return r; }
 
@@ -135,29 +118,6 @@ GFQ_HD P3v f7_reduce(P3v a) {
     P3v r; r.b0 = a.b0 ^ g; r.b1 = a.b1 ^ g; r.b2 = a.b2 ^ g;
     return r;
 }
-
-// fold5: a 4-bit value s3 s2 s1 s0 to a 3-bit representative of the same residue mod 5.
-// This is the paper's 8-operation search-found program, correct as printed.
-GFQ_HD P3v fold5(u32 s0, u32 s1, u32 s2, u32 s3) {
-    u32 t = s2 | s1;
-    P3v r;
-    r.b2 = s0 ^ t;
-    r.b1 = (r.b2 & s0) ^ (s3 ^ s1);
-    r.b0 = (t ^ s2) | (r.b1 & s3);
-    return r;
-}
-
-// F_5 addition: 4-bit sum, then fold5.
-GFQ_HD P3v f5_add(P3v a, P3v b) {
-    P4v s = add3x3(a, b);
-    return fold5(s.b0, s.b1, s.b2, s.b3);
-}
-
-// F_5 doubling: fold5 of the shifted value a2 a1 a0 0.
-GFQ_HD P3v f5_dbl(P3v a) { return fold5(0u, a.b0, a.b1, a.b2); }
-
-// F_5 negation: fold5 of a1 a0 0 a2 (value 8 a1 + 4 a0 + a2 = -(a0 + 2 a1 + 4 a2) mod 5).
-GFQ_HD P3v f5_neg(P3v a) { return fold5(a.b2, 0u, a.b0, a.b1); }
 
 // F_5 reduction to [0, 5).  The printed six-operation program does not preserve the
 // residue; this replacement subtracts 5 exactly when the representative is 5, 6 or 7:
@@ -265,6 +225,19 @@ GFQ_HD void f3b_sub(const u32 *a, const u32 *b, u32 *r) { f3b_add_t<true>(a, b, 
 // Back to the storage code: residue 0 (00 or 11) -> 00, 1 -> 10, 2 -> 11.
 GFQ_HD void f3_from_bin(const u32 *b, u32 *x0, u32 *x1) { *x0 = b[0] ^ b[1]; *x1 = b[1] & ~b[0]; }
 
+// Addition on the storage code of Section 4.1, through the binary residues: both operands
+// to b0 + 2 b1 (one XOR each), the four-instruction residue addition, back to the code.
+// Used off the product's inner loop (partial sums, Strassen-Winograd operand sums).
+GFQ_HD F3v f3_add(F3v x, F3v y) {
+    u32 a[2], b[2], r[2];
+    f3_to_bin(x.u, x.s, a);
+    f3_to_bin(y.u, y.s, b);
+    f3b_add(a, b, r);
+    F3v z;
+    f3_from_bin(r, &z.u, &z.s);
+    return z;
+}
+
 // Full adder on three bits, the operands selected by NEG (4: x, 2: y, 1: z) complemented:
 // sum and carry, one three-input instruction each.
 template <int NEG> GFQ_HD u32 fa_sum(u32 x, u32 y, u32 z) { return lut3<lut3_flip(0x96, NEG)>(x, y, z); }
@@ -291,7 +264,7 @@ GFQ_HD void f3_nc_value(const u32 *s, u32 *r) {
 }
 
 // F_5 addition and subtraction of 3-bit representatives in eight three-input instructions
-// (against eleven to thirteen for a 4-bit sum folded by fold5).  Bits of weight 4 = -1 enter
+// (against eleven to thirteen for a 4-bit sum folded back modulo 5).  Bits of weight 4 = -1 enter
 // weight 1 complemented (4x = ~x - 1) and a constant bit fixes the offsets, so that four
 // adders reduce the columns to one bit each, the last carry being bit 2 of the result:
 //   a + b: weight 2 gets a1, b1 and a constant 1 (sum ~(a1 ^ b1), carry a1 | b1, which goes
@@ -315,6 +288,16 @@ GFQ_HD void f5_sub8(const u32 *a, const u32 *b, u32 *r) {
     r[0] = fa_sum<3>(s1, a[2], c1);
     r[1] = u1 ^ k2;
     r[2] = u1 & k2;
+}
+// F_5 negation of a 3-bit representative: 0 - a by the subtraction above (the zero operand
+// folds into its truth tables).
+GFQ_HD P3v f5_neg(P3v a) {
+    const u32 z[3] = {0u, 0u, 0u}, b[3] = {a.b0, a.b1, a.b2};
+    u32 r[3];
+    f5_sub8(z, b, r);
+    P3v n;
+    n.b0 = r[0]; n.b1 = r[1]; n.b2 = r[2];
+    return n;
 }
 
 // One F_5 slab into a carry-save accumulator modulo 5 of three planes (a, b, c): its value
