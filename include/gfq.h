@@ -129,6 +129,26 @@ typedef struct { int k; int rows; int split; int variant; } gfq_config;
 int gfq_matmul_config(int q, int64_t m, int64_t l, int64_t n, const void *A, const void *B,
                       void *C, const gfq_config *cfg);
 
+/* gfq_matmul_config for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  Where the inner dimension
+ * is split, the slices' partial products go to a fixed device array of the library
+ * (GFQ_NOALLOC_SCRATCH_BYTES on each device, held from the library's loading until the
+ * process ends) instead of the workspace gfq_matmul allocates; the call makes no device
+ * allocation and times no launch (gfq_set_timing does not apply).
+ * cfg NULL: the configuration gfq_matmul would choose, its split lowered until the partial
+ * products (split * gfq_packed_bytes(q, m, n) bytes) fit the array.  An explicit cfg whose
+ * partial products do not fit returns GFQ_EBUDGET; one that does not split (split = 1, or
+ * l at most k) does not use the array.
+ * Every call on a device shares that device's array, which keeps what the last call left in
+ * it: calls that overlap in time on one device (different streams or threads) race on it,
+ * so issue them on one stream or wait between them.  Nothing in it needs clearing: each
+ * partial product is written in full before it is summed.  The first call on a device looks
+ * up the array's address on that device (GFQ_EHIP if the lookup fails).
+ * Other arguments and return codes as for gfq_matmul_config. */
+#define GFQ_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int gfq_matmul_noalloc(int q, int64_t m, int64_t l, int64_t n, const void *A, const void *B,
+                       void *C, const gfq_config *cfg);
+
 /* The configuration gfq_matmul would use for this problem shape (no launch). */
 int gfq_choose_config(int q, int64_t m, int64_t l, int64_t n, gfq_config *out);
 

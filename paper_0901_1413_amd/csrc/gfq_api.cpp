@@ -134,16 +134,6 @@ void gfq::fit_tiles(int q, int64_t m, int64_t l, int64_t n, gfq_config *c, bool 
 
 namespace {
 
-int check_config(int q, const gfq_config &c) {
-    if (c.k < 1 || c.k > KMAX) return GFQ_EINVAL;
-    if (c.rows != 256 && c.rows != 512 && c.rows != 1024 && c.rows != 2048) return GFQ_EINVAL;
-    if (c.split < 1 || c.split > 64) return GFQ_EINVAL;
-    if (c.variant != GFQ_VARIANT_ROWWISE && !(c.variant == GFQ_VARIANT_KARATSUBA && has_matrix_route(q)))
-        return GFQ_EINVAL;
-    if (mm_plan(kernel_field(q, c), c.k, c.rows).srb == 0) return GFQ_EINVAL;
-    return GFQ_OK;
-}
-
 // Batches launched by gfq_matmul_batched stay alive until their launch has completed;
 // each call (and gfq_sync) releases the ones whose completion event has fired.
 struct PendingBatch { gfq_batch *b; hipEvent_t done; };
@@ -184,6 +174,84 @@ int gfq::validate_mm(int q, int64_t m, int64_t l, int64_t n, const void *A, cons
     return GFQ_OK;
 }
 
+
+int gfq::check_config(int q, const gfq_config &c) {
+    if (c.k < 1 || c.k > KMAX) return GFQ_EINVAL;
+    if (c.rows != 256 && c.rows != 512 && c.rows != 1024 && c.rows != 2048) return GFQ_EINVAL;
+    if (c.split < 1 || c.split > 64) return GFQ_EINVAL;
+    if (c.variant != GFQ_VARIANT_ROWWISE && !(c.variant == GFQ_VARIANT_KARATSUBA && has_matrix_route(q)))
+        return GFQ_EINVAL;
+    if (mm_plan(kernel_field(q, c), c.k, c.rows).srb == 0) return GFQ_EINVAL;
+    return GFQ_OK;
+}
+
+int gfq::matmul_into(int q, int64_t m, int64_t l, int64_t n, const void *A, const void *B, void *C,
+                     const gfq_config *cfg, void *fixed_ws, size_t fixed_bytes) {
+    int st = validate_mm(q, m, l, n, A, B, C);
+    if (st != GFQ_OK) return st;
+    if (m == 0 || n == 0) return GFQ_OK;
+    gfq_config c;
+    if (cfg) {
+        c = *cfg;
+        st = check_config(q, c);
+        if (st != GFQ_OK) return st;
+    } else {
+        gfq_choose_config(q, m, l, n, &c);
+    }
+    const int P = planes_of(q);
+    const int Wn = words_of(n);
+    if (l == 0) {
+        hipError_t e = launch_fill_zero(C, gfq_packed_bytes(q, m, n), t_stream);
+        return e == hipSuccess ? GFQ_OK : hip_fail(e, "zero fill");
+    }
+    MMArgs a;
+    a.A = (const u32 *)A;
+    a.B = (const u32 *)B;
+    a.m = (int)m;
+    a.l = (int)l;
+    a.n = (int)n;
+    a.Wl = words_of(l);
+    a.Wn = Wn;
+    a.k = c.k;
+    a.S = (int)((l + c.k - 1) / c.k);
+    a.split_stride = (size_t)m * P * Wn;
+    int split = std::min(c.split, a.S);
+    if (fixed_ws) {
+        // the slices' partial products must fit the fixed region: a chosen split is capped,
+        // an explicit one that does not fit is refused
+        const size_t fit = fixed_bytes / (a.split_stride * 4);
+        if (split > 1 && (size_t)split > fit) {
+            if (cfg) return GFQ_EBUDGET;
+            split = (int)std::max<size_t>(1, std::min<size_t>(fit, (size_t)split));
+        }
+    }
+    a.slabs_per_split = (a.S + split - 1) / split;
+    split = (a.S + a.slabs_per_split - 1) / a.slabs_per_split;
+    const int kq = kernel_field(q, c);
+    const MMPlan plan = mm_plan(kq, c.k, c.rows);
+    // launches are timed only on the allocating path (events are created per launch)
+    const bool may_time = fixed_ws == nullptr;
+    if (split == 1) {
+        a.out = (u32 *)C;
+        hipError_t e = may_time ? timed(0, [&] { return launch_matmul(kq, a, plan, t_stream); })
+                                : launch_matmul(kq, a, plan, t_stream);
+        return e == hipSuccess ? GFQ_OK : hip_fail(e, "matmul launch");
+    }
+    void *ws = fixed_ws;
+    if (!ws) {
+        st = workspace(a.split_stride * 4 * split, t_stream, &ws);
+        if (st != GFQ_OK) return st;
+    }
+    a.out = (u32 *)ws;
+    auto product = [&] { return launch_matmul(kq, a, plan, t_stream); };
+    auto partial_sum = [&] {
+        return launch_reduce(q, (const u32 *)ws, (u32 *)C, (int)m, (int)n, Wn, split, a.split_stride, t_stream);
+    };
+    hipError_t e = may_time ? timed(0, product) : product();
+    if (e != hipSuccess) return hip_fail(e, "matmul launch");
+    e = may_time ? timed(1, partial_sum) : partial_sum();
+    return e == hipSuccess ? GFQ_OK : hip_fail(e, "reduce launch");
+}
 
 extern "C" {
 
@@ -296,54 +364,7 @@ int gfq_choose_config(int q, int64_t m, int64_t l, int64_t n, gfq_config *out) {
 
 int gfq_matmul_config(int q, int64_t m, int64_t l, int64_t n, const void *A, const void *B, void *C,
                       const gfq_config *cfg) {
-    int st = validate_mm(q, m, l, n, A, B, C);
-    if (st != GFQ_OK) return st;
-    if (m == 0 || n == 0) return GFQ_OK;
-    gfq_config c;
-    if (cfg) {
-        c = *cfg;
-        st = check_config(q, c);
-        if (st != GFQ_OK) return st;
-    } else {
-        gfq_choose_config(q, m, l, n, &c);
-    }
-    const int P = planes_of(q);
-    const int Wn = words_of(n);
-    if (l == 0) {
-        hipError_t e = launch_fill_zero(C, gfq_packed_bytes(q, m, n), t_stream);
-        return e == hipSuccess ? GFQ_OK : hip_fail(e, "zero fill");
-    }
-    MMArgs a;
-    a.A = (const u32 *)A;
-    a.B = (const u32 *)B;
-    a.m = (int)m;
-    a.l = (int)l;
-    a.n = (int)n;
-    a.Wl = words_of(l);
-    a.Wn = Wn;
-    a.k = c.k;
-    a.S = (int)((l + c.k - 1) / c.k);
-    int split = std::min(c.split, a.S);
-    a.slabs_per_split = (a.S + split - 1) / split;
-    split = (a.S + a.slabs_per_split - 1) / a.slabs_per_split;
-    a.split_stride = (size_t)m * P * Wn;
-    const int kq = kernel_field(q, c);
-    const MMPlan plan = mm_plan(kq, c.k, c.rows);
-    if (split == 1) {
-        a.out = (u32 *)C;
-        hipError_t e = timed(0, [&] { return launch_matmul(kq, a, plan, t_stream); });
-        return e == hipSuccess ? GFQ_OK : hip_fail(e, "matmul launch");
-    }
-    void *ws = nullptr;
-    st = workspace(a.split_stride * 4 * split, t_stream, &ws);
-    if (st != GFQ_OK) return st;
-    a.out = (u32 *)ws;
-    hipError_t e = timed(0, [&] { return launch_matmul(kq, a, plan, t_stream); });
-    if (e != hipSuccess) return hip_fail(e, "matmul launch");
-    e = timed(1, [&] {
-        return launch_reduce(q, (const u32 *)ws, (u32 *)C, (int)m, (int)n, Wn, split, a.split_stride, t_stream);
-    });
-    return e == hipSuccess ? GFQ_OK : hip_fail(e, "reduce launch");
+    return matmul_into(q, m, l, n, A, B, C, cfg, nullptr, 0);
 }
 
 int gfq_matmul(int q, int64_t m, int64_t l, int64_t n, const void *A, const void *B, void *C) {

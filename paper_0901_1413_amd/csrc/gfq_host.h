@@ -45,5 +45,14 @@ hipError_t launch_fill_random(u32 *p, size_t n, u32 seed, hipStream_t st);
 void fit_tiles(int q, int64_t m, int64_t l, int64_t n, gfq_config *c, bool keep_rows = false, int min_slabs = 32);
 // Field, dimension, pointer, alignment and aliasing checks of one product.
 int validate_mm(int q, int64_t m, int64_t l, int64_t n, const void *A, const void *B, void *C);
+// Range checks of an explicit configuration for field q (GFQ_OK or GFQ_EINVAL).
+int check_config(int q, const gfq_config &c);
+// One product as gfq_matmul_config (cfg NULL: the chosen configuration).  With fixed_ws, the
+// split-l partial products go to that device region of fixed_bytes instead of the
+// per-(device, stream) workspace, nothing is allocated and no launch is timed; a chosen split
+// is lowered until its partials fit, an explicit one whose partials do not fit returns
+// GFQ_EBUDGET.
+int matmul_into(int q, int64_t m, int64_t l, int64_t n, const void *A, const void *B, void *C,
+                const gfq_config *cfg, void *fixed_ws, size_t fixed_bytes);
 
 }  // namespace gfq

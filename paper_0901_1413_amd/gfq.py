@@ -70,6 +70,8 @@ _SIGS = {
     "gfq_matmul": (ctypes.c_int, [ctypes.c_int, _I64, _I64, _I64, _VP, _VP, _VP]),
     "gfq_matmul_config": (ctypes.c_int, [ctypes.c_int, _I64, _I64, _I64, _VP, _VP, _VP,
                                          ctypes.POINTER(Config)]),
+    "gfq_matmul_noalloc": (ctypes.c_int, [ctypes.c_int, _I64, _I64, _I64, _VP, _VP, _VP,
+                                          ctypes.POINTER(Config)]),
     "gfq_choose_config": (ctypes.c_int, [ctypes.c_int, _I64, _I64, _I64, ctypes.POINTER(Config)]),
     "gfq_matmul_sw": (ctypes.c_int, [ctypes.c_int, _I64, _I64, _I64, _VP, _VP, _VP, ctypes.c_int,
                                      ctypes.POINTER(Config)]),
@@ -202,6 +204,34 @@ def matmul(q: int, A, B, m: int, l: int, n: int, out=None, k: int = 0, rows: int
     else:
         _check(load().gfq_matmul(q, m, l, n, _VP(A.data_ptr()), _VP(B.data_ptr()), _VP(out.data_ptr())),
                "gfq_matmul")
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20   # GFQ_NOALLOC_SCRATCH_BYTES
+
+
+def matmul_noalloc(q: int, A, B, m: int, l: int, n: int, out, k: int = 0, rows: int = 0, split: int = 0,
+                   variant=None):
+    """gfq_matmul_noalloc: C = A B into the caller's packed `out` with no device allocation
+    (split partial products in the library's fixed per-device array).  k, rows, split and
+    variant give an explicit configuration (the others from gfq_choose_config); none of
+    them: the library's choice with the split fitted to the array."""
+    _bind_stream()
+    cfg = None
+    if k or rows or split or variant is not None:
+        c = Config()
+        _check(load().gfq_choose_config(q, m, l, n, ctypes.byref(c)), "gfq_choose_config")
+        if k:
+            c.k = k
+        if rows:
+            c.rows = rows
+        if split:
+            c.split = split
+        if variant is not None:
+            c.variant = variant
+        cfg = ctypes.byref(c)
+    _check(load().gfq_matmul_noalloc(q, m, l, n, _VP(A.data_ptr()), _VP(B.data_ptr()), _VP(out.data_ptr()), cfg),
+           "gfq_matmul_noalloc")
     return out
 
 
