@@ -3,11 +3,13 @@
 // Three representations meet in the product kernel:
 //   storage     the packed format of the C ABI (Section 4 encodings), P planes;
 //   table       how table entries (sums of rows of B) are held in LDS, P planes;
-//   accumulator how a lane keeps its running row of C, PA planes (a carry-save pair of
-//               residues modulo 7 for F_7, three-plane carry-save values modulo 3 and 5 for
-//               F_3 and F_5, see gfq_field.h).
+//   accumulator how a lane keeps its running row of C, PA planes (a binary residue
+//               modulo 3 for F_3, a carry-save pair of residues modulo 7 for F_7, a
+//               three-plane carry-save value modulo 5 for F_5, see gfq_field.h).
 // SPLIT_PREFIX: table chunk prefixes are summed one slab ahead by a quarter of the threads
 // (fields whose table addition is long) rather than by every build thread for itself.
+// SWAP_NEGATES: exchanging planes 2j and 2j + 1 of a table entry negates it; such fields
+// define neg_sel, which negates an accumulator where a lane mask is set.
 // Every trait works on one 32-bit word per plane (32 columns); the kernels apply it to
 // the four words of a 128-bit LDS read.
 #pragma once
@@ -22,24 +24,32 @@ namespace gfq {
 template <int Q> struct FT;
 
 // F_3 (Section 4.1).  Basis {1, -1}: phi_0 = [a = 1] = x0 ^ x1, phi_1 = [a = -1] = x1.
-// Table entries are binary residues mod 3; the accumulator is a three-plane carry-save value
-// mod 3 and receives T[phi_0] and -T[phi_1] (the complement) per slab.
+// Table entries and the accumulator are binary residues mod 3 (b0 + 2 b1, 3 meaning 0); per
+// slab the accumulator receives T[phi_0] and -T[phi_1], two four-instruction residue
+// additions.  Exchanging the two planes of a residue multiplies it by 2 = -1 (mod 3)
+// (SWAP_NEGATES): a lane that reads every table entry with its planes exchanged
+// accumulates -C, and neg_sel turns it back.
 template <> struct FT<3> {
-    static constexpr int P = 2, PT = 2, D = 2, GP = 2, PA = 3;
-    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false;
+    static constexpr int P = 2, PT = 2, D = 2, GP = 2, PA = 2;
+    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false, SWAP_NEGATES = true;
     static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0] ^ x[1]; f[1] = x[1]; }
     __device__ static void to_table(const u32 *x, u32 *t) { f3_to_bin(x[0], x[1], t); }
     __device__ static void tadd(const u32 *a, const u32 *b, u32 *r) { f3b_add(a, b, r); }
     __device__ static void tsub(const u32 *a, const u32 *b, u32 *r) { f3b_sub(a, b, r); }
     __device__ static void acc_init(u32 *c, int) { for (int i = 0; i < PA; i++) c[i] = 0u; }
-    // three planes, a + b + 2c modulo 3 (f3_nc_slab): T[phi_0] added, T[phi_1] subtracted
-    __device__ static void accumulate(u32 *c, const u32 (*t)[P]) { f3_nc_slab(c, t[0], t[1]); }
-    __device__ static void finish(const u32 *c, u32 *out) {
-        u32 v[2];
-        f3_nc_value(c, v);
-        f3_from_bin(v, &out[0], &out[1]);
+    __device__ static void accumulate(u32 *c, const u32 (*t)[P]) {
+        u32 x[2];
+        f3b_add(c, t[0], x);
+        f3b_sub(x, t[1], c);
     }
+    // the accumulator negated where gm is all ones (its planes exchanged), kept elsewhere
+    __device__ static void neg_sel(u32 *c, u32 gm) {
+        const u32 c0 = c[0];
+        c[0] = lut3<0xCA>(gm, c[1], c0);          // gm ? c1 : c0
+        c[1] = lut3<0xCA>(gm, c0, c[1]);
+    }
+    __device__ static void finish(const u32 *c, u32 *out) { f3_from_bin(c, &out[0], &out[1]); }
     __device__ static void sadd(const u32 *a, const u32 *b, u32 *r) {
         F3v z = f3_add(F3v{a[0], a[1]}, F3v{b[0], b[1]});
         r[0] = z.u; r[1] = z.s;
@@ -52,7 +62,7 @@ template <> struct FT<3> {
 // planes, so alpha_d T[phi_d] costs nothing; the accumulator is a carry-save pair mod 7.
 template <> struct FT<7> {
     static constexpr int P = 3, PT = 3, D = 3, GP = 3, PA = 6;
-    static constexpr bool SPLIT_PREFIX = true, HALF_ROWS = false;
+    static constexpr bool SPLIT_PREFIX = true, HALF_ROWS = false, SWAP_NEGATES = false;
     static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; f[2] = x[2]; }
     __device__ static void to_table(const u32 *x, u32 *t) { t[0] = x[0]; t[1] = x[1]; t[2] = x[2]; }
@@ -91,7 +101,7 @@ template <> struct FT<7> {
 // is already canonical at the end.
 template <> struct FT<5> {
     static constexpr int P = 3, PT = 3, D = 3, GP = 3, PA = 3;
-    static constexpr bool SPLIT_PREFIX = true, HALF_ROWS = false;
+    static constexpr bool SPLIT_PREFIX = true, HALF_ROWS = false, SWAP_NEGATES = false;
     static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; f[2] = x[2]; }
     __device__ static void to_table(const u32 *x, u32 *t) { t[0] = x[0]; t[1] = x[1]; t[2] = x[2]; }
@@ -119,7 +129,7 @@ template <> struct FT<5> {
 // T[phi_0] + x T[phi_1]; with x (c0 + c1 x) = c1 + (c0 + c1) x that is two XOR planes.
 template <> struct FT<4> {
     static constexpr int P = 2, PT = 2, D = 2, GP = 2, PA = 2;
-    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false;
+    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false, SWAP_NEGATES = false;
     static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; }
     __device__ static void to_table(const u32 *x, u32 *t) { t[0] = x[0]; t[1] = x[1]; }
@@ -143,7 +153,7 @@ template <> struct FT<4> {
 // Same packed operands and product as FT<4>; selected by the configuration.
 template <> struct FT<GF4_KARATSUBA> {
     static constexpr int P = 2, PT = 3, D = 3, GP = 1, PA = 2;
-    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false;
+    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false, SWAP_NEGATES = false;
     static constexpr int gplane(int d, int) { return d; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; f[2] = x[0] ^ x[1]; }
     __device__ static void to_table(const u32 *x, u32 *t) { t[0] = x[0]; t[1] = x[1]; t[2] = x[0] ^ x[1]; }
@@ -166,7 +176,7 @@ template <> struct FT<GF4_KARATSUBA> {
 // x^2 T[phi_2] (g8_acc, six operations for three planes).
 template <> struct FT<8> {
     static constexpr int P = 3, PT = 3, D = 3, GP = 3, PA = 3;
-    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false;
+    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false, SWAP_NEGATES = false;
     static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; f[2] = x[2]; }
     __device__ static void to_table(const u32 *x, u32 *t) { t[0] = x[0]; t[1] = x[1]; t[2] = x[2]; }
@@ -192,7 +202,7 @@ template <> struct FT<9> {
     static constexpr int P = 4, PT = 4, D = 4, GP = 4, PA = 8;
     // HALF_ROWS: a row's gathers are consumed in two halves (accumulate_half), so only half a
     // row of 128-bit reads is in flight at a time and four rows per lane fit the registers
-    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = true;
+    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = true, SWAP_NEGATES = false;
     static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0] ^ x[1]; f[1] = x[1]; f[2] = x[2] ^ x[3]; f[3] = x[3]; }
     __device__ static void to_table(const u32 *x, u32 *t) { f3_to_bin(x[0], x[1], t); f3_to_bin(x[2], x[3], t + 2); }
@@ -255,7 +265,7 @@ template <> struct FT<9> {
 // FT<8>; selected by the configuration.
 template <> struct FT<GF8_TRINOMIAL> {
     static constexpr int P = 3, PT = 6, D = 6, GP = 1, PA = 3;
-    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false;
+    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false, SWAP_NEGATES = false;
     static constexpr int gplane(int d, int) { return d; }
     __device__ static void phis(const u32 *x, u32 *f) {
         f[0] = x[0]; f[1] = x[1]; f[2] = x[2]; f[3] = x[0] ^ x[1]; f[4] = x[0] ^ x[2]; f[5] = x[1] ^ x[2];
@@ -285,7 +295,7 @@ template <> struct FT<GF8_TRINOMIAL> {
 // operands and product as FT<9>; selected by the configuration.
 template <> struct FT<F9_KARATSUBA> {
     static constexpr int P = 4, PT = 6, D = 6, GP = 2, PA = 12;
-    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false;
+    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false, SWAP_NEGATES = false;
     static constexpr int gplane(int d, int p) { return (d >> 1) * 2 + p; }
     __device__ static void phis(const u32 *x, u32 *f) {
         const F3v s = f3_add(F3v{x[0], x[1]}, F3v{x[2], x[3]});   // a0 + a1

@@ -39,6 +39,8 @@ static hipError_t launch_mm(const MMArgs &a0, const MMPlan &plan, const MMStride
     constexpr int LPR = TWD / 4;
     constexpr int TM = (NT_MM / LPR) * R;
     if (plan.TM != TM || plan.lds > 163840) return hipErrorInvalidValue;
+    // byte-permuted gather addresses take the second table at a multiple of 64 KiB
+    if (perm_addr_tile<Q, TWD, REP>() && plan.tb1 % 65536u != 0) return hipErrorInvalidValue;
     MMArgs a = a0;
     a.tb1 = plan.tb1;
     const int row_tiles = (a.m + TM - 1) / TM;
@@ -73,7 +75,7 @@ static hipError_t launch_mm_rows(const MMArgs &a, const MMPlan &plan, const MMSt
         return launch_mm<STRIDED, Q, TWD, REP, 4>(a, plan, sd, st);       // eight rows per lane would spill
     } else {
         if (plan.R == 4) return launch_mm<STRIDED, Q, TWD, REP, 4>(a, plan, sd, st);
-        if constexpr ((Q == 4 || Q == GF4_KARATSUBA) && TWD == 16) {
+        if constexpr (((Q == 4 || Q == GF4_KARATSUBA) && TWD == 16) || (Q == 3 && (TWD == 16 || TWD == 32))) {
             if (plan.R == 16) return launch_mm<STRIDED, Q, TWD, REP, 16>(a, plan, sd, st);   // two planes per word
         }
         return launch_mm<STRIDED, Q, TWD, REP, 8>(a, plan, sd, st);

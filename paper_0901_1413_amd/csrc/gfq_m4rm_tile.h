@@ -49,6 +49,19 @@ __device__ __forceinline__ u32 comp4(const uint4 &v, int i) {
 
 template <int H> struct half_tag { static constexpr int value = H; };
 
+// Tiles whose rows of C, two to a 16-lane read pass, read their table planes in opposite
+// orders (see m4rm_tile, GSW): fields negated by exchanging planes 2j and 2j + 1, 128-byte
+// super-rows.  With two table planes an entry takes 256 bytes, so its offset is the entry
+// index times 256: one byte, and every gathered address is put together by one byte
+// permutation (lane byte, entry byte, table-base bytes).  That needs the second table at a
+// multiple of 65536 bytes (the launcher checks it).
+template <int Q, int TWD, int REP> constexpr bool gsw_tile() {
+    return FT<Q>::SWAP_NEGATES && REP == 1 && TWD == 32;
+}
+template <int Q, int TWD, int REP> constexpr bool perm_addr_tile() {
+    return gsw_tile<Q, TWD, REP>() && FT<Q>::PT == 2 && !FT<Q>::HALF_ROWS;
+}
+
 // One tile of the product: column tile bx, row tile by, slab slice bz of the problem `a`.
 // Called by every thread of an NT-thread workgroup; uses the workgroup's dynamic LDS.
 template <int Q, int TWD, int REP, int R, int NT>
@@ -71,7 +84,16 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
     // entry starts on a 256-byte boundary, so plane p of every entry would sit in the same
     // half and the two rows of a pass would always meet there: planes swap in pairs on odd
     // entries (plane p of entry e at (p ^ (e & 1)) * SRB), so the halves follow the entries.
-    constexpr bool SWZ = (PT % 2 == 0) && SRB == 128;
+    //
+    // Fields whose entries are negated by exchanging planes 2j and 2j + 1 (F::SWAP_NEGATES)
+    // avoid the meetings altogether: the second row of every pass (lanes 8-15 of each 16)
+    // reads plane p ^ 1 where the first reads plane p, so the two rows are always in
+    // opposite halves; that row accumulates -C and is negated before it is stored.
+    constexpr bool GSW = gsw_tile<Q, TWD, REP>();
+    constexpr bool PERM = perm_addr_tile<Q, TWD, REP>();
+    static_assert(!GSW || (SRB == 128 && LPR == 8), "two rows of C per 16-lane pass");
+    constexpr bool SWZ = (PT % 2 == 0) && SRB == 128 && !GSW;
+    constexpr bool XSW = SWZ || GSW;             // odd planes read at the row's address ^ SRB
     static_assert(KMAX * P * CG <= NT, "one B staging chunk per thread");
     static_assert(REP * LPR <= 16, "super-row wider than a 16-lane read group");
     static_assert(NCH % REP == 0 || REP % NCH == 0, "replica rotation");
@@ -313,22 +335,34 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
 #pragma unroll
             for (int p = 0; p < PT; p++) v[p] = pb[(ch * PT + p) * TWD];
         } else {
-            // the chunk's prefix here: a masked sum of its rows G + t
-            u32 pr[LOG_NCH][P];
-#pragma unroll
-            for (int t = 0; t < LOG_NCH; t++)
-#pragma unroll
-                for (int p = 0; p < P; p++) pr[t][p] = bs[((G + t) * P + p) * TWD];
+            // the chunk's prefix here: the sum of its rows G + t over the bits t of ch.  A wave
+            // holds 64 / TWD consecutive chunks, so only the low LOWB bits of ch differ
+            // between its lanes: those rows enter masked (the zero row adds nothing, and the
+            // first one is the prefix itself), the others only where the wave's bit is set
+            // (a branch on a value every lane shares).
+            constexpr int LOWB = TWD >= 64 ? 0 : log2_floor(64 / TWD);
+            const int chw = __builtin_amdgcn_readfirstlane(ch);
 #pragma unroll
             for (int p = 0; p < PT; p++) v[p] = 0u;
 #pragma unroll
             for (int t = 0; t < LOG_NCH; t++) {
-                const u32 m = (t < C) ? 0u - (u32)((ch >> t) & 1) : 0u;
-                u32 r[PT], x[PT];
-                F::to_table(pr[t], x);
+                if (t >= C) break;
+                if (t >= LOWB && !((chw >> t) & 1)) continue;
+                u32 pr[P], x[PT];
 #pragma unroll
-                for (int p = 0; p < PT; p++) r[p] = x[p] & m;        // the zero row adds nothing
-                step(v, r, true);
+                for (int p = 0; p < P; p++) pr[p] = bs[((G + t) * P + p) * TWD];
+                F::to_table(pr, x);
+                if (t < LOWB) {
+                    const u32 m = 0u - (u32)((ch >> t) & 1);
+#pragma unroll
+                    for (int p = 0; p < PT; p++) x[p] &= m;
+                }
+                if (t == 0) {
+#pragma unroll
+                    for (int p = 0; p < PT; p++) v[p] = x[p];
+                } else {
+                    step(v, x, true);
+                }
             }
         }
         unsigned char *eb = T + (u32)(ch << G) * (PT * SRB);
@@ -361,7 +395,8 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
         for (int i = 0; i < 4; i++) F::acc_init(acc[r][i], s_end - s_begin);
 
     const int rs = tid / LPR, cg = tid % LPR;
-    const u32 laneoff = (u32)(tid % (REP * LPR)) * 16u;
+    const bool neg_row = GSW && ((tid / LPR) & 1);   // reads planes exchanged, accumulates -C
+    const u32 laneoff = (u32)(tid % (REP * LPR)) * 16u + (neg_row ? (u32)SRB : 0u);
 
     // gathers of one row: D table rows, GP planes each (plane F::gplane(d, p) of row d), 4 words
     // per lane
@@ -374,13 +409,23 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
 #pragma unroll
         for (int d = 0; d < D; d++) {
             const u32 x = iw[r * IBW + (d >> 1)];
-            const u32 off = ((d & 1) ? (x >> 16) : (x & 0xffffu)) | lo;
+            u32 off, offx;
+            if constexpr (PERM) {
+                // offsets are entry * 256 (byte 1 of each 16-bit half); lo holds the lane's
+                // byte offset (byte 0) and the table base (bytes 2, 3)
+                const u32 sel = (d & 1) ? 0x03020700u : 0x03020500u;
+                off = __builtin_amdgcn_perm(x, lo, sel);
+                offx = __builtin_amdgcn_perm(x, lo ^ (u32)SRB, sel);
+            } else {
+                off = ((d & 1) ? (x >> 16) : (x & 0xffffu)) | lo;
+                offx = XSW ? off ^ (u32)SRB : off;
+            }
             lds_u32x4 *row = (lds_u32x4 *)(uintptr_t)off;
-            lds_u32x4 *rowx = (lds_u32x4 *)(uintptr_t)(SWZ ? off ^ (u32)SRB : off);   // odd planes
+            lds_u32x4 *rowx = (lds_u32x4 *)(uintptr_t)offx;   // odd planes
 #pragma unroll
             for (int p = 0; p < GP; p++) {
                 const int pl = F::gplane(d, p);
-                const u32x4 v = (SWZ && (pl & 1)) ? rowx[(pl & ~1) * (SRB / 16)] : row[(SWZ ? (pl & ~1) : pl) * (SRB / 16)];
+                const u32x4 v = (XSW && (pl & 1)) ? rowx[(pl & ~1) * (SRB / 16)] : row[(XSW ? (pl & ~1) : pl) * (SRB / 16)];
                 t[d][p] = make_uint4(v.x, v.y, v.z, v.w);
             }
         }
@@ -405,11 +450,11 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
             const u32 x = iw[r * IBW + (d >> 1)];
             const u32 off = ((d & 1) ? (x >> 16) : (x & 0xffffu)) | lo;
             lds_u32x4 *row = (lds_u32x4 *)(uintptr_t)off;
-            lds_u32x4 *rowx = (lds_u32x4 *)(uintptr_t)(SWZ ? off ^ (u32)SRB : off);   // odd planes
+            lds_u32x4 *rowx = (lds_u32x4 *)(uintptr_t)(XSW ? off ^ (u32)SRB : off);   // odd planes
 #pragma unroll
             for (int p = 0; p < GP; p++) {
                 const int pl = F::gplane(d, p);
-                const u32x4 v = (SWZ && (pl & 1)) ? rowx[(pl & ~1) * (SRB / 16)] : row[(SWZ ? (pl & ~1) : pl) * (SRB / 16)];
+                const u32x4 v = (XSW && (pl & 1)) ? rowx[(pl & ~1) * (SRB / 16)] : row[(XSW ? (pl & ~1) : pl) * (SRB / 16)];
                 t[dd][p] = make_uint4(v.x, v.y, v.z, v.w);
             }
         }
@@ -542,7 +587,10 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
             if (row < a.m) {
                 u32 o[4][P];
 #pragma unroll
-                for (int i = 0; i < 4; i++) F::finish(acc[r][i], o[i]);
+                for (int i = 0; i < 4; i++) {
+                    if constexpr (GSW) F::neg_sel(acc[r][i], neg_row ? 0xffffffffu : 0u);
+                    F::finish(acc[r][i], o[i]);
+                }
 #pragma unroll
                 for (int p = 0; p < P; p++)
                     *reinterpret_cast<uint4 *>(out + ((size_t)row * P + p) * a.Wn + w) =

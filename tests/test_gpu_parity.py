@@ -331,7 +331,7 @@ WIDE_K = {3: 8, 4: 8, 5: 7, 7: 7, 8: 7, 9: 7}
 
 
 @pytest.mark.parametrize("q", FIELDS)
-@pytest.mark.parametrize("rows,split", [(512, 1), (512, 3), (256, 2)])
+@pytest.mark.parametrize("rows,split", [(512, 1), (512, 3), (256, 2), (1024, 1), (1024, 3), (2048, 2)])
 def test_wide_tiles(gfq_gpu, q, rows, split):
     """32-word tiles: three column tiles with a ragged last one (n = 2300 is 72 words), a ragged
     last row tile and a ragged last slab, at the tile heights and splits the layout runs with;
@@ -340,11 +340,12 @@ def test_wide_tiles(gfq_gpu, q, rows, split):
     check(gfq_gpu, q, A, B, k=WIDE_K[q], rows=rows, split=split)
 
 
-@pytest.mark.parametrize("q", [3, 9])
-def test_wide_tiles_entry_parity(gfq_gpu, q):
+@pytest.mark.parametrize("q,rows", [(3, 512), (3, 1024), (3, 256), (9, 0)])
+def test_wide_tiles_entry_parity(gfq_gpu, q, rows):
     """B = identity rows in a fixed order and A one-hot, so that every table entry of both
     parities is gathered and each product row equals one row of B: a plane swap left undone on
-    odd entries would show as swapped planes in those rows."""
+    odd entries, or on the rows that read their planes exchanged (F_3: the second row of every
+    16-lane read pass, which accumulates the negated row), would show as swapped planes."""
     k = WIDE_K[q]
     l, n = 2 * k, 1500
     rng = np.random.default_rng(231)
@@ -355,4 +356,4 @@ def test_wide_tiles_entry_parity(gfq_gpu, q):
         for t in range(k):
             A[e, t] = (e >> t) & 1
         A[e, k + (e % k)] = 1                # and one row of slab 1
-    check(gfq_gpu, q, A, B, k=k)
+    check(gfq_gpu, q, A, B, k=k, rows=rows)
