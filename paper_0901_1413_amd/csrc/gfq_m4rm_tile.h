@@ -94,6 +94,9 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
     static_assert(!GSW || (SRB == 128 && LPR == 8), "two rows of C per 16-lane pass");
     constexpr bool SWZ = (PT % 2 == 0) && SRB == 128 && !GSW;
     constexpr bool XSW = SWZ || GSW;             // odd planes read at the row's address ^ SRB
+    // gathers of two rows ahead where the accumulate per row is short (F_3: 32 instructions
+    // per row against four 128-bit reads) and the registers allow it
+    constexpr bool PF2 = GSW && R == 16;
     static_assert(KMAX * P * CG <= NT, "one B staging chunk per thread");
     static_assert(REP * LPR <= 16, "super-row wider than a 16-lane read group");
     static_assert(NCH % REP == 0 || REP % NCH == 0, "replica rotation");
@@ -135,6 +138,14 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
     };
 
     // ---- staging of A: a window of words (w, w+1, w+2) per staged row and plane ----
+    // Staging slot j of this thread is position i = tid + j NT of the offset buffer, which
+    // holds the rows of one row slot together (position rs R + r for row rs + r RS, so that a
+    // lane fetches its R rows' offsets with 128-bit reads); slot j therefore stages that
+    // row, and the offsets of a wave's 64 lanes land in consecutive words (no bank conflict).
+    auto srow = [&](int j) -> int {
+        const int i = min(tid + j * NT, TM - 1);
+        return (i % R) * RS + i / R;
+    };
     u32 aw[ARPT][P][3], apre[ARPT][P];
     int aw_w = (s_begin * k) >> 5;
     // One staged row per thread and at most three planes: the words entering the window come
@@ -148,16 +159,15 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
     // slabs, so l >= 1, Wl >= 4 and m >= 1 (a tile exists).
     auto load_quad = [&](int wn) {
         const int qw = min(wn & ~3, a.Wl - 4);
-        const int row = min(row0 + min(tid, TM - 1), a.m - 1);
+        const int row = min(row0 + srow(0), a.m - 1);
 #pragma unroll
         for (int p = 0; p < (AQ ? P : 0); p++)
             aq[p] = *reinterpret_cast<const uint4 *>(a.A + ((size_t)row * P + p) * a.Wl + qw);
     };
     auto quad_word = [](const uint4 &q, int c) -> u32 { return c == 0 ? q.x : (c == 1 ? q.y : (c == 2 ? q.z : q.w)); };
     auto a_word = [&](int j, int p, int w) -> u32 {
-        const int lr = tid + j * NT;
-        const int row = row0 + lr;
-        if (lr < TM && row < a.m && w < a.Wl) return a.A[((size_t)row * P + p) * a.Wl + w];
+        const int row = row0 + srow(j);
+        if (tid + j * NT < TM && row < a.m && w < a.Wl) return a.A[((size_t)row * P + p) * a.Wl + w];
         return 0u;
     };
 #pragma unroll
@@ -174,8 +184,7 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
         if (s_begin < s_end) load_quad(aw_w + 3);
     }
     auto apre_mask = [&](int j, int w) -> u32 {
-        const int lr = tid + j * NT;
-        return (lr < TM && row0 + lr < a.m && w < a.Wl) ? 0xffffffffu : 0u;
+        return (tid + j * NT < TM && row0 + srow(j) < a.m && w < a.Wl) ? 0xffffffffu : 0u;
     };
     // offsets (u16, entry * PT * SRB) of the D table rows for slab s, for every tile row
     auto stage_idx = [&](int s) {
@@ -183,8 +192,8 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
         u32 *ib = Ib + (s % 3) * TM * IBW;
 #pragma unroll
         for (int j = 0; j < ARPT; j++) {
-            const int lr = tid + j * NT;
-            if (lr < TM) {
+            const int pos = tid + j * NT;           // row srow(j)
+            if (pos < TM) {
                 u32 x[P], f[D];
 #pragma unroll
                 for (int p = 0; p < P; p++) x[p] = __builtin_amdgcn_alignbit(aw[j][p][1], aw[j][p][0], sh) & kmask;
@@ -195,9 +204,6 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
                     const u32 e = d < D ? f[d < D ? d : 0] : 0u;
                     o[d] = e * (u32)(PT * SRB) + (SWZ ? (e & 1u) * (u32)SRB : 0u);   // plane 0's place
                 }
-                // slot-major: the R rows of one row slot are adjacent, so a lane fetches
-                // all of its offsets with one or two 128-bit reads
-                const int pos = (lr % RS) * R + lr / RS;
 #pragma unroll
                 for (int w = 0; w < IBW; w++) ib[pos * IBW + w] = o[2 * w] | (o[2 * w + 1] << 16);
             }
@@ -213,7 +219,7 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
         const int w = min(aw_w + 3, a.Wl - 1);
 #pragma unroll
         for (int j = 0; j < ARPT; j++) {
-            const int row = min(row0 + min(tid + j * NT, TM - 1), a.m - 1);
+            const int row = min(row0 + srow(j), a.m - 1);
 #pragma unroll
             for (int p = 0; p < P; p++) apre[j][p] = a.A[((size_t)row * P + p) * a.Wl + w];
         }
@@ -503,6 +509,16 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
                 consume_half0(r, h0);
                 if (r + 1 < R) fetch_half(iw, r + 1, 0, lo, h0);
                 consume_half1(r, h1);
+            }
+        } else if constexpr (PF2) {
+            // two rows of reads in flight: row r+2's are issued before row r is added
+            uint4 tq[3][D][GP];
+            fetch(iw, 0, lo, tq[0]);
+            if (R > 1) fetch(iw, 1, lo, tq[1]);
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                if (r + 2 < R) fetch(iw, r + 2, lo, tq[(r + 2) % 3]);
+                consume(r, tq[r % 3]);
             }
         } else {
             uint4 ta[D][GP], tb[D][GP];
