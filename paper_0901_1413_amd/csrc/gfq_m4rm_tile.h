@@ -255,12 +255,16 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
     // masked sum).  The rows a stage needs are read from LDS in one batch before its chain
     // of additions. ----
     constexpr bool SPLIT_PREFIX = F::SPLIT_PREFIX;
-    constexpr int GMAX = KMAX > LOG_NCH ? KMAX - LOG_NCH : 0;   // longest walk: 2^GMAX entries
+    // HALF_BUILD: only the first half of the waves build (one per SIMD), each walking twice
+    // as far, so that half as many chunk prefixes are summed
+    constexpr bool HALF_BUILD = GSW && R == 16;
+    constexpr int LOG_NB = LOG_NCH - (HALF_BUILD ? 1 : 0);     // log2 of the building chunks
+    constexpr int GMAX = KMAX > LOG_NB ? KMAX - LOG_NB : 0;     // longest walk: 2^GMAX entries
     constexpr int PFW = NCH / 4;                                // prefix threads per word
     constexpr int PFB = LOG_NCH > 2 ? LOG_NCH - 2 : 0;         // masked bits per prefix thread
     static_assert(NCH >= 4, "four chunks per prefix thread");
     const int dw = tid % TWD, ch = tid / TWD;
-    const int C = k > LOG_NCH ? LOG_NCH : k;     // chunk bits
+    const int C = k > LOG_NB ? LOG_NB : k;       // chunk bits
     const int G = k - C;                         // walk bits
     const int nchunks = 1 << C;
     u32 rep_off[REP];                            // this chunk's copy rotation
