@@ -257,7 +257,7 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
     constexpr bool SPLIT_PREFIX = F::SPLIT_PREFIX;
     // HALF_BUILD: only the first half of the waves build (one per SIMD), each walking twice
     // as far, so that half as many chunk prefixes are summed
-    constexpr bool HALF_BUILD = GSW && R == 16;
+    constexpr bool HALF_BUILD = !SPLIT_PREFIX && NCH >= 8;
     constexpr int LOG_NB = LOG_NCH - (HALF_BUILD ? 1 : 0);     // log2 of the building chunks
     constexpr int GMAX = KMAX > LOG_NB ? KMAX - LOG_NB : 0;     // longest walk: 2^GMAX entries
     constexpr int PFW = NCH / 4;                                // prefix threads per word
