@@ -10,6 +10,12 @@
 // (fields whose table addition is long) rather than by every build thread for itself.
 // SWAP_NEGATES: exchanging planes 2j and 2j + 1 of a table entry negates it; such fields
 // define neg_sel, which negates an accumulator where a lane mask is set.
+// HALF_BUILD_ROWS: from this many rows per lane on, the gathers of a slab outweigh its
+// table build enough that only half of the waves (one per SIMD) build the table, each
+// walking twice as far, with half the chunk prefixes (measured faster for every field at
+// the rows per lane listed; F_7, whose eleven-instruction table additions face four rows per
+// lane of eighteen-instruction accumulates, measured slower: its building waves became the
+// tail of every slab).
 // Every trait works on one 32-bit word per plane (32 columns); the kernels apply it to
 // the four words of a 128-bit LDS read.
 #pragma once
@@ -32,6 +38,7 @@ template <int Q> struct FT;
 template <> struct FT<3> {
     static constexpr int P = 2, PT = 2, D = 2, GP = 2, PA = 2;
     static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false, SWAP_NEGATES = true;
+    static constexpr int HALF_BUILD_ROWS = 8;
     static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0] ^ x[1]; f[1] = x[1]; }
     __device__ static void to_table(const u32 *x, u32 *t) { f3_to_bin(x[0], x[1], t); }
@@ -63,6 +70,7 @@ template <> struct FT<3> {
 template <> struct FT<7> {
     static constexpr int P = 3, PT = 3, D = 3, GP = 3, PA = 6;
     static constexpr bool SPLIT_PREFIX = true, HALF_ROWS = false, SWAP_NEGATES = false;
+    static constexpr int HALF_BUILD_ROWS = 1 << 30;
     static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; f[2] = x[2]; }
     __device__ static void to_table(const u32 *x, u32 *t) { t[0] = x[0]; t[1] = x[1]; t[2] = x[2]; }
@@ -102,6 +110,7 @@ template <> struct FT<7> {
 template <> struct FT<5> {
     static constexpr int P = 3, PT = 3, D = 3, GP = 3, PA = 3;
     static constexpr bool SPLIT_PREFIX = true, HALF_ROWS = false, SWAP_NEGATES = false;
+    static constexpr int HALF_BUILD_ROWS = 8;
     static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; f[2] = x[2]; }
     __device__ static void to_table(const u32 *x, u32 *t) { t[0] = x[0]; t[1] = x[1]; t[2] = x[2]; }
@@ -130,6 +139,7 @@ template <> struct FT<5> {
 template <> struct FT<4> {
     static constexpr int P = 2, PT = 2, D = 2, GP = 2, PA = 2;
     static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false, SWAP_NEGATES = false;
+    static constexpr int HALF_BUILD_ROWS = 8;
     static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; }
     __device__ static void to_table(const u32 *x, u32 *t) { t[0] = x[0]; t[1] = x[1]; }
@@ -154,6 +164,7 @@ template <> struct FT<4> {
 template <> struct FT<GF4_KARATSUBA> {
     static constexpr int P = 2, PT = 3, D = 3, GP = 1, PA = 2;
     static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false, SWAP_NEGATES = false;
+    static constexpr int HALF_BUILD_ROWS = 8;
     static constexpr int gplane(int d, int) { return d; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; f[2] = x[0] ^ x[1]; }
     __device__ static void to_table(const u32 *x, u32 *t) { t[0] = x[0]; t[1] = x[1]; t[2] = x[0] ^ x[1]; }
@@ -177,6 +188,7 @@ template <> struct FT<GF4_KARATSUBA> {
 template <> struct FT<8> {
     static constexpr int P = 3, PT = 3, D = 3, GP = 3, PA = 3;
     static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false, SWAP_NEGATES = false;
+    static constexpr int HALF_BUILD_ROWS = 8;
     static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; f[2] = x[2]; }
     __device__ static void to_table(const u32 *x, u32 *t) { t[0] = x[0]; t[1] = x[1]; t[2] = x[2]; }
@@ -203,6 +215,7 @@ template <> struct FT<9> {
     // HALF_ROWS: a row's gathers are consumed in two halves (accumulate_half), so only half a
     // row of 128-bit reads is in flight at a time and four rows per lane fit the registers
     static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = true, SWAP_NEGATES = false;
+    static constexpr int HALF_BUILD_ROWS = 4;
     static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0] ^ x[1]; f[1] = x[1]; f[2] = x[2] ^ x[3]; f[3] = x[3]; }
     __device__ static void to_table(const u32 *x, u32 *t) { f3_to_bin(x[0], x[1], t); f3_to_bin(x[2], x[3], t + 2); }
@@ -266,6 +279,7 @@ template <> struct FT<9> {
 template <> struct FT<GF8_TRINOMIAL> {
     static constexpr int P = 3, PT = 6, D = 6, GP = 1, PA = 3;
     static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false, SWAP_NEGATES = false;
+    static constexpr int HALF_BUILD_ROWS = 8;
     static constexpr int gplane(int d, int) { return d; }
     __device__ static void phis(const u32 *x, u32 *f) {
         f[0] = x[0]; f[1] = x[1]; f[2] = x[2]; f[3] = x[0] ^ x[1]; f[4] = x[0] ^ x[2]; f[5] = x[1] ^ x[2];
@@ -296,6 +310,7 @@ template <> struct FT<GF8_TRINOMIAL> {
 template <> struct FT<F9_KARATSUBA> {
     static constexpr int P = 4, PT = 6, D = 6, GP = 2, PA = 12;
     static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false, SWAP_NEGATES = false;
+    static constexpr int HALF_BUILD_ROWS = 1 << 30;
     static constexpr int gplane(int d, int p) { return (d >> 1) * 2 + p; }
     __device__ static void phis(const u32 *x, u32 *f) {
         const F3v s = f3_add(F3v{x[0], x[1]}, F3v{x[2], x[3]});   // a0 + a1

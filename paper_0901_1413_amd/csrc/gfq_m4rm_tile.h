@@ -256,13 +256,14 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
     // of additions. ----
     constexpr bool SPLIT_PREFIX = F::SPLIT_PREFIX;
     // HALF_BUILD: only the first half of the waves build (one per SIMD), each walking twice
-    // as far, so that half as many chunk prefixes are summed
-    constexpr bool HALF_BUILD = !SPLIT_PREFIX && NCH >= 8;
+    // as far, so that half as many chunk prefixes are summed (F::HALF_BUILD_ROWS)
+    constexpr bool HALF_BUILD = NCH >= 8 && R >= F::HALF_BUILD_ROWS;
     constexpr int LOG_NB = LOG_NCH - (HALF_BUILD ? 1 : 0);     // log2 of the building chunks
+    constexpr int NB = 1 << LOG_NB;
     constexpr int GMAX = KMAX > LOG_NB ? KMAX - LOG_NB : 0;     // longest walk: 2^GMAX entries
-    constexpr int PFW = NCH / 4;                                // prefix threads per word
-    constexpr int PFB = LOG_NCH > 2 ? LOG_NCH - 2 : 0;         // masked bits per prefix thread
-    static_assert(NCH >= 4, "four chunks per prefix thread");
+    constexpr int PFW = NB / 4;                                 // prefix threads per word
+    constexpr int PFB = LOG_NB > 2 ? LOG_NB - 2 : 0;           // masked bits per prefix thread
+    static_assert(NB >= 4, "four chunks per prefix thread");
     const int dw = tid % TWD, ch = tid / TWD;
     const int C = k > LOG_NB ? LOG_NB : k;       // chunk bits
     const int G = k - C;                         // walk bits
