@@ -108,12 +108,16 @@ int gfq_oracle_matmul(int q, int64_t m, int64_t l, int64_t n,
                     C[i * ldc + j] = (uint8_t)(r + 3 * m);
                 }
             } else if (q == 4 || q == 8) {
-                uint8_t (*mul)(uint8_t, uint8_t) = q == 4 ? gf4_mul : gf8_mul;
+                /* the two fields in loops of their own, so that each calls its
+                 * multiplication directly */
                 for (int64_t t = 0; t < l; t++) {
                     uint8_t a = arow[t];
                     if (a == 0) continue;
                     const uint8_t *brow = B + t * ldb;
-                    for (int64_t j = 0; j < n; j++) acc[j] ^= mul(a, brow[j]);
+                    if (q == 4)
+                        for (int64_t j = 0; j < n; j++) acc[j] ^= gf4_mul(a, brow[j]);
+                    else
+                        for (int64_t j = 0; j < n; j++) acc[j] ^= gf8_mul(a, brow[j]);
                 }
                 for (int64_t j = 0; j < n; j++) C[i * ldc + j] = (uint8_t)acc[j];
             } else {
