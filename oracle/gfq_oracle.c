@@ -73,13 +73,14 @@ int gfq_oracle_matmul(int q, int64_t m, int64_t l, int64_t n,
     if (m == 0 || n == 0) return 0;
     if (C == NULL || (l > 0 && (A == NULL || B == NULL))) return -3;
     if (lda < l || ldb < n || ldc < n) return -2;
+    /* a thread count for this call only (the process default is never changed) */
 #ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
+    const int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
 #else
     (void)nthreads;
 #endif
     int err = 0;
-#pragma omp parallel
+#pragma omp parallel num_threads(nt)
     {
         int32_t *acc = (int32_t *)malloc((size_t)n * 2 * sizeof(int32_t));
         if (acc == NULL) {
