@@ -7,18 +7,26 @@ partial-sum kernel when the inner dimension is split), unpack C.  Inputs are res
 HBM before timing starts.
 
 Printed: one JSON line with field-ops/s (2 m l n / t) for the whole step, the roofline of
-the dominant kernel (the product kernel of the field that takes longest), the CPU oracle
-timed on a bounded row sample of the same products (its rows are also compared bit-exactly
-with the GPU product), and sections for the other workloads:
+the dominant kernel (the product kernel of the field that takes longest) and of the F_3
+product, the machine rates the rooflines are quoted against (derived from the unit counts
+and clock, and microbenchmarked in the run: v_bitop3_b32 lane operations, 128-bit LDS
+reads, HBM copy), the CPU oracle timed on a bounded row sample of the same products on all
+host threads and on one (its rows are also compared bit-exactly with the GPU product), and
+sections for the other workloads:
   c1       F_3 512^3: per-product latency p50/p99 and the oracle's time for the product
   c2_k     the 8192^3 products with the slab width k swept 4..10 (each bit-exact)
   mfma     comparison only: the same 8192^3 products as exact int8 matrix-core GEMMs
            (torch._int_mm, int32 accumulation) reduced mod p, checked against this path
   c3       F_7 and GF(4), A 16384 x 2048 times B 2048 x 16384, dense and 10% density
+  ext      GF(8) and F_9 products (row-wise and matrix-level routes)
+  sw       Strassen-Winograd levels over the product
   c4       4096 products of mixed fields and log-uniform shapes: one batched launch
-           (captured in a HIP graph) against one plain launch per product
+           (captured in a HIP graph) against one plain launch per product; every product
+           against the oracle
   c5       served requests with Poisson arrivals: continuous batching against serial
-           plain launches over the same trace, latency p50/p99 and throughput
+           plain launches over the same trace, latency p50/p99 and throughput; every
+           request with n <= 1024 and 2% of the others against the oracle, Freivalds' check
+           on all
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--only c1,c5] [--c5-requests N]
 """
@@ -35,21 +43,14 @@ sys.path.insert(0, ROOT)
 
 M = L = N = 8192
 FIELDS = (3, 5)
-PEAK_VALU_OPS = 256 * 64 * 2.4e9          # 32-bit VALU lane-operations per second
+# 32-bit VALU lane operations per second: 256 CUs x 128 lanes per clock x 2.4 GHz, the rate
+# behind the published fp32 vector peak (157.3 TFLOP/s = 78.6e12 lane FMAs); the v_bitop3_b32
+# microbenchmark issues 1.62 wave64 instructions per CU and clock, so one per clock (64
+# lanes) would understate it
+PEAK_VALU_OPS = 256 * 128 * 2.4e9
+PEAK_LDS = 256 * 256 * 2.4e9              # LDS bytes per second: 64 banks x 4 B per clock per CU
 PEAK_HBM = 8.0e12
-SECTIONS = ("c1", "c2_k", "mfma", "c3", "ext", "sw", "table1", "c4", "c5")
-
-# The paper's Table 1, its own implementation's column: ms for square n x n products on a
-# 2.6 GHz Opteron (context only; other hardware, not a target).  F_{2^2} and F_{2^3} were
-# computed there through M4RI products over F_2.
-PAPER_TABLE1_MS = {
-    3: {100: 0.032, 500: 1.68, 1000: 12.2, 2500: 199},
-    5: {100: 0.110, 500: 6.47, 1000: 49.4, 2500: 742},
-    7: {100: 0.105, 500: 6.04, 1000: 45.7, 2500: 672},
-    4: {100: 0.091, 500: 1.89, 1000: 9.5, 2500: 132},
-    8: {100: 0.187, 500: 3.85, 1000: 20.6, 2500: 261},
-    9: {100: 0.097, 500: 5.22, 1000: 37.6, 2500: 601},
-}
+SECTIONS = ("c1", "c2_k", "mfma", "c3", "ext", "sw", "c4", "c5")
 
 # Per-unit operation counts of the method on gfx950 (three-input bitwise instructions).
 # A unit is (row of C, slab of k rows of B, 32-column word).  Accumulate: the slab's D
@@ -62,6 +63,11 @@ C_ADD = {3: 4, 4: 2, 5: 8, 7: 11, 8: 3, 9: 8}
 # The paper's two-input operation counts (Sections 4.1 and 4.2) for the same units.
 C_ACC_PAPER = {3: 12, 4: 4, 5: 60, 7: 51}
 C_ADD_PAPER = {3: 6, 4: 2, 5: 20, 7: 17}
+# LDS words per unit: the slab's gathers read D table rows of GP planes per row of C and
+# word; the table holds PT planes per entry.  Row-wise routes (variant 0) and the
+# matrix-level routes of GF(4), GF(8), F_9 (variant 1).
+LDS_GEOM = {(3, 0): (2, 2, 2), (4, 0): (2, 2, 2), (5, 0): (3, 3, 3), (7, 0): (3, 3, 3), (8, 0): (3, 3, 3),
+            (9, 0): (4, 4, 4), (4, 1): (3, 1, 3), (8, 1): (6, 1, 6), (9, 1): (6, 2, 6)}
 
 
 # HBM traffic of the product kernels from rocprofv3 FETCH_SIZE / WRITE_SIZE passes on this
@@ -98,6 +104,67 @@ def algorithmic_ops(q, m, l, n, k, acc, add, fin=None):
     return ops
 
 
+def algorithmic_lds_bytes(q, m, l, n, k, variant=0):
+    """LDS bytes the method moves: every row's gathers for every slab and word, plus every
+    table entry written once per slab and column strip."""
+    D, GP, PT = LDS_GEOM[(q, variant)]
+    S = -(-l // k)
+    W = -(-n // 32)
+    return 4.0 * S * W * (m * D * GP + (1 << k) * PT)
+
+
+def rooflines(q, m, l, n, cfg, product_ms, peaks=None):
+    """VALU and LDS fractions of one product launch: algorithmic work over the launch's time,
+    against the derived peaks (VALU: 256 CUs x 128 lanes x 2.4 GHz; LDS: 256 B per clock per
+    CU) and, where measured in this run, the microbenchmarked ones."""
+    dur = product_ms * 1e-3
+    variant = cfg.get("variant", 0)
+    ops = algorithmic_ops(q, m, l, n, cfg["k"], C_ACC, C_ADD) if variant == 0 else None
+    lds = algorithmic_lds_bytes(q, m, l, n, cfg["k"], variant)
+    r = {"lds_TBps": round(lds / dur / 1e12, 3), "lds_frac_of_spec": round(lds / dur / PEAK_LDS, 4)}
+    if ops is not None:
+        r["alu_frac"] = round(ops / dur / PEAK_VALU_OPS, 4)
+    if peaks:
+        if ops is not None:
+            r["alu_frac_of_measured"] = round(ops / dur / peaks["valu_lane_ops_per_s"], 4)
+        r["lds_frac_of_measured"] = round(lds / dur / peaks["lds_bytes_per_s"], 4)
+    return r
+
+
+def rooflines_extra(q, m, l, n, cfg, product_ms, ctx):
+    r = rooflines(q, m, l, n, cfg, product_ms, getattr(ctx, "peaks", None))
+    r.pop("alu_frac", None)                     # the entry's frac
+    return r
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def section_peaks(ctx, reps=3):
+    """Microbenchmarked machine rates (gfq_probe_*): best of reps runs each."""
+    gfq = ctx.gfq
+    best = {}
+    for kind, kw in (("valu", {"blocks": 2048, "iters": 4096}), ("lds", {"blocks": 2048, "iters": 256}),
+                     ("copy", {"nbytes": 1 << 30})):
+        gfq.probe(kind, **kw)                       # warm-up
+        best[kind] = max(gfq.probe(kind, **kw)["rate"] for _ in range(reps))
+    clk_cu = 2.4e9 * 256
+    return {"valu_lane_ops_per_s": best["valu"], "valu_frac_of_derived": round(best["valu"] / PEAK_VALU_OPS, 4),
+            "lds_bytes_per_s": best["lds"], "lds_bytes_per_clk_per_cu": round(best["lds"] / clk_cu, 1),
+            "hbm_copy_bytes_per_s": best["copy"], "hbm_frac_of_8TBps": round(best["copy"] / PEAK_HBM, 4),
+            "derived": {"valu_lane_ops_per_s": PEAK_VALU_OPS, "lds_bytes_per_s": PEAK_LDS, "hbm_bytes_per_s": PEAK_HBM},
+            "probes": "v_bitop3_b32 in 17 independent chains per lane; 128-bit LDS reads, each 16-lane group one "
+                      "256-byte row (the gathers' shape); 128-bit device copy of 1 GiB (reads + writes)"}
+
+
 def percentile(xs, p):
     xs = sorted(xs)
     if not xs:
@@ -123,9 +190,10 @@ class Ctx:
         return [self.torch.cuda.Event(enable_timing=True) for _ in range(n)]
 
 
-def cpu_baseline(ctx, data, seconds=10.0):
-    """Time the oracle on the first rows of A for each field (about `seconds` in total) and
-    compare those rows with the GPU product."""
+def cpu_baseline(ctx, data, seconds=10.0, single_thread_seconds=2.0):
+    """Time the oracle on the first rows of A for each field (about `seconds` in total, all
+    host threads) and compare those rows with the GPU product; then on one thread, on the
+    last rows (about `single_thread_seconds`)."""
     import numpy as np
     oracle = ctx.oracle
     per_field = seconds / len(FIELDS)
@@ -146,6 +214,21 @@ def cpu_baseline(ctx, data, seconds=10.0):
             chunk = min(1024, chunk * 2)
         total_t += t_used
         rows_done[q] = r0
+    # one thread: blocks of 8 rows from the end of A
+    one_ops, one_t, one_rows = 0.0, 0.0, {}
+    for q in FIELDS:
+        A, B, Cgpu = data[q]["A"], data[q]["B"], data[q]["C_host"]
+        r1, t_used = M, 0.0
+        while t_used < single_thread_seconds / len(FIELDS) and r1 > 0:
+            r0 = max(0, r1 - 8)
+            t0 = time.perf_counter()
+            Cs = oracle.matmul(q, A[r0:r1], B, threads=1)
+            t_used += time.perf_counter() - t0
+            one_ops += 2.0 * (r1 - r0) * L * N
+            match = match and bool(np.array_equal(Cs, Cgpu[r0:r1]))
+            r1 = r0
+        one_t += t_used
+        one_rows[q] = M - r1
     return {
         "value": total_ops / total_t,
         "unit": "field-ops/s",
@@ -153,6 +236,10 @@ def cpu_baseline(ctx, data, seconds=10.0):
         "kind": "oracle",
         "sample": ", ".join(f"F_{q}: rows 0..{rows_done[q] - 1} of A times all of B" for q in FIELDS)
                   + "; schoolbook i-t-j loop, int32 accumulation, OpenMP over rows",
+        "cpu_model": cpu_model(),
+        "single_thread": {"value": one_ops / one_t, "unit": "field-ops/s", "threads": 1,
+                          "sample": ", ".join(f"F_{q}: the last {one_rows[q]} rows of A times all of B"
+                                              for q in FIELDS)},
         "sample_rows_match_gpu": match,
     }
 
@@ -238,12 +325,18 @@ def headline(ctx, args):
             "achieved": round(ach / 1e12, 3), "peak": round(PEAK_VALU_OPS / 1e12, 3), "unit": "Tops/s",
             "frac": round(ach / PEAK_VALU_OPS, 4),
             "traffic": (round((tr["read_mib"] + tr["write_mib"]) * 2 ** 20) if tr.get("src") == src_hash else None),
+            "algorithmic_hbm_bytes": (M * L + L * N + M * N) * {3: 2, 5: 3}[q] // 8,
             "avg_ms": round(kernel_ms[q]["product_ms"], 4),
             "partial_sum_ms": round(kernel_ms[q]["reduce_ms"], 4),
-            "paper_op_frac": round(ops_paper / dur / PEAK_VALU_OPS, 4),
+            # the paper's two-input operation count over the same time, per issued lane
+            # instruction of the peak: one three-input instruction does up to two of them, so
+            # this ratio is no roofline fraction and may exceed 1
+            "paper_two_input_ops_per_peak_instruction": round(ops_paper / dur / PEAK_VALU_OPS, 4),
+            **rooflines_extra(q, M, L, N, c, kernel_ms[q]["product_ms"], ctx),
             "config": c,
         })
     dominant = max(rooflines, key=lambda r: r["avg_ms"])
+    f3 = next(r for r in rooflines if r["kernel"] == "m4rm_kernel<F_3>")
     out = {
         "metric": "GF(q) matmul field-ops/s (2mln/t) batched vs plain, 1 MI355X; p99 latency",
         "value": value,
@@ -262,6 +355,7 @@ def headline(ctx, args):
                    "fields": list(FIELDS), "m": M, "l": L, "n": N,
                    "kernel_config": {f"F_{q}": data[q]["cfg"] for q in FIELDS}},
         "roofline": {k: dominant[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
+        "roofline_F_3": {k: f3[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
         "roofline_kernels": rooflines,
         "latency_per_product": lat,
     }
@@ -357,10 +451,10 @@ def section_c2_k(ctx, data, reps=3):
             gfq.set_timing(False)
             pm = t["product_ms"] / t["product_launches"]
             rm = (t["reduce_ms"] / t["reduce_launches"]) if t["reduce_launches"] else 0.0
-            ops = algorithmic_ops(q, M, L, N, k, C_ACC, C_ADD)
             rows.append({"k": k, "product_ms": round(pm, 4), "partial_sum_ms": round(rm, 4),
                          "field_ops_per_s": 2.0 * M * L * N / ((pm + rm) * 1e-3),
-                         "alu_frac": round(ops / (pm * 1e-3) / PEAK_VALU_OPS, 4), "bit_exact": same})
+                         **rooflines(q, M, L, N, {"k": k, "variant": 0}, pm, getattr(ctx, "peaks", None)),
+                         "bit_exact": same})
         out[f"F_{q}"] = rows
     return out
 
@@ -475,8 +569,10 @@ def section_c3(ctx, reps=3, sample_rows=32):
             cfg = gfq.choose_config(q, m, l, n)
             rows = np.sort(inputs.rng(3, q, 3).choice(m, size=sample_rows, replace=False))
             got = Cd[torch.from_numpy(rows).to(ctx.dev)].cpu().numpy()
-            ok = bool(np.array_equal(got, ctx.oracle.matmul(q, A[rows], B)))
-            ops = algorithmic_ops(q, m, l, n, cfg["k"], C_ACC, C_ADD)
+            t0 = time.perf_counter()
+            want = ctx.oracle.matmul(q, A[rows], B)
+            oracle_s = time.perf_counter() - t0
+            ok = bool(np.array_equal(got, want))
             # comparison only: the same product as int8 matrix-core GEMMs
             A8, B8 = Ad.view(torch.int8), Bd.view(torch.int8)
             C8 = int8_product(torch, q, A8, B8)
@@ -517,8 +613,13 @@ def section_c3(ctx, reps=3, sample_rows=32):
             res[name] = {"path_ms": round(path_ms, 4), "product_ms": round(pm, 4), "partial_sum_ms": round(rm, 4),
                          "field_ops_per_s_path": 2.0 * m * l * n / (path_ms * 1e-3),
                          "field_ops_per_s_product": 2.0 * m * l * n / ((pm + rm) * 1e-3),
-                         "alu_frac": round(ops / (pm * 1e-3) / PEAK_VALU_OPS, 4), "config": cfg,
+                         **rooflines(q, m, l, n, cfg, pm, getattr(ctx, "peaks", None)),
+                         # GF(4)'s accumulate is three XORs per unit against 16 bytes of table
+                         # reads: its bound is the LDS port, F_7's the VALU
+                         "bound": "lds" if q == 4 else "alu", "config": cfg,
                          "sampled_rows_bit_exact": ok, "sampled_rows": sample_rows,
+                         "oracle_field_ops_per_s": 2.0 * sample_rows * l * n / oracle_s,
+                         "oracle_threads": ctx.oracle.max_threads(),
                          "int8_mfma_comparison_ms": round(mfma_ms, 4), "int8_mfma_equals": same8}
             if kara is not None:
                 res[name]["karatsuba_variant"] = kara
@@ -557,7 +658,6 @@ def section_ext(ctx, reps=3, sample_rows=32):
         rows = np.sort(inputs.rng(6, m, 3).choice(m, size=sample_rows, replace=False))
         got = Cd[torch.from_numpy(rows).to(ctx.dev)].cpu().numpy()
         ok = bool(np.array_equal(got, ctx.oracle.matmul(q, A[rows], B)))
-        ops = algorithmic_ops(q, m, l, n, cfg["k"], C_ACC, C_ADD)
         A8, B8 = Ad.view(torch.int8), Bd.view(torch.int8)
         same8 = bool(torch.equal(int8_product(torch, q, A8, B8), Cd))
         ev = ctx.events(2)
@@ -589,7 +689,7 @@ def section_ext(ctx, reps=3, sample_rows=32):
         name = ("GF8_" if q == 8 else "F9_") + f"{m}x{l}x{n}" + ("" if density == 1.0 else "_density0.1")
         res[name] = {"product_ms": round(pm, 4), "partial_sum_ms": round(rm, 4),
                      "field_ops_per_s_product": 2.0 * m * l * n / ((pm + rm) * 1e-3),
-                     "alu_frac": round(ops / (pm * 1e-3) / PEAK_VALU_OPS, 4), "config": cfg,
+                     **rooflines(q, m, l, n, cfg, pm, getattr(ctx, "peaks", None)), "config": cfg,
                      "sampled_rows_bit_exact": ok, "sampled_rows": sample_rows,
                      "int8_mfma_comparison_ms": round(mfma_ms, 4), "int8_mfma_equals": same8,
                      "matrix_route": best}
@@ -650,42 +750,7 @@ def section_sw(ctx, reps=5, sizes=(8192, 16384), fields=(3, 5, 4, 8), max_levels
 
 
 # ------------------------------------------------------------------------------------
-# table1: the paper's Table 1 shapes (square n = 100 .. 2500, six fields), for context
-# ------------------------------------------------------------------------------------
-
-def section_table1(ctx, reps=20):
-    import numpy as np
-    torch, gfq, inputs = ctx.torch, ctx.gfq, ctx.inputs
-    res = {}
-    for q, row in PAPER_TABLE1_MS.items():
-        out = {}
-        for n, paper_ms in row.items():
-            A, B = inputs.pair(q, n, n, n, cfg=8, idx=q * 10000 + n)
-            Ap, Bp = gfq.pack(q, ctx.up(A)), gfq.pack(q, ctx.up(B))
-            Cp = gfq.empty_packed(q, n, n)
-            gfq.matmul(q, Ap, Bp, n, n, n, out=Cp)
-            torch.cuda.synchronize()
-            C = gfq.unpack(q, Cp, n, n).cpu().numpy()
-            rows = np.arange(n) if n <= 1000 else np.arange(0, n, 7)
-            ok = bool(np.array_equal(C[rows], ctx.oracle.matmul(q, A[rows], B)))
-            ev = ctx.events(2)
-            ev[0].record()
-            for _ in range(reps):
-                gfq.matmul(q, Ap, Bp, n, n, n, out=Cp)
-            ev[1].record()
-            torch.cuda.synchronize()
-            ms = ev[0].elapsed_time(ev[1]) / reps
-            out[str(n)] = {"product_ms": round(ms, 4), "field_ops_per_s": 2.0 * n ** 3 / (ms * 1e-3),
-                           "paper_opteron_ms": paper_ms, "bit_exact_vs_oracle": ok,
-                           "rows_checked": "all" if n <= 1000 else "every 7th"}
-        res[("GF" if q in (4, 8) else "F_") + str(q)] = out
-    return {"workload": "square n x n products as in the paper's Table 1, uniform entries, one product per "
-                        "launch (tuned configuration); paper_opteron_ms is the paper's own column (2.6 GHz "
-                        "Opteron), context only", **res}
-
-
-# ------------------------------------------------------------------------------------
-# c4: 4096 products of mixed fields and shapes, batched vs plain
+# c4: 4096 products of mixed fields and shapes, batched against plain launches
 # ------------------------------------------------------------------------------------
 
 def section_c4(ctx, count=4096, reps=5, pool=2048):
@@ -745,14 +810,24 @@ def section_c4(ctx, count=4096, reps=5, pool=2048):
     plain_ms = ev[0].elapsed_time(ev[1]) / reps
     same = all(torch.equal(C[:gfq.packed_bytes(q, m, n)], C2[:gfq.packed_bytes(q, m, n)])
                for (q, m, l, n, _, _, C), C2 in zip(probs, plain_out))
-    # oracle on a seeded sample of the products
-    pick = inputs.rng(4, 2, 2).choice(count, size=8, replace=False)
-    ok = True
-    for i in pick:
+    # the method's work per product at the slab width the batch gave it: the batch's VALU
+    # fraction over the replay time
+    ks = b.slab_widths()
+    batch_ops = sum(algorithmic_ops(q, m, l, n, k, C_ACC, C_ADD) for (q, m, l, n), k in zip(specs, ks))
+    # every product against the oracle (timed: the oracle's rate on this workload)
+    ok, oracle_s = True, 0.0
+    t_log = time.monotonic() + 10.0
+    for i in range(count):
+        if time.monotonic() > t_log:
+            log(f"c4 check: oracle {i} of {count}")
+            t_log += 10.0
         q, m, l, n = specs[i]
         ra, ca, rb, cb = offs[i]
+        got = gfq.unpack(q, probs[i][6], m, n).cpu().numpy()
+        t0 = time.perf_counter()
         want = ctx.oracle.matmul(q, pools_h[q][0][ra:ra + m, ca:ca + l], pools_h[q][1][rb:rb + l, cb:cb + n])
-        ok = ok and bool(np.array_equal(gfq.unpack(q, probs[i][6], m, n).cpu().numpy(), want))
+        oracle_s += time.perf_counter() - t0
+        ok = ok and bool(np.array_equal(got, want))
     del graph
     b.destroy()
     return {"workload": f"{count} products, field uniform over F_3/F_5/F_7, m, l, n log-uniform in [64, 2048], "
@@ -764,7 +839,9 @@ def section_c4(ctx, count=4096, reps=5, pool=2048):
             "speedup": round(plain_ms / batched_ms, 2),
             "completion_p50_us": round(percentile(done_us, 50), 1),
             "completion_p99_us": round(percentile(done_us, 99), 1),
-            "batched_equals_plain": same, "oracle_sample_bit_exact": ok,
+            "batched_alu_frac": round(batch_ops / (batched_ms * 1e-3) / PEAK_VALU_OPS, 4),
+            "batched_equals_plain": same, "oracle_all_bit_exact": ok, "oracle_checked": count,
+            "oracle_field_ops_per_s": ops / oracle_s, "oracle_threads": ctx.oracle.max_threads(),
             "tuned_classes_used": ctx.tuned}
 
 
@@ -848,17 +925,8 @@ def section_c5(ctx, count=20000, budget=200 * 10 ** 9, pool=4096, load=0.8):
     srv.destroy()
     torch.cuda.synchronize()
     identical = bool(torch.equal(outs[0], outs[1]))
-    # oracle on a seeded sample of the smaller requests
-    small = [i for i, (_, _, n) in enumerate(trace) if n <= 512]
-    pick = inputs.rng(5, 2, 2).choice(len(small), size=min(16, len(small)), replace=False)
-    ok = True
-    for j in pick:
-        i = small[j]
-        _, q, n = trace[i]
-        ra, ca, rb, cb = offs[i]
-        want = ctx.oracle.matmul(q, pools_h[q][0][ra:ra + n, ca:ca + n], pools_h[q][1][rb:rb + n, cb:cb + n])
-        got = outs[0][int(starts[i]):int(starts[i]) + n * n].view(n, n).cpu().numpy()
-        ok = ok and bool(np.array_equal(got, want))
+    del outs[1]
+    check = c5_check(ctx, trace, offs, pools_h, outs[0], starts)
     del outs
     return {"workload": f"{count} requests, field uniform over {{3,4,5,7}}, square n log-uniform in [128, 4096], "
                         f"Poisson arrivals at {load} x the measured capacity; operands uniform windows of seeded "
@@ -866,7 +934,65 @@ def section_c5(ctx, count=20000, budget=200 * 10 ** 9, pool=4096, load=0.8):
             "budget_bytes": budget, "capacity_req_per_s": round(mu, 1), "offered_req_per_s": round(lam, 1),
             "continuous_batching": served, "serial_plain": serial,
             "p99_ratio_serial_over_batched": round(serial["latency_p99_ms"] / served["latency_p99_ms"], 2),
-            "results_identical_batched_vs_serial": identical, "oracle_sample_bit_exact": ok}
+            "results_identical_batched_vs_serial": identical, **check}
+
+
+def c5_check(ctx, trace, offs, pools_h, out, starts, vectors=8):
+    """The served products against the oracle: every request with n <= 1024 and a seeded 2%
+    of the larger ones in full, and every request by Freivalds' check, C X = A (B X) for
+    `vectors` random columns X over the field (a wrong C passes with probability at most
+    q^-vectors).  C X is formed from the served C in device memory (float64 products of
+    exact integers, reduced in the field); A (B X) by the oracle on the host."""
+    import numpy as np
+    torch, inputs, oracle = ctx.torch, ctx.inputs, ctx.oracle
+    big = [i for i, (_, _, n) in enumerate(trace) if n > 1024]
+    pick = inputs.rng(5, 2, 2).choice(len(big), size=max(1, len(big) // 50), replace=False) if big else []
+    full = sorted([i for i, (_, _, n) in enumerate(trace) if n <= 1024] + [big[j] for j in pick])
+    ok_full, full_ops, full_s = True, 0.0, 0.0
+    t_log = time.monotonic() + 10.0
+    for done, i in enumerate(full):
+        if time.monotonic() > t_log:
+            log(f"c5 check: oracle {done} of {len(full)}")
+            t_log += 10.0
+        _, q, n = trace[i]
+        ra, ca, rb, cb = offs[i]
+        got = out[int(starts[i]):int(starts[i]) + n * n].view(n, n).cpu().numpy()
+        t0 = time.perf_counter()
+        want = oracle.matmul(q, pools_h[q][0][ra:ra + n, ca:ca + n], pools_h[q][1][rb:rb + n, cb:cb + n])
+        full_s += time.perf_counter() - t0
+        full_ops += 2.0 * n ** 3
+        ok_full = ok_full and bool(np.array_equal(got, want))
+
+    def cx_on_device(q, C, X):
+        Xd = torch.from_numpy(X).to(C.device).double()
+        if q != 4:
+            return torch.remainder(C.double() @ Xd, q).to(torch.uint8).cpu().numpy()
+        c0, c1 = (C & 1).double(), (C >> 1).double()
+        x0, x1 = torch.remainder(Xd, 2), torch.div(Xd, 2, rounding_mode="floor")
+        y0 = torch.remainder(c0 @ x0 + c1 @ x1, 2)                 # x^2 = x + 1
+        y1 = torch.remainder(c0 @ x1 + c1 @ x0 + c1 @ x1, 2)
+        return (y0 + 2 * y1).to(torch.uint8).cpu().numpy()
+
+    # A (B X) as the transpose of X^T B^T A^T (the fields are commutative): rows as long as
+    # the matrices, so the oracle's inner loop runs over n columns, not over the vectors;
+    # the operand windows come from the transposed pools
+    pools_t = {q: (np.ascontiguousarray(a.T), np.ascontiguousarray(b.T)) for q, (a, b) in pools_h.items()}
+    ok_fr = True
+    for i, (_, q, n) in enumerate(trace):
+        if time.monotonic() > t_log:
+            log(f"c5 check: Freivalds {i} of {len(trace)}")
+            t_log += 10.0
+        ra, ca, rb, cb = offs[i]
+        X = inputs.rng(5, 3, i).integers(0, q, size=(n, vectors), dtype=np.uint8)
+        C = out[int(starts[i]):int(starts[i]) + n * n].view(n, n)
+        lhs = cx_on_device(q, C, X)
+        At, Bt = pools_t[q][0][ca:ca + n, ra:ra + n], pools_t[q][1][cb:cb + n, rb:rb + n]
+        rhs = oracle.matmul(q, oracle.matmul(q, np.ascontiguousarray(X.T), Bt), At).T
+        ok_fr = ok_fr and bool(np.array_equal(lhs, rhs))
+    return {"oracle_full_checked": len(full), "oracle_full_bit_exact": ok_full,
+            "oracle_full_rule": "every request with n <= 1024 and a seeded 2% of the larger ones",
+            "oracle_field_ops_per_s": full_ops / full_s, "oracle_threads": oracle.max_threads(),
+            "freivalds_checked": len(trace), "freivalds_vectors": vectors, "freivalds_all_pass": ok_fr}
 
 
 def main():
@@ -909,9 +1035,12 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    log("machine peaks")
+    ctx.peaks = section_peaks(ctx)
     log("headline")
     out, data = headline(ctx, args)
     out["tuning_cache_loaded"] = ctx.tuned
+    out["machine_peaks"] = ctx.peaks
     sections = [s for s in args.only.split(",") if s]
     res = {}
     for s in sections:
@@ -945,9 +1074,6 @@ def main():
         log("sw")
         res["sw"] = section_sw(ctx)
         torch.cuda.empty_cache()
-    if "table1" in sections:
-        log("table1")
-        res["table1"] = section_table1(ctx)
     if "c4" in sections:
         log("c4")
         res["c4"] = section_c4(ctx)

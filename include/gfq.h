@@ -218,6 +218,9 @@ typedef struct gfq_batch gfq_batch;
 int gfq_batch_create(int count, const gfq_problem *problems, gfq_batch **out);
 int gfq_batch_launch(gfq_batch *batch);
 int gfq_batch_times(gfq_batch *batch, double *completion_us);
+/* The slab width k the batch gives each product (host array of count ints; the work the
+ * method does per product, Section 2, depends on it). */
+int gfq_batch_slab_widths(const gfq_batch *batch, int *k);
 int gfq_batch_destroy(gfq_batch *batch);
 
 /* Autotuning.  gfq_tune times candidate configurations on scratch operands of the given
@@ -369,6 +372,23 @@ const char *gfq_strerror(int status);
 
 /* Most recent HIP error text seen by this thread (empty if none). */
 const char *gfq_last_hip_error(void);
+
+/* Measurement helpers (no part of the paper's method): the machine rates that the product
+ * kernels' roofline fractions are quoted against, each run once and timed with HIP events on
+ * the calling thread's stream (the call waits for it).
+ * gfq_probe_valu: blocks workgroups of 512 lanes, each lane iters x 17 dependent-free
+ *   v_bitop3_b32 instructions (the product's only arithmetic); *lane_ops = total lane
+ *   operations.  sink: device scratch of blocks x 512 words (written only by a value no
+ *   run produces).
+ * gfq_probe_lds: blocks workgroups of 512 lanes reading 128-bit LDS words, every 16-lane group
+ *   one 256-byte row per read (the access shape of the product's gathers), iters x 16 reads
+ *   per lane; *bytes = total bytes read.  sink as above.
+ * gfq_probe_copy: copies bytes (a multiple of 16, 16-byte aligned device buffers) in 128-bit
+ *   words; HBM traffic is 2 x bytes.
+ * Return GFQ_EINVAL for bad arguments, GFQ_EHIP for a failed launch. */
+int gfq_probe_valu(int blocks, int iters, uint32_t *sink, double *lane_ops, float *ms);
+int gfq_probe_lds(int blocks, int iters, uint32_t *sink, double *bytes, float *ms);
+int gfq_probe_copy(const void *src, void *dst, size_t bytes, float *ms);
 
 #ifdef __cplusplus
 }

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgfq.so")
 SOURCES = ["gfq_m4rm_gf4.hip", "gfq_m4rm_gf8.hip", "gfq_m4rm_f9.hip", "gfq_m4rm_f5.hip", "gfq_m4rm_f7.hip",
-           "gfq_m4rm_f3.hip", "gfq_m4rm.hip", "gfq_batch.hip", "gfq_pack.hip", "gfq_sw.hip", "gfq_noalloc.hip", "gfq_api.cpp", "gfq_batch_host.cpp", "gfq_tune.cpp",
+           "gfq_m4rm_f3.hip", "gfq_m4rm.hip", "gfq_batch.hip", "gfq_pack.hip", "gfq_sw.hip", "gfq_noalloc.hip", "gfq_probe.hip", "gfq_api.cpp", "gfq_batch_host.cpp", "gfq_tune.cpp",
            "gfq_server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS_CC = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

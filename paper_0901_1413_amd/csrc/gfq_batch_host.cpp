@@ -194,6 +194,7 @@ struct gfq_batch {
     BatchItem *items = nullptr;
     u32 *prod_done = nullptr;
     unsigned long long *times = nullptr;   // [0] start, [1 + p] completion of product p
+    std::vector<int> k;                    // slab width of each product
 };
 
 static void batch_release(gfq_batch *b) {
@@ -223,6 +224,8 @@ int gfq::batch_create_with(int count, const gfq_problem *problems, const gfq_con
     std::vector<BatchProd> prods(std::max(count, 1));
     size_t nitems = 0;
     plan_batch(count, problems, cfgs, prods.data(), &b->groups, &nitems);
+    b->k.resize(count);
+    for (int i = 0; i < count; i++) b->k[i] = prods[i].a.k;
 
     // one allocation: products | items | tile counts | times
     auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
@@ -275,6 +278,12 @@ int gfq_batch_times(gfq_batch *b, double *completion_us) {
     if (e != hipSuccess) return hip_fail(e, "batch times");
     for (int p = 0; p < b->count; p++)
         completion_us[p] = t[1 + p] >= t[0] ? (double)(t[1 + p] - t[0]) * 0.01 : 0.0;   // 100 MHz ticks
+    return GFQ_OK;
+}
+
+int gfq_batch_slab_widths(const gfq_batch *b, int *k) {
+    if (!b || !k) return GFQ_ENULL;
+    std::copy(b->k.begin(), b->k.end(), k);
     return GFQ_OK;
 }
 

@@ -80,6 +80,7 @@ _SIGS = {
     "gfq_batch_launch": (ctypes.c_int, [_VP]),
     "gfq_batch_times": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double)]),
     "gfq_batch_destroy": (ctypes.c_int, [_VP]),
+    "gfq_batch_slab_widths": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int)]),
     "gfq_tune": (ctypes.c_int, [ctypes.c_int, _I64, _I64, _I64, ctypes.c_int, ctypes.POINTER(Config)]),
     "gfq_tune_lookup": (ctypes.c_int, [ctypes.c_int, _I64, _I64, _I64, ctypes.c_int, ctypes.POINTER(Config)]),
     "gfq_tune_save": (ctypes.c_int, [ctypes.c_char_p]),
@@ -97,6 +98,11 @@ _SIGS = {
     "gfq_set_timing": (ctypes.c_int, [ctypes.c_int]),
     "gfq_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]),
+    "gfq_probe_valu": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _VP, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_float)]),
+    "gfq_probe_lds": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _VP, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_float)]),
+    "gfq_probe_copy": (ctypes.c_int, [_VP, _VP, ctypes.c_size_t, ctypes.POINTER(ctypes.c_float)]),
     "gfq_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "gfq_last_hip_error": (ctypes.c_char_p, []),
 }
@@ -299,6 +305,12 @@ class Batch:
         _check(load().gfq_batch_times(self.handle, out), "gfq_batch_times")
         return list(out)[: self.count]
 
+    def slab_widths(self):
+        """The slab width k the batch gives each product."""
+        out = (ctypes.c_int * max(1, self.count))()
+        _check(load().gfq_batch_slab_widths(self.handle, out), "gfq_batch_slab_widths")
+        return list(out)[: self.count]
+
     def destroy(self):
         if self.handle:
             _check(load().gfq_batch_destroy(self.handle), "gfq_batch_destroy")
@@ -367,6 +379,28 @@ def timing_read() -> dict:
            "gfq_timing_read")
     return {"product_ms": pm.value, "product_launches": pc.value, "reduce_ms": rm.value,
             "reduce_launches": rc.value}
+
+
+def probe(kind: str, blocks: int = 2048, iters: int = 4096, nbytes: int = 1 << 30) -> dict:
+    """Machine-rate microbenchmarks (gfq_probe_*): kind "valu" (lane operations per second of
+    v_bitop3_b32), "lds" (128-bit LDS read bytes per second), "copy" (HBM bytes per second of
+    a device copy, reads plus writes)."""
+    import torch
+    _bind_stream()
+    ms = ctypes.c_float()
+    amount = ctypes.c_double()
+    if kind in ("valu", "lds"):
+        sink = torch.empty(blocks * 512, dtype=torch.int32, device="cuda")
+        fn = load().gfq_probe_valu if kind == "valu" else load().gfq_probe_lds
+        _check(fn(blocks, iters, _VP(sink.data_ptr()), ctypes.byref(amount), ctypes.byref(ms)), f"gfq_probe_{kind}")
+        return {"amount": amount.value, "ms": ms.value, "rate": amount.value / (ms.value * 1e-3)}
+    if kind == "copy":
+        src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        _check(load().gfq_probe_copy(_VP(src.data_ptr()), _VP(dst.data_ptr()), nbytes, ctypes.byref(ms)),
+               "gfq_probe_copy")
+        return {"amount": 2.0 * nbytes, "ms": ms.value, "rate": 2.0 * nbytes / (ms.value * 1e-3)}
+    raise ValueError(kind)
 
 
 def sync():

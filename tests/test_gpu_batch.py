@@ -1,5 +1,7 @@
-"""Batched persistent launches: every product of a mixed batch against the oracle and
-against the same product launched alone (bit-exact), graph replays, degenerate products."""
+"""Batched products (one work-list launch per field and tile shape, workgroups taking
+(product, row tile, column tile) items longest first): every product of a mixed batch
+against the oracle and against the same product launched alone (bit-exact), graph replays,
+degenerate products."""
 import numpy as np
 import pytest
 

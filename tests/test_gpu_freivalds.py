@@ -3,8 +3,9 @@
 Freivalds: for random X (n x 32 over F_q), C = A B implies C X = A (B X).  The three
 products with X are computed by the oracle (32 columns are cheap at any size), C by the HIP
 path.  A wrong C passes with probability at most q^-32 per product.  The shapes are the
-benchmark's: 8192^3 (F_3, F_5; GF(8), F_9) and 16384 x 2048 x 16384 (F_7, GF(4)), plus a
-two-level Strassen-Winograd product."""
+benchmark's: 8192^3 (F_3, F_5; GF(8), F_9) and 16384 x 2048 x 16384 (F_7, GF(4); dense and
+10% density; and every field in the shipped table's configuration), plus a two-level
+Strassen-Winograd product."""
 import numpy as np
 import pytest
 
@@ -45,6 +46,36 @@ def test_full_size_freivalds(gfq_gpu, q, shape):
     # the check catches one wrong element (a planted error, on the CPU copy)
     C[m // 3, n // 2] = (C[m // 3, n // 2] + 1) % q
     assert not freivalds(q, A, B, C, seed=q)
+
+
+@pytest.mark.parametrize("q", [7, 4])
+def test_sparse_16384x2048x16384_freivalds(gfq_gpu, q):
+    """The 10%-density variant of the rectangular workload (zero with probability 0.9, else
+    uniform non-zero), every element."""
+    m, l, n = 16384, 2048, 16384
+    A, B = inputs.pair(q, m, l, n, cfg=244, idx=q, density=0.1)
+    C = product(gfq_gpu, q, A, B)
+    assert freivalds(q, A, B, C, seed=300 + q)
+    C[m - 1, 7] = (C[m - 1, 7] + 1) % q
+    assert not freivalds(q, A, B, C, seed=300 + q)
+
+
+@pytest.mark.parametrize("q", [3, 5, 7, 4])
+def test_tuned_16384x2048x16384_freivalds(gfq_gpu, q):
+    """The rectangular workload in the shipped table's configuration for its class."""
+    import os
+    g = gfq_gpu
+    m, l, n = 16384, 2048, 16384
+    table = os.path.join(os.path.dirname(g.__file__), "tuning", "gfx950.txt")
+    g.tune_clear()
+    try:
+        g.tune_load(table)
+        assert g.tune_lookup(q, m, l, n) is not None
+        A, B = inputs.pair(q, m, l, n, cfg=245, idx=q)
+        C = product(g, q, A, B)
+        assert freivalds(q, A, B, C, seed=400 + q)
+    finally:
+        g.tune_clear()
 
 
 @pytest.mark.parametrize("q", [3, 5])
