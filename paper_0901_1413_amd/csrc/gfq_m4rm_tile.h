@@ -260,7 +260,9 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
     constexpr bool HALF_BUILD = NCH >= 8 && R >= F::HALF_BUILD_ROWS;
     constexpr int LOG_NB = LOG_NCH - (HALF_BUILD ? 1 : 0);     // log2 of the building chunks
     constexpr int NB = 1 << LOG_NB;
-    constexpr int GMAX = KMAX > LOG_NB ? KMAX - LOG_NB : 0;     // longest walk: 2^GMAX entries
+    // the widest slab whose two tables fit 128 KiB at this super-row width
+    constexpr int KT = log2_floor(65536 / (PT * SRB)) < KMAX ? log2_floor(65536 / (PT * SRB)) : KMAX;
+    constexpr int GMAX = KT > LOG_NB ? KT - LOG_NB : 0;         // longest walk: 2^GMAX entries
     constexpr int PFW = NB / 4;                                 // prefix threads per word
     constexpr int PFB = LOG_NB > 2 ? LOG_NB - 2 : 0;           // masked bits per prefix thread
     static_assert(NB >= 4, "four chunks per prefix thread");
