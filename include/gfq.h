@@ -299,6 +299,9 @@ typedef struct {
     int max_batch;       /* requests per batch, 1..4096 (0 = 256; serial mode uses 1)       */
     int max_items;       /* tiles per batch, 32768..1048576 (0 = 65536)                     */
     int mode;            /* GFQ_SERVE_BATCHED or GFQ_SERVE_SERIAL                           */
+    double watchdog_s;   /* a batch not complete this many seconds after its launch fails:   *
+                          * its requests complete with GFQ_EHIP, its slot and arena ranges   *
+                          * are never reused, the server is marked failed (0 = no watchdog) */
 } gfq_server_opts;
 
 #define GFQ_REQ_A_PACKED 1
@@ -317,6 +320,9 @@ typedef struct {
     int flags;              /* GFQ_REQ_* bits                                             */
     uint64_t tag;           /* returned with the completion                               */
     double not_before_us;   /* arrival time on the server clock; 0 = at submission        */
+    void *C_host;           /* NULL, or host memory (pinned for speed) that receives a copy  *
+                             * of the product before the completion is reported: the span of *
+                             * C, (m - 1) ldc + n bytes (packed: gfq_packed_bytes)            */
 } gfq_request;
 
 typedef struct {

@@ -26,12 +26,11 @@
 #include "gfq_host.h"
 #include "gfq_internal.h"
 #include "gfq_sched.h"
+#include "gfq_serve_core.h"
 
 using namespace gfq;
 
 namespace {
-
-typedef std::chrono::steady_clock Clock;
 
 constexpr int64_t kMaxSide = 65535;   // keeps every tile index of a request in 16 bits
 constexpr size_t kNone = ~(size_t)0;
@@ -43,19 +42,8 @@ struct Req {
     double arrival = 0;
     size_t bytes = 0;                  // arena bytes (packed forms the server makes)
     size_t items = 0;                  // tile bound
+    uint64_t tag = 0;
     size_t offA = kNone, offB = kNone, offC = kNone;   // within the arena range
-};
-
-struct Slot {
-    hipStream_t st = nullptr;
-    hipEvent_t ev = nullptr;
-    char *dev = nullptr;               // descriptors (staged part, then counts and times)
-    char *host = nullptr;              // pinned staging mirror of the staged part
-    u32 *done = nullptr;               // per-product tile counts (zero between launches)
-    unsigned long long *times = nullptr;
-    bool busy = false;
-    double launch_us = 0;
-    std::vector<std::pair<Req, uintptr_t>> reqs;
 };
 
 bool overlaps(uintptr_t a, size_t na, uintptr_t b, size_t nb) { return na && nb && a < b + nb && b < a + na; }
@@ -66,64 +54,49 @@ size_t span(int q, int64_t rows, int64_t cols, int64_t ld, bool packed) {
     return packed ? gfq_packed_bytes(q, rows, cols) : (size_t)((rows - 1) * ld + cols);
 }
 
-}  // namespace
+// The device side of the server: one stream, completion event and descriptor buffer (with
+// its pinned staging mirror) per slot.
+struct HipExec {
+    typedef std::vector<std::pair<Req, uintptr_t>> Batch;
+    struct Slot {
+        hipStream_t st = nullptr;
+        hipEvent_t ev = nullptr;
+        char *dev = nullptr;               // descriptors (staged part, then counts and times)
+        char *host = nullptr;              // pinned staging mirror of the staged part
+        u32 *done = nullptr;               // per-product tile counts (zero between launches)
+        unsigned long long *times = nullptr;
+        bool retired = false;              // given up by the watchdog: never waited for or freed
+    };
+    int mode = GFQ_SERVE_BATCHED;
+    size_t staged_cap = 0;
+    std::vector<Slot> sl;
 
-struct gfq_server {
-    gfq_server_opts o{};
-    int device = 0;
-    size_t staged_cap = 0;             // bytes of the staged part of a slot buffer
-    size_t off_done = 0, off_times = 0, slot_bytes = 0;
-    Clock::time_point t0;
-    std::vector<Slot> slots;
-    Arena *arena = nullptr;
-    ArrivalQueue<Req> queue;           // worker only
-
-    std::mutex mu;                     // guards incoming, completions, stop, failed
-    std::condition_variable cv_work, cv_done;
-    std::vector<Req> incoming;
-    std::deque<gfq_completion> completions;
-    bool stop = false;
-    bool failed = false;
-    std::thread worker;
-
-    std::atomic<int64_t> submitted{0}, completed{0}, batches{0}, admitted{0}, max_batch_seen{0};
-    std::atomic<size_t> a_in_use{0}, a_held{0}, a_peak{0};
-
-    double now() const { return std::chrono::duration<double, std::micro>(Clock::now() - t0).count(); }
+    int slots() const { return (int)sl.size(); }
+    int launch(int i, const Batch &b);
+    int poll(int i) {
+        const hipError_t e = hipEventQuery(sl[i].ev);
+        if (e == hipErrorNotReady) return 1;
+        return e == hipSuccess ? 0 : hip_fail(e, "server batch");
+    }
+    void drain(int i) { (void)hipStreamSynchronize(sl[i].st); }
+    void retire(int i) { sl[i].retired = true; }
+    hipError_t copy_to_host(const Req &rq, const void *C, hipStream_t st) const;
+    hipError_t launch_batch(Slot &s, const Batch &b);
+    hipError_t launch_serial(Slot &s, const Batch &b);
 };
 
-namespace {
-
-void complete(gfq_server *s, Slot &sl, int status) {
-    const double t = s->now();
-    std::vector<gfq_completion> out;
-    out.reserve(sl.reqs.size());
-    for (auto &rp : sl.reqs) {
-        s->arena->release(rp.second, rp.first.bytes);
-        gfq_completion c;
-        c.tag = rp.first.r.tag;
-        c.status = status;
-        c.batch_size = (int)sl.reqs.size();
-        c.arrival_us = rp.first.arrival;
-        c.launch_us = sl.launch_us;
-        c.done_us = t;
-        out.push_back(c);
-    }
-    s->a_in_use = s->arena->in_use();
-    sl.reqs.clear();
-    sl.busy = false;
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        for (auto &c : out) s->completions.push_back(c);
-        if (status != GFQ_OK) s->failed = true;
-    }
-    s->completed += (int64_t)out.size();
-    s->cv_done.notify_all();
+// The request's product to its host destination, if it has one: the span of C (uint8 with
+// leading dimension ldc, or packed), after the product is complete on the stream.
+hipError_t HipExec::copy_to_host(const Req &rq, const void *C, hipStream_t st) const {
+    const gfq_request &r = rq.r;
+    if (!r.C_host || r.m <= 0 || r.n <= 0) return hipSuccess;
+    const bool pc = r.flags & GFQ_REQ_C_PACKED;
+    return hipMemcpyAsync(r.C_host, C, span(r.q, r.m, r.n, r.ldc, pc), hipMemcpyDeviceToHost, st);
 }
 
-// Batched mode: stage descriptors and enqueue the launches of one batch on slot sl.
-hipError_t launch_batch(gfq_server *s, Slot &sl) {
-    const int nreq = (int)sl.reqs.size();
+// Batched mode: stage descriptors and enqueue the launches of one batch on slot s.
+hipError_t HipExec::launch_batch(Slot &s, const Batch &b) {
+    const int nreq = (int)b.size();
     std::vector<gfq_problem> probs(nreq);
     std::vector<ConvJob> pack, unpack;
     u32 pack_blocks = 0, unpack_blocks = 0;
@@ -147,9 +120,9 @@ hipError_t launch_batch(gfq_server *s, Slot &sl) {
         v.push_back(j);
     };
     for (int i = 0; i < nreq; i++) {
-        const Req &rq = sl.reqs[i].first;
+        const Req &rq = b[i].first;
         const gfq_request &r = rq.r;
-        char *base = (char *)sl.reqs[i].second;
+        char *base = (char *)b[i].second;
         const void *A = rq.offA != kNone ? base + rq.offA : r.A;
         const void *B = rq.offB != kNone ? base + rq.offB : r.B;
         void *C = rq.offC != kNone ? base + rq.offC : r.C;
@@ -168,40 +141,43 @@ hipError_t launch_batch(gfq_server *s, Slot &sl) {
     const size_t o_prods = o_unpack + rup(sizeof(ConvJob) * unpack.size());
     const size_t o_items = o_prods + rup(sizeof(BatchProd) * nreq);
     const size_t used = o_items + sizeof(BatchItem) * nitems;
-    if (used > s->staged_cap) return hipErrorInvalidValue;   // bounded by the batch limits
-    char *h = sl.host;
+    if (used > staged_cap) return hipErrorInvalidValue;   // bounded by the batch limits
+    char *h = s.host;
     std::memcpy(h, pack.data(), sizeof(ConvJob) * pack.size());
     std::memcpy(h + o_unpack, unpack.data(), sizeof(ConvJob) * unpack.size());
     std::memcpy(h + o_prods, prods.data(), sizeof(BatchProd) * nreq);
     for (const BatchGroup &g : groups)
         std::memcpy(h + o_items + sizeof(BatchItem) * g.item_off, g.items.data(), sizeof(BatchItem) * g.items.size());
-    hipError_t e = hipMemcpyAsync(sl.dev, h, used, hipMemcpyHostToDevice, sl.st);
+    hipError_t e = hipMemcpyAsync(s.dev, h, used, hipMemcpyHostToDevice, s.st);
     if (e == hipSuccess)
-        e = launch_conv_list((const ConvJob *)sl.dev, (int)pack.size(), pack_blocks, sl.st);
+        e = launch_conv_list((const ConvJob *)s.dev, (int)pack.size(), pack_blocks, s.st);
     // the lists run one after another on the slot's stream: the slots already overlap one
     // another's batches, and forking each slot's lists onto side streams (as gfq_batch_launch
     // does) measured slower here (served p99 10.9 -> 13.8 ms)
     for (size_t j = 0; e == hipSuccess && j < groups.size(); j++) {
         BatchList bl;
-        bl.prods = (const BatchProd *)(sl.dev + o_prods);
-        bl.items = (const BatchItem *)(sl.dev + o_items) + groups[j].item_off;
-        bl.prod_done = sl.done;
-        bl.prod_time = sl.times + 1;
+        bl.prods = (const BatchProd *)(s.dev + o_prods);
+        bl.items = (const BatchItem *)(s.dev + o_items) + groups[j].item_off;
+        bl.prod_done = s.done;
+        bl.prod_time = s.times + 1;
         e = launch_batched(groups[j].q, groups[j].R, groups[j].twd, bl, (int)groups[j].items.size(), groups[j].lds,
-                           sl.st);
+                           s.st);
     }
     if (e == hipSuccess)
-        e = launch_conv_list((const ConvJob *)(sl.dev + o_unpack), (int)unpack.size(), unpack_blocks, sl.st);
+        e = launch_conv_list((const ConvJob *)(s.dev + o_unpack), (int)unpack.size(), unpack_blocks, s.st);
+    for (int i = 0; e == hipSuccess && i < nreq; i++) {
+        const Req &rq = b[i].first;
+        e = copy_to_host(rq, rq.offC != kNone ? rq.r.C : probs[i].C, s.st);
+    }
     return e;
 }
 
 // Serial mode: the single-product calls for the slot's one request.
-hipError_t launch_serial(gfq_server *s, Slot &sl) {
-    (void)s;
-    gfq_set_stream(sl.st);
-    const Req &rq = sl.reqs[0].first;
+hipError_t HipExec::launch_serial(Slot &s, const Batch &b) {
+    gfq_set_stream(s.st);
+    const Req &rq = b[0].first;
     const gfq_request &r = rq.r;
-    char *base = (char *)sl.reqs[0].second;
+    char *base = (char *)b[0].second;
     const void *A = rq.offA != kNone ? base + rq.offA : r.A;
     const void *B = rq.offB != kNone ? base + rq.offB : r.B;
     void *C = rq.offC != kNone ? base + rq.offC : r.C;
@@ -210,121 +186,40 @@ hipError_t launch_serial(gfq_server *s, Slot &sl) {
     if (st == GFQ_OK && rq.offB != kNone) st = gfq_pack(r.q, r.l, r.n, (const uint8_t *)r.B, r.ldb, (void *)B);
     if (st == GFQ_OK) st = gfq_matmul(r.q, r.m, r.l, r.n, A, B, C);
     if (st == GFQ_OK && rq.offC != kNone) st = gfq_unpack(r.q, r.m, r.n, C, (uint8_t *)r.C, r.ldc);
-    return st == GFQ_OK ? hipSuccess : hipErrorLaunchFailure;
+    if (st != GFQ_OK) return hipErrorLaunchFailure;
+    return copy_to_host(rq, r.C, s.st);
 }
 
-// Poll the busy slots; returns true if any finished.
-bool reap(gfq_server *s) {
-    bool any = false;
-    for (Slot &sl : s->slots) {
-        if (!sl.busy) continue;
-        const hipError_t e = hipEventQuery(sl.ev);
-        if (e == hipErrorNotReady) continue;
-        if (e != hipSuccess) hip_fail(e, "server batch");
-        complete(s, sl, e == hipSuccess ? GFQ_OK : GFQ_EHIP);
-        any = true;
-    }
-    return any;
+int HipExec::launch(int i, const Batch &b) {
+    Slot &s = sl[i];
+    hipError_t e = mode == GFQ_SERVE_SERIAL ? launch_serial(s, b) : launch_batch(s, b);
+    if (e == hipSuccess) e = hipEventRecord(s.ev, s.st);
+    return e == hipSuccess ? 0 : hip_fail(e, "server launch");
 }
 
-// Admit and launch batches while a slot is free; returns true if anything was launched.
-bool admit(gfq_server *s) {
-    bool any = false;
-    int retries = 0;
-    for (Slot &sl : s->slots) {
-        if (sl.busy) continue;
-        while (true) {
-            const double t = s->now();
-            bool idle = true;
-            for (const Slot &x : s->slots) idle = idle && !x.busy;
-            sl.reqs.clear();
-            const bool ok = admit_batch(s->queue, *s->arena, t, s->o.max_batch, (size_t)s->o.max_items,
-                                        [](const Req &r) { return r.items; }, [](const Req &r) { return r.bytes; },
-                                        &sl.reqs, idle);
-            if (!ok) {
-                // nothing in flight and the head request fits no free extent: start the arena
-                // afresh once; if even that fails, the device has no memory for it
-                if (retries++ == 0) {
-                    s->arena->reset();
-                    s->a_held = 0;
-                    continue;
-                }
-                Req head = s->queue.front();
-                s->queue.pop();
-                s->admitted++;
-                gfq_completion c{head.r.tag, GFQ_ENOMEM, 0, head.arrival, t, t};
-                {
-                    std::lock_guard<std::mutex> lk(s->mu);
-                    s->completions.push_back(c);
-                }
-                s->completed++;
-                s->cv_done.notify_all();
-                retries = 0;
-                continue;
-            }
-            break;
-        }
-        if (sl.reqs.empty()) break;
-        s->admitted += (int64_t)sl.reqs.size();
-        s->a_in_use = s->arena->in_use();
-        s->a_held = s->arena->held();
-        if (s->a_in_use > s->a_peak) s->a_peak = s->a_in_use.load();
-        if ((int64_t)sl.reqs.size() > s->max_batch_seen) s->max_batch_seen = (int64_t)sl.reqs.size();
-        sl.launch_us = s->now();
-        hipError_t e = s->o.mode == GFQ_SERVE_SERIAL ? launch_serial(s, sl) : launch_batch(s, sl);
-        if (e == hipSuccess) e = hipEventRecord(sl.ev, sl.st);
-        s->batches++;
-        sl.busy = true;
-        if (e != hipSuccess) {
-            hip_fail(e, "server launch");
-            (void)hipStreamSynchronize(sl.st);
-            complete(s, sl, GFQ_EHIP);
-        }
-        any = true;
-    }
-    return any;
-}
+}  // namespace
 
-void worker_main(gfq_server *s) {
-    (void)hipSetDevice(s->device);
-    std::unique_lock<std::mutex> lk(s->mu);
-    while (true) {
-        for (Req &r : s->incoming) s->queue.push(r.arrival, r);
-        s->incoming.clear();
-        const bool stopping = s->stop;
-        lk.unlock();
-        bool busy = false;
-        reap(s);
-        if (!stopping) admit(s);
-        for (const Slot &sl : s->slots) busy = busy || sl.busy;
-        const double next = s->queue.next_arrival();
-        lk.lock();
-        if (stopping && !busy) break;
-        if (!s->incoming.empty()) continue;
-        if (busy) {
-            // batches in flight: poll their events closely (completion latency matters)
-            lk.unlock();
-            std::this_thread::yield();
-            lk.lock();
-        } else if (!s->queue.empty() && !stopping) {
-            const double wait = next - s->now();
-            if (wait > 300.0) {
-                s->cv_work.wait_for(lk, std::chrono::microseconds((int64_t)(wait - 150.0)));
-            } else if (wait > 0) {
-                lk.unlock();
-                std::this_thread::yield();
-                lk.lock();
-            }
-        } else if (!stopping) {
-            s->cv_work.wait(lk, [s] { return s->stop || !s->incoming.empty(); });
-        }
-    }
-}
+struct gfq_server {
+    gfq_server_opts o{};
+    int device = 0;
+    HipExec exec;
+    Arena *arena = nullptr;
+    ServeCore<Req, HipExec> *core = nullptr;
+};
+
+namespace {
 
 void server_free(gfq_server *s) {
     if (!s) return;
+    delete s->core;                    // stops the worker
+    // ranges handed out to a retired slot may still be written by the device: the arena's
+    // memory is kept then
+    bool retired = false;
+    for (const HipExec::Slot &x : s->exec.sl) retired = retired || x.retired;
+    if (retired) s->arena = nullptr;
     delete s->arena;
-    for (Slot &sl : s->slots) {
+    for (HipExec::Slot &sl : s->exec.sl) {
+        if (sl.retired) continue;
         if (sl.ev) (void)hipEventDestroy(sl.ev);
         if (sl.st) (void)hipStreamDestroy(sl.st);
         if (sl.dev) (void)hipFree(sl.dev);
@@ -348,7 +243,7 @@ int gfq_server_create(const gfq_server_opts *opts, gfq_server **out) {
     if (o.max_batch == 0) o.max_batch = 256;
     if (o.max_items == 0) o.max_items = 65536;
     if (o.slots < 1 || o.slots > 8 || o.max_batch < 1 || o.max_batch > 4096 || o.max_items < 32768 ||
-        o.max_items > (1 << 20))
+        o.max_items > (1 << 20) || !(o.watchdog_s >= 0.0))
         return GFQ_EINVAL;
     if (o.mode == GFQ_SERVE_SERIAL) {
         o.slots = 1;
@@ -356,26 +251,27 @@ int gfq_server_create(const gfq_server_opts *opts, gfq_server **out) {
     }
     gfq_server *s = new gfq_server();
     s->o = o;
-    s->t0 = Clock::now();
     hipError_t e = hipGetDevice(&s->device);
     if (e == hipSuccess) e = set_batched_lds_limits();
     if (e != hipSuccess) { server_free(s); return hip_fail(e, "server setup"); }
     const size_t mb = (size_t)o.max_batch;
-    s->staged_cap = rup(sizeof(ConvJob) * 2 * mb) + rup(sizeof(ConvJob) * mb) + rup(sizeof(BatchProd) * mb) +
-                    rup(sizeof(BatchItem) * (size_t)o.max_items);
-    s->off_done = s->staged_cap;
-    s->off_times = s->off_done + rup(sizeof(u32) * mb);
-    s->slot_bytes = s->off_times + rup(sizeof(unsigned long long) * (mb + 1));
-    s->slots.resize(o.slots);
-    for (Slot &sl : s->slots) {
+    HipExec &x = s->exec;
+    x.mode = o.mode;
+    x.staged_cap = rup(sizeof(ConvJob) * 2 * mb) + rup(sizeof(ConvJob) * mb) + rup(sizeof(BatchProd) * mb) +
+                   rup(sizeof(BatchItem) * (size_t)o.max_items);
+    const size_t off_done = x.staged_cap;
+    const size_t off_times = off_done + rup(sizeof(u32) * mb);
+    const size_t slot_bytes = off_times + rup(sizeof(unsigned long long) * (mb + 1));
+    x.sl.resize(o.slots);
+    for (HipExec::Slot &sl : x.sl) {
         e = hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipMalloc(&sl.dev, s->slot_bytes);
-        if (e == hipSuccess) e = hipHostMalloc(&sl.host, s->staged_cap, hipHostMallocDefault);
-        if (e == hipSuccess) e = hipMemset(sl.dev, 0, s->slot_bytes);
+        if (e == hipSuccess) e = hipMalloc(&sl.dev, slot_bytes);
+        if (e == hipSuccess) e = hipHostMalloc(&sl.host, x.staged_cap, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipMemset(sl.dev, 0, slot_bytes);
         if (e != hipSuccess) { server_free(s); return hip_fail(e, "server slots"); }
-        sl.done = (u32 *)(sl.dev + s->off_done);
-        sl.times = (unsigned long long *)(sl.dev + s->off_times);
+        sl.done = (u32 *)(sl.dev + off_done);
+        sl.times = (unsigned long long *)(sl.dev + off_times);
     }
     const int dev = s->device;
     s->arena = new Arena(
@@ -388,7 +284,12 @@ int gfq_server_create(const gfq_server_opts *opts, gfq_server **out) {
             return true;
         },
         [](uintptr_t p) { (void)hipFree((void *)p); });
-    s->worker = std::thread(worker_main, s);
+    ServeLimits lim;
+    lim.max_batch = o.max_batch;
+    lim.max_items = (size_t)o.max_items;
+    lim.watchdog_us = o.watchdog_s * 1e6;
+    s->core = new ServeCore<Req, HipExec>(s->exec, *s->arena, lim);
+    s->core->start_on([dev] { (void)hipSetDevice(dev); });
     *out = s;
     return GFQ_OK;
 }
@@ -399,7 +300,7 @@ int gfq_server_submit(gfq_server *s, const gfq_request *reqs, int count) {
     if (count == 0) return GFQ_OK;
     if (!reqs) return GFQ_ENULL;
     std::vector<Req> v(count);
-    const double t = s->now();
+    const double t = s->core->now();
     for (int i = 0; i < count; i++) {
         const gfq_request &r = reqs[i];
         if (!valid_field(r.q)) return GFQ_EFIELD;
@@ -420,6 +321,7 @@ int gfq_server_submit(gfq_server *s, const gfq_request *reqs, int count) {
             return GFQ_EALIAS;
         Req &q = v[i];
         q.r = r;
+        q.tag = r.tag;
         q.arrival = std::max(t, r.not_before_us);
         size_t off = 0;
         if (inner && !pa) { q.offA = off; off += rup(gfq_packed_bytes(r.q, r.m, r.l)); }
@@ -429,61 +331,43 @@ int gfq_server_submit(gfq_server *s, const gfq_request *reqs, int count) {
         q.items = batch_tiles_bound(r.m, r.n);
         if (Arena::round(q.bytes) > s->o.budget_bytes) return GFQ_EBUDGET;
     }
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        if (s->failed) return GFQ_EHIP;
-        for (Req &r : v) s->incoming.push_back(r);
-    }
-    s->submitted += count;
-    s->cv_work.notify_one();
-    return GFQ_OK;
+    return s->core->submit(v) ? GFQ_OK : GFQ_EHIP;
 }
 
 int gfq_server_poll(gfq_server *s, gfq_completion *out, int max, int *got, double timeout_us) {
     if (!s || !got || (max > 0 && !out)) return GFQ_ENULL;
     *got = 0;
     if (max < 0) return GFQ_EINVAL;
-    std::unique_lock<std::mutex> lk(s->mu);
-    if (s->completions.empty() && timeout_us != 0) {
-        auto ready = [s] { return !s->completions.empty(); };
-        if (timeout_us < 0) s->cv_done.wait(lk, ready);
-        else s->cv_done.wait_for(lk, std::chrono::microseconds((int64_t)timeout_us), ready);
-    }
-    int n = 0;
-    while (n < max && !s->completions.empty()) {
-        out[n++] = s->completions.front();
-        s->completions.pop_front();
-    }
+    std::vector<ServeCompletion> c(std::max(max, 1));
+    const int n = s->core->poll(c.data(), max, timeout_us);
+    for (int i = 0; i < n; i++)
+        out[i] = gfq_completion{c[i].tag, c[i].status, c[i].batch_size, c[i].arrival_us, c[i].launch_us, c[i].done_us};
     *got = n;
     return GFQ_OK;
 }
 
-double gfq_server_now_us(const gfq_server *s) { return s ? s->now() : 0.0; }
+double gfq_server_now_us(const gfq_server *s) { return s ? s->core->now() : 0.0; }
 
 int gfq_server_stats_read(const gfq_server *s, gfq_server_stats *out) {
     if (!s || !out) return GFQ_ENULL;
-    out->submitted = s->submitted;
-    out->completed = s->completed;
-    out->batches = s->batches;
-    out->queued = s->submitted - s->admitted;
-    out->max_batch_seen = s->max_batch_seen;
-    out->arena_in_use = s->a_in_use;
-    out->arena_held = s->a_held;
-    out->arena_peak_in_use = s->a_peak;
+    const ServeCore<Req, HipExec> &c = *s->core;
+    out->submitted = c.submitted;
+    out->completed = c.completed;
+    out->batches = c.batches;
+    out->queued = c.submitted - c.admitted;
+    out->max_batch_seen = c.max_batch_seen;
+    out->arena_in_use = c.a_in_use;
+    out->arena_held = c.a_held;
+    out->arena_peak_in_use = c.a_peak;
     return GFQ_OK;
 }
 
 int gfq_server_destroy(gfq_server *s) {
     if (!s) return GFQ_OK;
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        s->stop = true;
-    }
-    s->cv_work.notify_all();
-    if (s->worker.joinable()) s->worker.join();
+    s->core->stop();
     hipError_t e = hipSetDevice(s->device);
-    for (Slot &sl : s->slots)
-        if (e == hipSuccess && sl.st) e = hipStreamSynchronize(sl.st);
+    for (HipExec::Slot &sl : s->exec.sl)
+        if (e == hipSuccess && sl.st && !sl.retired) e = hipStreamSynchronize(sl.st);
     server_free(s);
     return e == hipSuccess ? GFQ_OK : hip_fail(e, "server destroy");
 }

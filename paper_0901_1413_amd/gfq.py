@@ -39,14 +39,14 @@ class Problem(ctypes.Structure):
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_size_t), ("slots", ctypes.c_int), ("max_batch", ctypes.c_int),
-                ("max_items", ctypes.c_int), ("mode", ctypes.c_int)]
+                ("max_items", ctypes.c_int), ("mode", ctypes.c_int), ("watchdog_s", ctypes.c_double)]
 
 
 class Request(ctypes.Structure):
     _fields_ = [("q", ctypes.c_int), ("m", ctypes.c_int64), ("l", ctypes.c_int64), ("n", ctypes.c_int64),
                 ("A", ctypes.c_void_p), ("lda", ctypes.c_int64), ("B", ctypes.c_void_p), ("ldb", ctypes.c_int64),
                 ("C", ctypes.c_void_p), ("ldc", ctypes.c_int64), ("flags", ctypes.c_int),
-                ("tag", ctypes.c_uint64), ("not_before_us", ctypes.c_double)]
+                ("tag", ctypes.c_uint64), ("not_before_us", ctypes.c_double), ("C_host", ctypes.c_void_p)]
 
 
 class Completion(ctypes.Structure):
@@ -438,19 +438,22 @@ class Server:
     keeps their tensors alive until poll() has returned their completions."""
 
     def __init__(self, budget_bytes: int = 0, slots: int = 0, max_batch: int = 0, max_items: int = 0,
-                 serial: bool = False):
-        o = ServerOpts(budget_bytes, slots, max_batch, max_items, 1 if serial else 0)
+                 serial: bool = False, watchdog_s: float = 0.0):
+        o = ServerOpts(budget_bytes, slots, max_batch, max_items, 1 if serial else 0, watchdog_s)
         h = _VP()
         _check(load().gfq_server_create(ctypes.byref(o), ctypes.byref(h)), "gfq_server_create")
         self.handle = h
         self._keep = {}
 
     @staticmethod
-    def request(q, m, l, n, A, B, C, tag, not_before_us=0.0, flags=0) -> Request:
+    def request(q, m, l, n, A, B, C, tag, not_before_us=0.0, flags=0, C_host=None) -> Request:
+        """C_host: optional (pinned) host tensor that receives a copy of the product before
+        the completion is reported."""
         a, lda = _operand(A, m, l, flags & REQ_A_PACKED)
         b, ldb = _operand(B, l, n, flags & REQ_B_PACKED)
         c, ldc = _operand(C, m, n, flags & REQ_C_PACKED)
-        return Request(q, m, l, n, a, lda, b, ldb, c, ldc, flags, tag, not_before_us)
+        h = C_host.data_ptr() if C_host is not None else None
+        return Request(q, m, l, n, a, lda, b, ldb, c, ldc, flags, tag, not_before_us, h)
 
     def submit(self, reqs: Sequence[Request], keep: Sequence = ()):
         """Queue requests (Request structures); keep[i] (optional) is held until request i

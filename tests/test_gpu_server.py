@@ -263,3 +263,54 @@ def test_server_validation(gfq_gpu):
         assert comps[0]["status"] == 0 and comps[0]["tag"] == 7
     finally:
         srv.destroy()
+
+
+@pytest.mark.parametrize("serial", [False, True])
+def test_results_copied_to_host(gfq_gpu, serial):
+    """Requests with a host destination: the completion reports the product already in
+    host memory (pinned), equal to the device result and to the oracle's."""
+    import torch
+    g = gfq_gpu
+    specs = mixed_specs(421, 24, lo=16, hi=400)
+    srv = g.Server(budget_bytes=128 << 20, serial=serial)
+    try:
+        reqs, keep, host = make(g, specs, 422)
+        hosts = []
+        for i, (q, m, l, n) in enumerate(specs):
+            h = torch.full((m * n + 16,), 0xCD, dtype=torch.uint8, pin_memory=True)
+            hosts.append(h)
+            reqs[i].C_host = h.data_ptr()
+        srv.submit(reqs, [k + (h,) for k, h in zip(keep, hosts)])
+        comps = srv.wait_all(len(specs))
+        # read the host copies before anything else touches the device results
+        got_host = [hosts[i][:m * n].numpy().reshape(m, n).copy() for i, (q, m, l, n) in enumerate(specs)]
+        check(g, specs, keep, host, comps)
+        for i, (q, m, l, n) in enumerate(specs):
+            assert np.array_equal(got_host[i], keep[i][2].cpu().numpy()), ("host copy", i)
+            assert bool((hosts[i][m * n:] == 0xCD).all()), ("past the span", i)
+    finally:
+        srv.destroy()
+
+
+def test_watchdog_fails_overdue_batches(gfq_gpu):
+    """The watchdog forced from the host: with a limit far below any batch's run time every
+    batch is overdue at its first poll, so its requests complete with GFQ_EHIP, the server
+    is marked failed and refuses later submissions.  The device work itself runs to its end
+    normally; the test waits for it before the operands go away."""
+    import torch
+    g = gfq_gpu
+    specs = [(3, 256, 256, 256), (5, 200, 300, 100), (4, 128, 128, 128)]
+    srv = g.Server(budget_bytes=64 << 20, slots=1, watchdog_s=1e-9)
+    reqs, keep, host = make(g, specs, 431)
+    try:
+        srv.submit(reqs, keep)
+        comps = srv.wait_all(len(specs))
+        assert sorted(c["tag"] for c in comps) == list(range(len(specs)))
+        assert all(c["status"] == -8 for c in comps), comps
+        with pytest.raises(g.GfqError) as e:
+            srv.submit([g.Server.request(3, 256, 256, 256, keep[0][0], keep[0][1], keep[0][2], tag=99)])
+        assert e.value.status == -8
+    finally:
+        torch.cuda.synchronize()                  # the abandoned batch's device work
+        srv.destroy()
+    torch.cuda.synchronize()
