@@ -13,22 +13,47 @@
 
 namespace gfq {
 
-// grid (column tiles, row tiles, slab slices); row tile ty0 + blockIdx.y
+// The tile a workgroup runs.  The dispatcher hands workgroups to the chip's XCDs in turn
+// (workgroup i of a launch to XCD i mod 8), and each XCD has an L2 of its own.  Workgroup i
+// therefore runs tile L(i) of the grid, numbered column tile fastest, then row tile, then
+// slice, where L gives each XCD one contiguous range of tiles: the workgroups running
+// together on an XCD are neighbours, which read the same rows of A (the column tiles of a
+// row tile) and of B (the row tiles of a column tile), and share them in that XCD's L2
+// instead of every XCD fetching them from HBM.  L is a bijection of 0 .. total - 1 for any
+// total (the first total mod 8 XCDs take one tile more).
+__device__ __forceinline__ void xcd_tile(int &bx, int &by, int &bz) {
+    constexpr uint64_t NXCD = 8;
+    const uint64_t X = gridDim.x, Y = gridDim.y;
+    const uint64_t total = X * Y * gridDim.z;
+    const uint64_t flat = blockIdx.x + X * (blockIdx.y + Y * (uint64_t)blockIdx.z);
+    const uint64_t per = total / NXCD, rem = total % NXCD;
+    const uint64_t xcd = flat % NXCD, local = flat / NXCD;
+    const uint64_t L = xcd * per + (xcd < rem ? xcd : rem) + local;
+    bx = (int)(L % X);
+    by = (int)((L / X) % Y);
+    bz = (int)(L / (X * Y));
+}
+
+// grid (column tiles, row tiles, slab slices); row tile ty0 + the grid's row tile
 template <int Q, int TWD, int REP, int R, int NT>
 __global__ __launch_bounds__(NT) void m4rm_kernel(MMArgs a, int ty0) {
-    m4rm_tile<Q, TWD, REP, R, NT>(a, blockIdx.x, ty0 + (int)blockIdx.y, blockIdx.z);
+    int bx, by, bz;
+    xcd_tile(bx, by, bz);
+    m4rm_tile<Q, TWD, REP, R, NT>(a, bx, ty0 + by, bz);
 }
 
 // many products of one shape: grid.z = product x slab slices, operands at uniform strides
 // (a kernel of its own, so that the single-product kernel keeps its plain argument use)
 template <int Q, int TWD, int REP, int R, int NT>
 __global__ __launch_bounds__(NT) void m4rm_strided_kernel(MMArgs a, int ty0, int splits, MMStrides sd) {
-    const int prod = (int)blockIdx.z / splits;
-    const int bz = (int)blockIdx.z - prod * splits;
+    int bx, by, bzp;
+    xcd_tile(bx, by, bzp);
+    const int prod = bzp / splits;
+    const int bz = bzp - prod * splits;
     a.A += (size_t)prod * sd.A;
     a.B += (size_t)prod * sd.B;
     a.out += (size_t)prod * sd.out;
-    m4rm_tile<Q, TWD, REP, R, NT>(a, blockIdx.x, ty0 + (int)blockIdx.y, bz);
+    m4rm_tile<Q, TWD, REP, R, NT>(a, bx, ty0 + by, bz);
 }
 
 // ---------------------------------------------------------------------------------------

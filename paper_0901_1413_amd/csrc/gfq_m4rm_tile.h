@@ -22,7 +22,9 @@
 //   gather  for every row, D table rows of slab s, alpha_d-scaled into the accumulator;
 //   barrier.
 // The build of slab s+1 and the gathers of slab s are independent: half of the waves
-// build first, the other half gather first, so every SIMD overlaps the two.
+// build first, the other half gather first, so every SIMD overlaps the two.  Where a
+// tile's gathers outweigh its build (F::HALF_BUILD_ROWS rows per lane or more) only the
+// first half of the waves builds, each thread walking twice as many entries.
 //
 // LDS table layout.  One (entry, plane) "super-row" is SRB bytes holding REP copies of
 // the TWD-word tile row.  gfx950 serves a 128-bit LDS read of 16 lanes from 64 four-byte
@@ -30,7 +32,9 @@
 // 256 distinct consecutive bytes: with SRB = 256 the REP rows of C gathered by one 16-lane
 // group come from different copies.  With SRB = 128 a super-row is one 32-word row and a
 // group serves two rows of C, each in one half of the banks (planes swapped on odd entries
-// when their number is even, so that the half follows the entry); with SRB = 64 and less,
+// when their number is even, so that the half follows the entry; for F_3, whose entries are
+// negated by exchanging their planes, the second row reads them exchanged and never meets
+// the first); with SRB = 64 and less,
 // four or more rows of C share a group and conflict as their entries fall.  Table 0 sits
 // at LDS offset 0 and table 1 at TB1, a power of two not below the table size, so an
 // address is (offset | lane offset | base).
@@ -250,7 +254,7 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
     // subtracting it when it switches off.  For three-plane fields the prefixes come from
     // a stage one slab earlier (prefix): NCH/4 threads per word each take four consecutive
     // chunks (a masked sum over the bits above the lowest two, then a Gray walk over those
-    // two) and leave them in a small buffer.  Where a table addition is short (F_3: 6
+    // two) and leave them in a small buffer.  Where a table addition is short (F_3: 4
     // instructions; GF(4), GF(8): one XOR per plane) each thread sums its own prefix (a
     // masked sum).  The rows a stage needs are read from LDS in one batch before its chain
     // of additions. ----
