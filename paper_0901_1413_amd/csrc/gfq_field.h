@@ -243,26 +243,6 @@ GFQ_HD F3v f3_add(F3v x, F3v y) {
 template <int NEG> GFQ_HD u32 fa_sum(u32 x, u32 y, u32 z) { return lut3<lut3_flip(0x96, NEG)>(x, y, z); }
 template <int NEG> GFQ_HD u32 fa_carry(u32 x, u32 y, u32 z) { return lut3<lut3_flip(0xE8, NEG)>(x, y, z); }
 
-// One F_3 slab into a carry-save accumulator modulo 3 of three planes (a, b, c), value
-// a + b + 2c: the slab adds t - v for two binary residues t = T[phi_0], v = T[phi_1] (each
-// b0 + 2 b1, 3 meaning 0), with -v = ~v (mod 3).  Bits of weight 4 = 1 re-enter weight 1, so
-// the columns hold  weight 1: a, b, t0, ~v0  and  weight 2: c, t1, ~v1, and four full adders
-// (8 instructions, as for a carry-save pair) bring them back to two bits and one bit.
-GFQ_HD void f3_nc_slab(u32 *s, const u32 *t, const u32 *v) {
-    const u32 s1 = fa_sum<0>(s[0], s[1], t[0]), k1 = fa_carry<0>(s[0], s[1], t[0]);   // weight 1
-    const u32 u1 = fa_sum<1>(s[2], t[1], v[1]), m1 = fa_carry<1>(s[2], t[1], v[1]);   // weight 2: c, t1, ~v1
-    const u32 s2 = fa_sum<2>(s1, v[0], m1), k2 = fa_carry<2>(s1, v[0], m1);          // weight 1: s1, ~v0, m1
-    s[0] = s2;
-    s[1] = fa_carry<0>(u1, k1, k2);                                                    // weight 4 = 1
-    s[2] = fa_sum<0>(u1, k1, k2);
-}
-
-// The accumulator's value as a binary residue (b0 + 2 b1, 3 meaning 0): (a + 2c) + b.
-GFQ_HD void f3_nc_value(const u32 *s, u32 *r) {
-    const u32 x[2] = {s[0], s[2]}, y[2] = {s[1], 0u};
-    f3b_add(x, y, r);
-}
-
 // F_5 addition and subtraction of 3-bit representatives in eight three-input instructions
 // (against eleven to thirteen for a 4-bit sum folded back modulo 5).  Bits of weight 4 = -1 enter
 // weight 1 complemented (4x = ~x - 1) and a constant bit fixes the offsets, so that four

@@ -65,15 +65,13 @@ int main() {
         unsigned vns = bit(n2s[0]) | bit(n2s[1]) << 1, vnk = bit(n2k[0]) | bit(n2k[1]) << 1;
         printf("csa %u %u %u  %u %u  %u %u  %u %u  %u %u\n", S, K, X, v4s, v4k, v3s, v3k, v2s, v2k, vns, vnk);
     }
-    // F_3 slab step of the three-plane carry-save accumulator modulo 3: every (a, b, c, t, v)
-    for (unsigned st = 0; st < 8; st++)
+    // F_3 slab step as the product kernel takes it: acc + t, then - v (binary residues mod 3)
+    for (unsigned a = 0; a < 4; a++)
         for (unsigned t = 0; t < 4; t++) for (unsigned v = 0; v < 4; v++) {
-            u32 s3[3] = {st & 1, (st >> 1) & 1, st >> 2}, t2[2] = {t & 1, t >> 1}, v2[2] = {v & 1, v >> 1};
-            f3_nc_slab(s3, t2, v2);
-            u32 r[2];
-            f3_nc_value(s3, r);
-            printf("f3slab %u %u %u %u %u %u %u\n", st & 1, (st >> 1) & 1, st >> 2, t, v,
-                   bit(s3[0]) | bit(s3[1]) << 1 | bit(s3[2]) << 2, bit(r[0]) | bit(r[1]) << 1);
+            u32 c[2] = {a & 1, a >> 1}, t2[2] = {t & 1, t >> 1}, v2[2] = {v & 1, v >> 1}, x[2], r[2];
+            f3b_add(c, t2, x);
+            f3b_sub(x, v2, r);
+            printf("f3acc %u %u %u %u\n", a, t, v, bit(r[0]) | bit(r[1]) << 1);
         }
     // F_5 eight-instruction addition and subtraction on every pair of 3-bit representatives
     for (unsigned a = 0; a < 8; a++) for (unsigned b = 0; b < 8; b++) {

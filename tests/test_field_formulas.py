@@ -108,16 +108,20 @@ def test_carry_save_steps(table):
 
 
 def test_f3_slab_step(table):
-    """One slab of the three-plane F_3 accumulator (value a + b + 2c modulo 3): the new value
-    is a + b + 2c + t - v (mod 3) for every state and every binary residue t, v in 0..3; its
-    value read out as a binary residue is the same residue."""
-    rows = [r for r in table if r[0] == "f3slab"]
-    assert len(rows) == 8 * 4 * 4
-    for r in rows:
-        a, b, c, t, v, out, val = map(int, r[1:])
-        a2, b2, c2 = out & 1, (out >> 1) & 1, out >> 2
-        assert (a2 + b2 + 2 * c2) % 3 == (a + b + 2 * c + t - v) % 3, r
-        assert val % 3 == (a2 + b2 + 2 * c2) % 3, r
+    """One F_3 slab as the product kernel accumulates it (binary residues modulo 3): acc + t
+    - v for every residue code acc, t, v in 0..3.  And the exchange of a lane's planes: a
+    lane that reads t and v with their planes exchanged, starting from the exchanged
+    accumulator, ends at the exchange of the true result (exchanging b0 and b1 of b0 + 2 b1
+    multiplies it by 2 = -1 mod 3), which is what lets one row of each read pass gather
+    from the opposite half of the banks and be turned back at the store."""
+    rows = {tuple(map(int, r[1:4])): int(r[4]) for r in table if r[0] == "f3acc"}
+    assert len(rows) == 4 * 4 * 4
+    sw = lambda x: (x >> 1) | ((x & 1) << 1)
+    for x in range(4):
+        assert sw(x) % 3 == (-x) % 3
+    for (a, t, v), r in rows.items():
+        assert r % 3 == (a + t - v) % 3, (a, t, v, r)
+        assert sw(rows[(sw(a), sw(t), sw(v))]) % 3 == r % 3, (a, t, v)
 
 
 def test_f5_eight_instruction_add_sub(table):
