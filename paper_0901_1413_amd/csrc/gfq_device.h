@@ -210,11 +210,14 @@ template <> struct FT<8> {
 // entries are pairs of binary residues mod 3 (real, imaginary).  With i (x + y i) =
 // -y + x i the slab adds T0 - T1 + i T2 - i T3, i.e. real += T0.re - T1.re - T2.im + T3.im
 // and imaginary += T0.im - T1.im + T2.re - T3.re, into two carry-save pairs mod 3.
+// Exchanging planes 2j and 2j + 1 negates both residues of an entry (SWAP_NEGATES); a
+// carry-save step on exchanged operands gives the exchanged result bit for bit, so a lane
+// that reads every entry exchanged ends with the exchange of the true accumulator.
 template <> struct FT<9> {
     static constexpr int P = 4, PT = 4, D = 4, GP = 4, PA = 8;
     // HALF_ROWS: a row's gathers are consumed in two halves (accumulate_half), so only half a
     // row of 128-bit reads is in flight at a time and four rows per lane fit the registers
-    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = true, SWAP_NEGATES = false;
+    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = true, SWAP_NEGATES = true;
     static constexpr int HALF_BUILD_ROWS = 4;
     static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0] ^ x[1]; f[1] = x[1]; f[2] = x[2] ^ x[3]; f[3] = x[3]; }
@@ -248,6 +251,15 @@ template <> struct FT<9> {
             csa_step<2>(Sr, Kr, t[1] + 2);
             csa_step<2>(Si, Ki, t[0]);
             csa_step_neg<2>(Si, Ki, t[1]);
+        }
+    }
+    // the accumulator negated where gm is all ones (the planes of each residue exchanged)
+    __device__ static void neg_sel(u32 *c, u32 gm) {
+#pragma unroll
+        for (int j = 0; j < PA; j += 2) {
+            const u32 c0 = c[j];
+            c[j] = lut3<0xCA>(gm, c[j + 1], c0);      // gm ? c1 : c0
+            c[j + 1] = lut3<0xCA>(gm, c0, c[j + 1]);
         }
     }
     __device__ static void finish(const u32 *c, u32 *out) {
