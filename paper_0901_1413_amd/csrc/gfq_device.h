@@ -207,16 +207,17 @@ template <> struct FT<8> {
 // F_9 = F_3[i]/(i^2 + 1) (Section 4.3: the power basis {1, i} of the extension times the
 // basis {1, -1} of F_3 gives the additive basis {1, -1, i, -i}).  Storage: the F_3 code of
 // a0, then of a1 (four planes); phi = [a0 = 1], [a0 = -1], [a1 = 1], [a1 = -1].  Table
-// entries are pairs of binary residues mod 3 (real, imaginary).  With i (x + y i) =
-// -y + x i the slab adds T0 - T1 + i T2 - i T3, i.e. real += T0.re - T1.re - T2.im + T3.im
-// and imaginary += T0.im - T1.im + T2.re - T3.re, into two carry-save pairs mod 3.
-// Exchanging planes 2j and 2j + 1 negates both residues of an entry (SWAP_NEGATES); a
-// carry-save step on exchanged operands gives the exchanged result bit for bit, so a lane
-// that reads every entry exchanged ends with the exchange of the true accumulator.
+// entries and the accumulator are pairs of binary residues mod 3 (real, imaginary).  With
+// i (x + y i) = -y + x i the slab adds T0 - T1 + i T2 - i T3, i.e. real += T0.re - T1.re -
+// T2.im + T3.im and imaginary += T0.im - T1.im + T2.re - T3.re: eight four-instruction residue
+// additions (as F_3), four accumulator planes, so eight rows per lane fit.
+// Exchanging planes 2j and 2j + 1 negates both residues of an entry (SWAP_NEGATES), and the
+// residue additions on negated operands give the negated sum, so a lane that reads every entry
+// exchanged ends with the negated accumulator.
 template <> struct FT<9> {
-    static constexpr int P = 4, PT = 4, D = 4, GP = 4, PA = 8;
+    static constexpr int P = 4, PT = 4, D = 4, GP = 4, PA = 4;
     // HALF_ROWS: a row's gathers are consumed in two halves (accumulate_half), so only half a
-    // row of 128-bit reads is in flight at a time and four rows per lane fit the registers
+    // row of 128-bit reads is in flight at a time
     static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = true, SWAP_NEGATES = true;
     static constexpr int HALF_BUILD_ROWS = 4;
     static constexpr int gplane(int, int p) { return p; }
@@ -226,31 +227,23 @@ template <> struct FT<9> {
     __device__ static void tsub(const u32 *a, const u32 *b, u32 *r) { f3b_sub(a, b, r); f3b_sub(a + 2, b + 2, r + 2); }
     __device__ static void acc_init(u32 *c, int) { for (int i = 0; i < PA; i++) c[i] = 0u; }
     __device__ static void accumulate(u32 *c, const u32 (*t)[P]) {
-        u32 *Sr = c, *Kr = c + 2, *Si = c + 4, *Ki = c + 6;
-        csa_step<2>(Sr, Kr, t[0]);
-        csa_step_neg<2>(Sr, Kr, t[1]);
-        csa_step_neg<2>(Sr, Kr, t[2] + 2);
-        csa_step<2>(Sr, Kr, t[3] + 2);
-        csa_step<2>(Si, Ki, t[0] + 2);
-        csa_step_neg<2>(Si, Ki, t[1] + 2);
-        csa_step<2>(Si, Ki, t[2]);
-        csa_step_neg<2>(Si, Ki, t[3]);
+        accumulate_half<0>(c, t);
+        accumulate_half<1>(c, t + 2);
     }
     // the same additions in two halves: H = 0 takes T[phi_0] - T[phi_1] (t[0], t[1]), H = 1
-    // takes i T[phi_2] - i T[phi_3] (t[0], t[1] holding phi_2, phi_3); the order of carry-save
-    // steps does not change the residue the accumulator resolves to
+    // takes i T[phi_2] - i T[phi_3] (t[0], t[1] holding phi_2, phi_3)
     template <int H> __device__ static void accumulate_half(u32 *c, const u32 (*t)[P]) {
-        u32 *Sr = c, *Kr = c + 2, *Si = c + 4, *Ki = c + 6;
+        u32 x[2];
         if (H == 0) {
-            csa_step<2>(Sr, Kr, t[0]);
-            csa_step_neg<2>(Sr, Kr, t[1]);
-            csa_step<2>(Si, Ki, t[0] + 2);
-            csa_step_neg<2>(Si, Ki, t[1] + 2);
+            f3b_add(c, t[0], x);                   // real += T0.re - T1.re
+            f3b_sub(x, t[1], c);
+            f3b_add(c + 2, t[0] + 2, x);           // imaginary += T0.im - T1.im
+            f3b_sub(x, t[1] + 2, c + 2);
         } else {
-            csa_step_neg<2>(Sr, Kr, t[0] + 2);
-            csa_step<2>(Sr, Kr, t[1] + 2);
-            csa_step<2>(Si, Ki, t[0]);
-            csa_step_neg<2>(Si, Ki, t[1]);
+            f3b_sub(c, t[0] + 2, x);               // real += -T2.im + T3.im
+            f3b_add(x, t[1] + 2, c);
+            f3b_add(c + 2, t[0], x);               // imaginary += T2.re - T3.re
+            f3b_sub(x, t[1], c + 2);
         }
     }
     // the accumulator negated where gm is all ones (the planes of each residue exchanged)
@@ -263,11 +256,8 @@ template <> struct FT<9> {
         }
     }
     __device__ static void finish(const u32 *c, u32 *out) {
-        u32 v[2];
-        f3b_add(c, c + 2, v);
-        f3_from_bin(v, &out[0], &out[1]);
-        f3b_add(c + 4, c + 6, v);
-        f3_from_bin(v, &out[2], &out[3]);
+        f3_from_bin(c, &out[0], &out[1]);
+        f3_from_bin(c + 2, &out[2], &out[3]);
     }
     __device__ static void sadd(const u32 *a, const u32 *b, u32 *r) {
         F3v re = f3_add(F3v{a[0], a[1]}, F3v{b[0], b[1]});

@@ -57,12 +57,12 @@ inline int gathers_of(int q) {
 }
 inline bool split_prefix(int q) { return q == 5 || q == 7; }   // FT<q>::SPLIT_PREFIX
 inline int words_of(int64_t cols) { return (int)(((cols + 127) / 128) * 4); }
-// Rows of C per lane: bounded by the accumulator registers (8 planes per word for F_9, 6 for
-// F_7, 3 for F_5 and GF(8), 2 for F_3 and GF(4)) and the gathered table rows in
-// flight (F_9 by Karatsuba: two rows of twelve 128-bit reads and 12 accumulator planes).  The work-list kernels of batches use at
-// most 8.
+// Rows of C per lane: bounded by the accumulator registers (6 planes per word for F_7, 4 for
+// F_9, 3 for F_5 and GF(8), 2 for F_3 and GF(4)) and the gathered table rows in flight (F_9
+// by Karatsuba: two rows of twelve 128-bit reads and 12 accumulator planes).  The work-list
+// kernels of batches use at most 8.
 inline int max_rows_per_lane(int q) {
-    return q == F9_KARATSUBA ? 2 : (q == 7 || q == 9 ? 4 : (q == 3 || q == 4 || q == GF4_KARATSUBA ? 16 : 8));
+    return q == F9_KARATSUBA ? 2 : (q == 7 ? 4 : (q == 3 || q == 4 || q == GF4_KARATSUBA ? 16 : 8));
 }
 inline int max_rows_per_lane_batch(int q) { return q == 5 || q == 7 || q == 9 ? 4 : 8; }
 
@@ -129,7 +129,8 @@ inline MMPlan mm_plan(int q, int k, int rowsTile) {
     if (r > max_rows_per_lane(q)) r = max_rows_per_lane(q);
     if (r > 8 && p.twd != 16 && !(q == 3 && p.twd == 32)) r = 8;   // 16 rows per lane: 16-word tiles (F_3: and 32)
     if (r > 4 && p.twd < 16 && (q == 5 || q == 8 || q == GF8_TRINOMIAL)) r = 4;   // ... for F_5, GF(8) eight would
-    if (r > 2 && p.twd < 16 && q == 9) r = 2;                             // ... and for F_9 four would
+    if (r > 4 && p.twd < 32 && q == 9) r = 4;           // F_9: eight rows per lane on 32-word tiles only,
+    if (r > 2 && p.twd < 16 && q == 9) r = 2;           // two on narrow ones (four would spill)
     if (p.twd == 4 && q == 3 && r > 4) r = 4;            // 4-word tiles stage R * 4 rows per thread:
     if (p.twd == 4 && q == 7 && r > 2) r = 2;            // F_3 at eight and F_7 at four would spill
     for (; r >= 2; r /= 2) {

@@ -96,7 +96,7 @@ static hipError_t launch_mm_rows(const MMArgs &a, const MMPlan &plan, const MMSt
     if (plan.R == 2 || two_only) return launch_mm<STRIDED, Q, TWD, REP, 2>(a, plan, sd, st);
     if constexpr (two_only) {
         return hipErrorInvalidValue;
-    } else if constexpr (Q == 7 || Q == 9 || ((Q == 5 || Q == 8 || Q == GF8_TRINOMIAL) && TWD < 16)) {
+    } else if constexpr (Q == 7 || (Q == 9 && TWD < 32) || ((Q == 5 || Q == 8 || Q == GF8_TRINOMIAL) && TWD < 16)) {
         return launch_mm<STRIDED, Q, TWD, REP, 4>(a, plan, sd, st);       // eight rows per lane would spill
     } else {
         if (plan.R == 4) return launch_mm<STRIDED, Q, TWD, REP, 4>(a, plan, sd, st);

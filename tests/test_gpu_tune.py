@@ -70,19 +70,19 @@ def test_tune_rejects_bad_arguments(tuned):
 
 
 def test_lookup_splits_smaller_products_again(tuned, tmp_path):
-    """An entry of the class 2049..4096 timed at 4096^3 (F_9, k = 7, 512-row tiles, split 4):
-    a 4096^3 product keeps it; a 2500^3 product of the same class has 25 tiles instead of 64,
-    so its split is chosen again for its own shape (the cost model gives 8: 200 workgroups,
-    one round), never below the cached split; an entry timed at 2500^3 itself keeps its split
-    there.  The re-split product
-    is checked against the oracle on sampled rows."""
+    """An entry of the class 2049..4096 timed at 4096^3 (F_9, k = 7, 512-row tiles of 32 words,
+    split 4): a 4096^3 product keeps it; a 2500^3 product of the same class has 15 tiles (3
+    column tiles by 5 row tiles) instead of 32, so its split is chosen again for its own shape
+    (the cost model gives 16: 240 workgroups, one round), never below the cached split; an entry
+    timed at 2500^3 itself keeps its split there.  The re-split product is checked against the
+    oracle on sampled rows."""
     import torch
     g = tuned
     f = tmp_path / "t.txt"
     f.write_text("gfx950 0 9 12 12 12 7 512 4 0\n")
     g.tune_load(str(f))
     assert g.choose_config(9, 4096, 4096, 4096) == {"k": 7, "rows": 512, "split": 4, "variant": 0}
-    assert g.choose_config(9, 2500, 2500, 2500) == {"k": 7, "rows": 512, "split": 8, "variant": 0}
+    assert g.choose_config(9, 2500, 2500, 2500) == {"k": 7, "rows": 512, "split": 16, "variant": 0}
     q, N = 9, 2500
     A, B = inputs.pair(q, N, N, N, cfg=222, idx=0)
     C = g.matmul_unpacked(q, dev(A), dev(B))
@@ -93,8 +93,8 @@ def test_lookup_splits_smaller_products_again(tuned, tmp_path):
     f.write_text("gfx950 0 9 12 12 12 7 512 4 0 2500 2500\n")
     g.tune_load(str(f))
     assert g.choose_config(9, 2500, 2500, 2500)["split"] == 4
-    # the split chosen again is never below the cached one (the model alone would give 8)
+    # the split chosen again is never below the cached one (the model alone would give 16)
     g.tune_clear()
-    f.write_text("gfx950 0 9 12 12 12 7 512 16 0\n")
+    f.write_text("gfx950 0 9 12 12 12 7 512 32 0\n")
     g.tune_load(str(f))
-    assert g.choose_config(9, 2500, 2500, 2500)["split"] == 16
+    assert g.choose_config(9, 2500, 2500, 2500)["split"] == 32
