@@ -50,7 +50,7 @@ FIELDS = (3, 5)
 PEAK_VALU_OPS = 256 * 128 * 2.4e9
 PEAK_LDS = 256 * 256 * 2.4e9              # LDS bytes per second: 64 banks x 4 B per clock per CU
 PEAK_HBM = 8.0e12
-SECTIONS = ("c1", "c2_k", "mfma", "c3", "ext", "sw", "c4", "c5")
+SECTIONS = ("c1", "c2_k", "mfma", "c3", "ext", "sw", "c4", "c4_slices", "c5")
 
 # Per-unit operation counts of the method on gfx950 (three-input bitwise instructions).
 # A unit is (row of C, slab of k rows of B, 32-column word).  Accumulate: the slab's D
@@ -865,6 +865,64 @@ def section_c4(ctx, count=4096, reps=5, pool=2048):
 
 
 # ------------------------------------------------------------------------------------
+# c4_slices: a batch of products with few tiles and a long inner dimension, whose tiles the
+# batch cuts into slab slices (partial products summed by a partial-sum launch)
+# ------------------------------------------------------------------------------------
+
+def section_c4_slices(ctx, per_field=16, shape=(512, 16384, 512), reps=10, sample_rows=8):
+    import numpy as np
+    torch, gfq, inputs = ctx.torch, ctx.gfq, ctx.inputs
+    m, l, n = shape
+    specs = [(q, m, l, n) for q in (3, 5, 7) for _ in range(per_field)]
+    probs, host = [], []
+    for i, (q, _, _, _) in enumerate(specs):
+        A, B = inputs.pair(q, m, l, n, cfg=8, idx=i)
+        probs.append((q, m, l, n, gfq.pack(q, ctx.up(A)), gfq.pack(q, ctx.up(B)), gfq.empty_packed(q, m, n)))
+        host.append((A, B))
+    b = gfq.Batch(probs)
+    slices = b.slices()
+    b.launch()
+    torch.cuda.synchronize()
+    warm(torch, b.launch)
+    ev = ctx.events(2)
+    ev[0].record()
+    for _ in range(reps):
+        b.launch()
+    ev[1].record()
+    torch.cuda.synchronize()
+    batched_ms = ev[0].elapsed_time(ev[1]) / reps
+    done_us = sorted(b.times_us())
+    got = [gfq.unpack(q, C, m, n).cpu().numpy() for (q, _, _, _, _, _, C) in probs]
+    plain_out = [gfq.empty_packed(q, m, n) for (q, _, _, _) in specs]
+
+    def plain():
+        for (q, _, _, _, A, B, _), C in zip(probs, plain_out):
+            gfq.matmul(q, A, B, m, l, n, out=C)
+
+    warm(torch, plain)
+    ev[0].record()
+    for _ in range(reps):
+        plain()
+    ev[1].record()
+    torch.cuda.synchronize()
+    plain_ms = ev[0].elapsed_time(ev[1]) / reps
+    same = all(torch.equal(C[:gfq.packed_bytes(q, m, n)], C2[:gfq.packed_bytes(q, m, n)])
+               for (q, _, _, _, _, _, C), C2 in zip(probs, plain_out))
+    rows = np.sort(inputs.rng(8, m, 1).choice(m, size=sample_rows, replace=False))
+    ok = all(np.array_equal(got[i][rows], ctx.oracle.matmul(specs[i][0], host[i][0][rows], host[i][1]))
+             for i in range(len(specs)))
+    ops = 2.0 * m * l * n * len(specs)
+    b.destroy()
+    return {"workload": f"{len(specs)} products {m}x{l}x{n} ({per_field} each over F_3, F_5, F_7), uniform",
+            "batched_ms": round(batched_ms, 4), "batched_field_ops_per_s": ops / (batched_ms * 1e-3),
+            "plain_ms": round(plain_ms, 4), "plain_field_ops_per_s": ops / (plain_ms * 1e-3),
+            "speedup": round(plain_ms / batched_ms, 2), "slices": sorted(set(slices)),
+            "completion_p50_us": round(percentile(done_us, 50), 1),
+            "completion_p99_us": round(percentile(done_us, 99), 1),
+            "batched_equals_plain": same, "sampled_rows_bit_exact": bool(ok), "sampled_rows": sample_rows}
+
+
+# ------------------------------------------------------------------------------------
 # c5: served requests, continuous batching vs serial plain launches
 # ------------------------------------------------------------------------------------
 
@@ -1109,6 +1167,10 @@ def main():
     if "c4" in sections:
         log("c4")
         res["c4"] = section_c4(ctx)
+        torch.cuda.empty_cache()
+    if "c4_slices" in sections:
+        log("c4_slices")
+        res["c4_slices"] = section_c4_slices(ctx)
         torch.cuda.empty_cache()
     if "c5" in sections:
         log("c5")

@@ -188,8 +188,9 @@ int gfq_matmul_sw(int q, int64_t m, int64_t l, int64_t n, const void *A, const v
                   const gfq_config *leaf);
 
 /* Run count independent products (fields and shapes may differ) as one launch per
- * (field, tile shape) whose workgroups take (product, row tile, column tile) items from a
- * longest-first work list.  problems is a host array.  Each product obeys the gfq_matmul
+ * (field, tile shape) whose workgroups take (product, row tile, column tile, slab slice)
+ * items from a longest-first work list (the method of Section 2 per item), plus one
+ * partial-sum launch when products are sliced.  problems is a host array.  Each product obeys the gfq_matmul
  * rules; a validation error in any product rejects the whole batch before anything is
  * launched.  Equivalent to gfq_batch_create + gfq_batch_launch; the batch's descriptors are
  * released by a later call or gfq_sync once the launch has finished. */
@@ -200,19 +201,27 @@ int gfq_matmul_batched(int count, const gfq_problem *problems);
  * times.  gfq_batch_create validates every product (any error rejects the batch), chooses
  * each product's slab width and tile height (from the tuning cache when it holds the
  * product's size class; a product taller than 256 rows and at most 256 columns wide gets
- * one column of narrow tiles), orders each (field, tile shape) list of (product, row tile,
- * column tile) items longest first and uploads the descriptors; it synchronises.
+ * one column of narrow tiles), cuts the inner dimension of a product into slab slices
+ * (at least 8 slabs each, at most 64 slices and 256 MiB of partial products) when each of
+ * its tiles would take more than half of a compute unit's share of the whole batch (few
+ * tiles and a long inner dimension), orders each (field, tile shape) list of (product, row
+ * tile, column tile, slice) items longest first, allocates the descriptors and the sliced
+ * products' partial products in one device allocation and uploads the descriptors; it
+ * synchronises.
  * gfq_batch_launch enqueues one launch per list (a workgroup per item): the first on the
  * calling thread's stream, the others on side streams of the library (default priority,
  * kept per calling stream until the process ends) that fork from and join back into the
  * calling stream, so the lists overlap.  It allocates nothing, so it may be captured into a
  * graph (the lists become parallel branches); side streams are never created during a
  * capture: if the capturing stream has none yet, the lists are captured one after another
- * (one uncaptured launch on that stream first creates them).  Launches
+ * (one uncaptured launch on that stream first creates them).  When products are sliced, a
+ * partial-sum launch on the calling stream follows the joined lists and writes their C.
+ * Launches
  * of one batch must not overlap in time (they share its tile counters, completion stamps
  * and outputs): issue them on one stream, or wait for one before issuing the next.
  * gfq_batch_times waits for that stream and writes, per product, the microseconds from the
- * start of the most recent launch to the completion of the product's last tile.
+ * start of the most recent launch to the completion of the product (its last tile, or the
+ * last of its partial sums).
  * gfq_batch_destroy waits for the device and frees everything. */
 typedef struct gfq_batch gfq_batch;
 int gfq_batch_create(int count, const gfq_problem *problems, gfq_batch **out);
@@ -221,6 +230,9 @@ int gfq_batch_times(gfq_batch *batch, double *completion_us);
 /* The slab width k the batch gives each product (host array of count ints; the work the
  * method does per product, Section 2, depends on it). */
 int gfq_batch_slab_widths(const gfq_batch *batch, int *k);
+/* The number of slab slices the batch cut each product into (host array of count ints; 1:
+ * whole tiles). */
+int gfq_batch_slices(const gfq_batch *batch, int *slices);
 int gfq_batch_destroy(gfq_batch *batch);
 
 /* Autotuning.  gfq_tune times candidate configurations on scratch operands of the given

@@ -9,21 +9,41 @@
 namespace gfq {
 
 struct BatchProd {
-    MMArgs a;              // the product, as a single-product launch would see it (split 1)
-    u32 tiles;             // row tiles x column tiles
-    u32 pad;
+    MMArgs a;              // the product as a single-product launch sees it: with slab slices
+                           // a.out is the first slice's partial product (a.split_stride apart)
+    u32 units;             // work units until the product is complete: tiles x slices, plus
+                           // one partial-sum item per chunk of a sliced product
+    u32 slices;            // slab slices (1: the tiles write C directly)
+    u32 *C;                // the product
+    int q;                 // field (the storage addition of the partial sums)
+    int pad;
 };
 
 struct BatchItem {
     u32 prod;              // index into the product table
     uint16_t tx, ty;       // column tile, row tile
+    u32 slice;             // slab slice
 };
 
 struct BatchList {
     const BatchProd *prods;
     const BatchItem *items;            // this list's items, longest first (one per workgroup)
-    u32 *prod_done;                    // tiles finished per product (cleared on completion)
+    u32 *prod_done;                    // work units finished per product (cleared on completion)
     unsigned long long *prod_time;     // completion time per product (100 MHz clock)
+};
+
+// A partial-sum item: groups [first, first + count) of a sliced product, a group being one
+// row's four words of every plane (row = group / (Wn / 4)).
+struct ReduceItem {
+    u32 prod;
+    u32 first, count;
+};
+
+struct ReduceList {
+    const BatchProd *prods;
+    const ReduceItem *items;
+    u32 *prod_done;
+    unsigned long long *prod_time;
 };
 
 // Work-list kernel for field q with R rows per lane and tiles TWD words wide per plane: 16
@@ -32,6 +52,8 @@ struct BatchList {
 // tile.
 const void *batched_kernel(int q, int R, int twd);
 hipError_t launch_batched(int q, int R, int twd, const BatchList &bl, int items, size_t lds, hipStream_t st);
+// The partial sums of every sliced product of a batch: one workgroup per item, any fields.
+hipError_t launch_reduce_list(const ReduceList &rl, int items, hipStream_t st);
 hipError_t launch_batch_stamp(unsigned long long *t, hipStream_t st);
 
 }  // namespace gfq

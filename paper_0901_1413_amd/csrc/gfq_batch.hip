@@ -1,18 +1,23 @@
 // gfq_batch.hip -- many independent products in one launch per (field, tile height): the
-// grid is a work list of (product, row tile, column tile) items, longest first.
+// grid is a work list of (product, row tile, column tile, slab slice) items, longest first.
 //
 // Each product keeps its own shape and slab width k; the items of one list share a field
 // and a tile height (rows per lane R), so one kernel instance serves them.  Workgroup b
 // takes item b and runs the tile with the same body as the single-product kernel; the
 // hardware dispatcher hands items to compute units as they free up, in list order, so the
-// longest items start first and the tail of the launch is short.  The workgroup that
-// finishes a product's last tile stamps the product's completion time (100 MHz constant
-// clock) and clears the product's tile count, so the same lists can be launched again.
+// longest items start first and the tail of the launch is short.  A product whose tiles
+// would each take a large share of the batch (few tiles, a long inner dimension) is cut
+// into slab slices as well: each slice's items write a partial product, and a partial-sum
+// list (one launch for every sliced product, after the work lists) adds them into C.  The
+// workgroup that finishes a product's last unit of work stamps the product's completion
+// time (100 MHz constant clock) and clears the product's count, so the same lists can be
+// launched again.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "gfq_batch.h"
 #include "gfq_m4rm_tile.h"
+#include "gfq_reduce.h"
 
 namespace gfq {
 
@@ -20,13 +25,44 @@ template <int Q, int TWD, int REP, int R, int NT>
 __global__ __launch_bounds__(NT) void m4rm_list_kernel(BatchList bl) {
     const BatchItem item = bl.items[blockIdx.x];
     const MMArgs a = bl.prods[item.prod].a;
-    m4rm_tile<Q, TWD, REP, R, NT>(a, item.tx, item.ty, 0);
+    m4rm_tile<Q, TWD, REP, R, NT>(a, item.tx, item.ty, (int)item.slice);
     __syncthreads();                             // every thread of the tile has stored
     if (threadIdx.x == 0) {
         const u32 d = atomicAdd(&bl.prod_done[item.prod], 1u);
-        if (d + 1 == bl.prods[item.prod].tiles) {
+        if (d + 1 == bl.prods[item.prod].units) {
             bl.prod_time[item.prod] = __builtin_amdgcn_s_memrealtime();
             bl.prod_done[item.prod] = 0u;
+        }
+    }
+}
+
+// Partial sums of sliced products: item b adds the slices of its groups into C; the item
+// that finishes a product's last unit stamps and clears it, as the work lists do.
+__global__ __launch_bounds__(256) void reduce_list_kernel(ReduceList rl) {
+    const ReduceItem it = rl.items[blockIdx.x];
+    const BatchProd &p = rl.prods[it.prod];
+    const u32 *part = p.a.out;
+    u32 *C = p.C;
+    const int n = p.a.n, Wn = p.a.Wn, slices = (int)p.slices, q = p.q;
+    const size_t stride = p.a.split_stride;
+    const u32 groups = (u32)(Wn / 4);
+    for (u32 u = it.first + threadIdx.x; u < it.first + it.count; u += blockDim.x) {
+        const int row = (int)(u / groups), w = (int)(u % groups) * 4;
+        switch (q) {                             // one field per item: a uniform branch
+        case 3: reduce_group<3>(part, C, row, w, n, Wn, slices, stride); break;
+        case 4: reduce_group<4>(part, C, row, w, n, Wn, slices, stride); break;
+        case 5: reduce_group<5>(part, C, row, w, n, Wn, slices, stride); break;
+        case 8: reduce_group<8>(part, C, row, w, n, Wn, slices, stride); break;
+        case 9: reduce_group<9>(part, C, row, w, n, Wn, slices, stride); break;
+        default: reduce_group<7>(part, C, row, w, n, Wn, slices, stride); break;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const u32 d = atomicAdd(&rl.prod_done[it.prod], 1u);
+        if (d + 1 == p.units) {
+            rl.prod_time[it.prod] = __builtin_amdgcn_s_memrealtime();
+            rl.prod_done[it.prod] = 0u;
         }
     }
 }
@@ -73,6 +109,12 @@ hipError_t launch_batched(int q, int R, int twd, const BatchList &bl, int items,
     if (!k) return hipErrorInvalidValue;
     void *args[] = {(void *)&bl};
     return hipLaunchKernel(k, dim3(items), dim3(NT_MM), args, lds, st);
+}
+
+hipError_t launch_reduce_list(const ReduceList &rl, int items, hipStream_t st) {
+    if (items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(reduce_list_kernel, dim3(items), dim3(256), 0, st, rl);
+    return hipGetLastError();
 }
 
 hipError_t launch_batch_stamp(unsigned long long *t, hipStream_t st) {

@@ -1,13 +1,15 @@
 // gfq_batch_host.cpp -- building, launching and timing batches of products (the host side
-// of gfq_batch.hip): per-product launch parameters, work lists ordered longest first and
-// one device allocation for all descriptors.  A launch is a start stamp and one work-list
-// kernel per (field, tile height): the first on the caller's stream, the others forked onto
-// side streams and joined back, so that one group's last workgroups overlap the others'; it
-// allocates nothing, so a caller may capture it into a graph (the fork becomes parallel
-// branches of the graph).
+// of gfq_batch.hip): per-product launch parameters, work lists ordered longest first, slab
+// slices for products whose tiles are too long for the batch, and one device allocation for
+// all descriptors and partial products.  A launch is a start stamp, one work-list kernel per
+// (field, tile height) -- the first on the caller's stream, the others forked onto side
+// streams and joined back, so that one group's last workgroups overlap the others' -- and,
+// when products are sliced, one partial-sum launch; it allocates nothing, so a caller may
+// capture it into a graph (the fork becomes parallel branches of the graph).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -69,8 +71,11 @@ int group_index(int q, int R, int twd) {
 // Launch parameters of every product and its tiles, grouped by (field, rows per lane) and
 // ordered longest first within a group.
 void gfq::plan_batch(int count, const gfq_problem *problems, const gfq_config *cfgs, BatchProd *prods,
-                     std::vector<BatchGroup> *groups, size_t *nitems) {
+                     std::vector<BatchGroup> *groups, size_t *nitems, BatchSlicing *slicing) {
     std::vector<BatchGroup> g(24);
+    struct Shape { int gi = -1, tx = 0, ty = 0, TM = 0, twd = 16; double tile_cost = 0; };
+    std::vector<Shape> sh(count);
+    double total = 0;
     for (int i = 0; i < count; i++) {
         const gfq_problem &p = problems[i];
         BatchProd &bp = prods[i];
@@ -105,24 +110,78 @@ void gfq::plan_batch(int count, const gfq_problem *problems, const gfq_config *c
         a.k = k;
         a.S = p.l > 0 ? (int)((p.l + k - 1) / k) : 0;
         a.slabs_per_split = std::max(a.S, 1);
-        a.split_stride = 0;
+        a.split_stride = (size_t)p.m * P * a.Wn;
         mm_lds_bytes(p.q, k, srb, TM, &a.tb1);
+        bp.slices = 1;
+        bp.C = (u32 *)p.C;
+        bp.q = p.q;
         if (p.m == 0 || p.n == 0) continue;
-        const int tx = (a.Wn + twd - 1) / twd, ty = (a.m + TM - 1) / TM;
-        bp.tiles = (u32)(tx * ty);
-        BatchGroup &gr = g[group_index(p.q, R, twd)];
+        Shape &s = sh[i];
+        s.tx = (a.Wn + twd - 1) / twd;
+        s.ty = (a.m + TM - 1) / TM;
+        s.TM = TM;
+        s.twd = twd;
+        s.gi = group_index(p.q, R, twd);
+        // relative tile cost: rows x words x slabs (plus the tables it builds); the first tile
+        // is a whole one, the costliest
+        const double rows = std::min<int64_t>(TM, p.m), words = std::min(twd, a.Wn);
+        s.tile_cost = (rows + (double)(1 << k)) * words * std::max(a.S, 1) * (P == 2 ? 1.0 : 3.0);
+        for (int y = 0; y < s.ty; y++)
+            for (int x = 0; x < s.tx; x++)
+                total += (std::min<int64_t>(TM, p.m - (int64_t)y * TM) + (double)(1 << k)) *
+                         std::min(twd, a.Wn - x * twd) * std::max(a.S, 1) * (P == 2 ? 1.0 : 3.0);
+        BatchGroup &gr = g[s.gi];
         gr.q = p.q;
         gr.R = R;
         gr.twd = twd;
         gr.kmax = std::max(gr.kmax, k);
-        for (int y = 0; y < ty; y++)
-            for (int x = 0; x < tx; x++) {
-                const double rows = std::min<int64_t>(TM, p.m - (int64_t)y * TM);
-                const double words = std::min(twd, a.Wn - x * twd);
-                gr.items.push_back(BatchItem{(u32)i, (uint16_t)x, (uint16_t)y});
-                // relative tile cost: rows x words x slabs (plus the tables it builds)
-                gr.cost.push_back((rows + (double)(1 << k)) * words * std::max(a.S, 1) * (P == 2 ? 1.0 : 3.0));
+    }
+    if (slicing) {
+        slicing->partial_words = 0;
+        slicing->part_off.assign(count, 0);
+        slicing->reduce.clear();
+    }
+    const double share = total / std::max(1, slicing ? slicing->cus : 1);
+    for (int i = 0; i < count; i++) {
+        const Shape &s = sh[i];
+        if (s.gi < 0) continue;
+        BatchProd &bp = prods[i];
+        MMArgs &a = bp.a;
+        int slices = 1;
+        if (slicing && a.S >= 16 && s.tile_cost > 0.5 * share) {
+            // slices of at least 8 slabs, at most 64, and at most 256 MiB of partial products
+            const size_t part_bytes = a.split_stride * 4;
+            int64_t want = (int64_t)std::ceil(2.0 * s.tile_cost / share);
+            want = std::min<int64_t>(want, std::min<int64_t>(a.S / 8, 64));
+            want = std::min<int64_t>(want, (int64_t)(((size_t)256 << 20) / std::max<size_t>(part_bytes, 1)));
+            if (want >= 2) {
+                a.slabs_per_split = (a.S + (int)want - 1) / (int)want;
+                slices = (a.S + a.slabs_per_split - 1) / a.slabs_per_split;
             }
+        }
+        bp.slices = (u32)slices;
+        bp.units = (u32)(s.tx * s.ty * slices);
+        if (slices > 1) {
+            slicing->part_off[i] = slicing->partial_words;
+            slicing->partial_words += (size_t)slices * a.split_stride;
+            const u32 ngroups = (u32)a.m * (u32)(a.Wn / 4), chunk = 1024;
+            for (u32 f = 0; f < ngroups; f += chunk) {
+                slicing->reduce.push_back(ReduceItem{(u32)i, f, std::min(chunk, ngroups - f)});
+                bp.units++;
+            }
+        }
+        BatchGroup &gr = g[s.gi];
+        const int P = planes_of(problems[i].q);
+        for (int y = 0; y < s.ty; y++)
+            for (int x = 0; x < s.tx; x++)
+                for (int z = 0; z < slices; z++) {
+                    const double rows = std::min<int64_t>(s.TM, a.m - (int64_t)y * s.TM);
+                    const double words = std::min(s.twd, a.Wn - x * s.twd);
+                    const int slabs = std::max(1, std::min(a.slabs_per_split, a.S - z * a.slabs_per_split));
+                    gr.items.push_back(BatchItem{(u32)i, (uint16_t)x, (uint16_t)y, (u32)z});
+                    // relative item cost: rows x words x slabs (plus the tables it builds)
+                    gr.cost.push_back((rows + (double)(1 << a.k)) * words * slabs * (P == 2 ? 1.0 : 3.0));
+                }
     }
     groups->clear();
     size_t n = 0;
@@ -194,7 +253,10 @@ struct gfq_batch {
     BatchItem *items = nullptr;
     u32 *prod_done = nullptr;
     unsigned long long *times = nullptr;   // [0] start, [1 + p] completion of product p
+    ReduceItem *ritems = nullptr;          // partial-sum items of the sliced products
+    int nritems = 0;
     std::vector<int> k;                    // slab width of each product
+    std::vector<int> slices;               // slab slices of each product
 };
 
 static void batch_release(gfq_batch *b) {
@@ -223,28 +285,45 @@ int gfq::batch_create_with(int count, const gfq_problem *problems, const gfq_con
 
     std::vector<BatchProd> prods(std::max(count, 1));
     size_t nitems = 0;
-    plan_batch(count, problems, cfgs, prods.data(), &b->groups, &nitems);
+    BatchSlicing sl;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) == hipSuccess && cus > 0)
+        sl.cus = cus;
+    plan_batch(count, problems, cfgs, prods.data(), &b->groups, &nitems, &sl);
     b->k.resize(count);
-    for (int i = 0; i < count; i++) b->k[i] = prods[i].a.k;
+    b->slices.resize(count);
+    for (int i = 0; i < count; i++) {
+        b->k[i] = prods[i].a.k;
+        b->slices[i] = (int)prods[i].slices;
+    }
 
-    // one allocation: products | items | tile counts | times
+    // one allocation: products | items | partial-sum items | unit counts | times | partials
     auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t nr = sl.reduce.size();
     const size_t off_items = align(sizeof(BatchProd) * std::max(count, 1));
-    const size_t off_done = off_items + align(sizeof(BatchItem) * std::max<size_t>(nitems, 1));
+    const size_t off_ritems = off_items + align(sizeof(BatchItem) * std::max<size_t>(nitems, 1));
+    const size_t off_done = off_ritems + align(sizeof(ReduceItem) * std::max<size_t>(nr, 1));
     const size_t off_time = off_done + align(sizeof(u32) * std::max(count, 1));
-    const size_t total = off_time + align(sizeof(unsigned long long) * (count + 1));
+    const size_t off_part = off_time + align(sizeof(unsigned long long) * (count + 1));
+    const size_t total = off_part + align(sl.partial_words * sizeof(u32));
     e = hipMalloc(&b->mem, total);
     if (e != hipSuccess) { batch_release(b); hip_fail(e, "hipMalloc(batch)"); return GFQ_ENOMEM; }
     char *base = (char *)b->mem;
+    for (int i = 0; i < count; i++)
+        if (prods[i].slices > 1) prods[i].a.out = (u32 *)(base + off_part) + sl.part_off[i];
     std::vector<BatchItem> all(std::max<size_t>(nitems, 1));
     for (const BatchGroup &gr : b->groups) std::copy(gr.items.begin(), gr.items.end(), all.begin() + gr.item_off);
-    e = hipMemset(b->mem, 0, total);
+    e = hipMemset(b->mem, 0, off_part);
     if (e == hipSuccess && count > 0) e = hipMemcpy(base, prods.data(), sizeof(BatchProd) * count, hipMemcpyHostToDevice);
     if (e == hipSuccess && nitems > 0) e = hipMemcpy(base + off_items, all.data(), sizeof(BatchItem) * nitems, hipMemcpyHostToDevice);
+    if (e == hipSuccess && nr > 0)
+        e = hipMemcpy(base + off_ritems, sl.reduce.data(), sizeof(ReduceItem) * nr, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = set_batched_lds_limits();
     if (e != hipSuccess) { batch_release(b); return hip_fail(e, "batch upload"); }
     b->prods = (BatchProd *)base;
     b->items = (BatchItem *)(base + off_items);
+    b->ritems = (ReduceItem *)(base + off_ritems);
+    b->nritems = (int)nr;
     b->prod_done = (u32 *)(base + off_done);
     b->times = (unsigned long long *)(base + off_time);
     *out = b;
@@ -267,6 +346,14 @@ int gfq_batch_launch(gfq_batch *b) {
     base.prod_done = b->prod_done;
     base.prod_time = b->times + 1;
     if (e == hipSuccess) e = launch_group_lists(b->groups, base, st);
+    if (e == hipSuccess && b->nritems > 0) {
+        ReduceList rl;
+        rl.prods = b->prods;
+        rl.items = b->ritems;
+        rl.prod_done = b->prod_done;
+        rl.prod_time = b->times + 1;
+        e = launch_reduce_list(rl, b->nritems, st);
+    }
     return e == hipSuccess ? GFQ_OK : hip_fail(e, "batch launch");
 }
 
@@ -284,6 +371,12 @@ int gfq_batch_times(gfq_batch *b, double *completion_us) {
 int gfq_batch_slab_widths(const gfq_batch *b, int *k) {
     if (!b || !k) return GFQ_ENULL;
     std::copy(b->k.begin(), b->k.end(), k);
+    return GFQ_OK;
+}
+
+int gfq_batch_slices(const gfq_batch *b, int *slices) {
+    if (!b || !slices) return GFQ_ENULL;
+    std::copy(b->slices.begin(), b->slices.end(), slices);
     return GFQ_OK;
 }
 

@@ -25,10 +25,22 @@ struct BatchGroup {
     std::vector<BatchItem> items;    // longest first
     std::vector<double> cost;        // planning only
 };
+// Slab slices of a batch's products.  A product whose tiles would each take more than half of
+// a compute unit's share of the batch (few tiles, a long inner dimension) is cut into slices
+// of at least 8 slabs; product i's partial products take slices x m x P x Wn words at word
+// offset part_off[i] of a workspace of partial_words words (the caller points a.out there),
+// and `reduce` lists the partial-sum items of every sliced product.
+struct BatchSlicing {
+    int cus = 256;                     // compute units of the device
+    size_t partial_words = 0;
+    std::vector<size_t> part_off;
+    std::vector<ReduceItem> reduce;
+};
 // Per-product launch parameters (prods[0 .. count)) and the non-empty work lists, with
-// consecutive item offsets; *nitems = total tiles.  The problems must be valid.
+// consecutive item offsets; *nitems = total items.  Without `slicing` every product is whole
+// tiles.  The problems must be valid.
 void plan_batch(int count, const gfq_problem *problems, const gfq_config *cfgs, BatchProd *prods,
-                std::vector<BatchGroup> *groups, size_t *nitems);
+                std::vector<BatchGroup> *groups, size_t *nitems, BatchSlicing *slicing = nullptr);
 // Launch every group's work list: the first on st, the others forked onto side streams of
 // st and joined back into it (one after another on st while st is captured and has no side
 // streams yet).  base: the batch's lists with items pointing at item 0.

@@ -81,6 +81,7 @@ _SIGS = {
     "gfq_batch_times": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double)]),
     "gfq_batch_destroy": (ctypes.c_int, [_VP]),
     "gfq_batch_slab_widths": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int)]),
+    "gfq_batch_slices": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int)]),
     "gfq_tune": (ctypes.c_int, [ctypes.c_int, _I64, _I64, _I64, ctypes.c_int, ctypes.POINTER(Config)]),
     "gfq_tune_lookup": (ctypes.c_int, [ctypes.c_int, _I64, _I64, _I64, ctypes.c_int, ctypes.POINTER(Config)]),
     "gfq_tune_save": (ctypes.c_int, [ctypes.c_char_p]),
@@ -309,6 +310,12 @@ class Batch:
         """The slab width k the batch gives each product."""
         out = (ctypes.c_int * max(1, self.count))()
         _check(load().gfq_batch_slab_widths(self.handle, out), "gfq_batch_slab_widths")
+        return list(out)[: self.count]
+
+    def slices(self):
+        """The number of slab slices the batch cut each product into (1: whole tiles)."""
+        out = (ctypes.c_int * max(1, self.count))()
+        _check(load().gfq_batch_slices(self.handle, out), "gfq_batch_slices")
         return list(out)[: self.count]
 
     def destroy(self):

@@ -1,15 +1,21 @@
 // Host-side paths of the C ABI, run without a GPU (built with AddressSanitizer and
 // UndefinedBehaviorSanitizer on the host code of the library): the tuning-cache text parser
-// and writer, configuration choice, and every argument check that rejects a call before
-// anything is launched.  Prints "ok <name>" per group, or "FAIL ..." and exits 1.
+// and writer, configuration choice, every argument check that rejects a call before
+// anything is launched, and batch planning (every tile and slab slice exactly once, the
+// partial-sum items covering each sliced product, disjoint partial products).  Prints
+// "ok <name>" per group, or "FAIL ..." and exits 1.
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "gfq.h"
+#include "gfq_host.h"
 
 static void expect(bool ok, const char *what, long long a = 0) {
     if (!ok) {
@@ -122,6 +128,7 @@ int main() {
     expect(gfq_batch_create(2, probs, &bt) == GFQ_EALIAS && bt == nullptr, "batch create rejects");
     expect(gfq_batch_launch(nullptr) == GFQ_ENULL, "batch launch null");
     expect(gfq_batch_slab_widths(nullptr, nullptr) == GFQ_ENULL, "batch widths null");
+    expect(gfq_batch_slices(nullptr, nullptr) == GFQ_ENULL, "batch slices null");
     expect(gfq_server_submit(nullptr, nullptr, 1) == GFQ_ENULL, "server null");
     int got = 0;
     expect(gfq_server_poll(nullptr, nullptr, 1, &got, 0) == GFQ_ENULL, "server poll null");
@@ -139,6 +146,85 @@ int main() {
     expect(gfq_probe_valu(0, 1, (uint32_t *)A, &amount, &ms) == GFQ_EINVAL, "probe blocks");
     for (int s = -12; s <= 1; s++) expect(gfq_strerror(s) != nullptr && gfq_strerror(s)[0] != 0, "strerror", s);
     printf("ok validation\n");
+    // ---- batch planning: items, slab slices, partial-sum items (no device: default configs) ----
+    {
+        static unsigned char mem[1 << 12];
+        auto plan_check = [&](const std::vector<gfq_problem> &probs, bool slice, int *sliced) {
+            const int count = (int)probs.size();
+            std::vector<gfq::BatchProd> prods(count);
+            std::vector<gfq::BatchGroup> groups;
+            size_t nitems = 0;
+            gfq::BatchSlicing sl;
+            gfq::plan_batch(count, probs.data(), nullptr, prods.data(), &groups, &nitems, slice ? &sl : nullptr);
+            // every (product, tile, slice) exactly once, each list's items contiguous
+            std::map<std::tuple<unsigned, int, int, unsigned>, int> seen;
+            size_t off = 0;
+            for (const gfq::BatchGroup &g : groups) {
+                expect(g.item_off == off, "group offsets consecutive", (long long)off);
+                off += g.items.size();
+                for (const gfq::BatchItem &it : g.items) {
+                    expect(it.prod < (unsigned)count && it.slice < prods[it.prod].slices, "item in range", it.prod);
+                    expect(seen[std::make_tuple(it.prod, (int)it.tx, (int)it.ty, it.slice)]++ == 0, "item once", it.prod);
+                }
+            }
+            expect(off == nitems, "item count", (long long)nitems);
+            *sliced = 0;
+            std::vector<long long> reduce_units(count, 0), covered(count, 0);
+            for (const gfq::ReduceItem &r : sl.reduce) {
+                expect(r.prod < (unsigned)count && prods[r.prod].slices > 1, "reduce item of a sliced product", r.prod);
+                expect(r.first == (unsigned)covered[r.prod], "reduce items contiguous", r.prod);
+                covered[r.prod] += r.count;
+                reduce_units[r.prod]++;
+            }
+            std::vector<std::pair<size_t, size_t>> spans;
+            for (int i = 0; i < count; i++) {
+                const gfq::BatchProd &bp = prods[i];
+                const gfq::MMArgs &a = bp.a;
+                long long tiles = 0;
+                for (auto &kv : seen)
+                    if (std::get<0>(kv.first) == (unsigned)i && std::get<3>(kv.first) == 0) tiles++;
+                expect(bp.units == tiles * bp.slices + reduce_units[i], "units", i);
+                if (bp.slices > 1) {
+                    ++*sliced;
+                    expect(slice, "sliced only when asked", i);
+                    expect(a.slabs_per_split >= 8 && bp.slices <= 64, "slice bounds", a.slabs_per_split);
+                    expect((long long)a.slabs_per_split * (bp.slices - 1) < a.S && (long long)a.slabs_per_split * bp.slices >= a.S,
+                           "slices cover the slabs", i);
+                    expect(covered[i] == (long long)a.m * (a.Wn / 4), "partial sums cover C", i);
+                    expect(a.split_stride == (size_t)a.m * gfq::planes_of(bp.q) * a.Wn, "partial stride", i);
+                    spans.push_back(std::make_pair(sl.part_off[i], sl.part_off[i] + bp.slices * a.split_stride));
+                } else {
+                    expect(a.slabs_per_split >= a.S, "a whole product has one slice", i);
+                }
+            }
+            std::sort(spans.begin(), spans.end());
+            for (size_t j = 0; j < spans.size(); j++) {
+                expect(spans[j].second <= sl.partial_words, "partials inside the workspace", (long long)j);
+                if (j) expect(spans[j - 1].second <= spans[j].first, "partials disjoint", (long long)j);
+            }
+        };
+        std::vector<gfq_problem> probs;
+        // long inner dimensions, few tiles each: sliced
+        for (int q : {3, 4, 5, 7, 8, 9}) probs.push_back(gfq_problem{q, 300, 20000, 700, mem, mem, mem});
+        // and some small products beside them
+        for (int i = 0; i < 40; i++) probs.push_back(gfq_problem{3 + (i % 2) * 2, 64 + i, 100 + 7 * i, 33 + 5 * i, mem, mem, mem});
+        int sliced = 0;
+        plan_check(probs, true, &sliced);
+        expect(sliced == 6, "the six long products sliced", sliced);
+        plan_check(probs, false, &sliced);
+        expect(sliced == 0, "no slices without slicing", sliced);
+        // many products of similar size: none sliced
+        std::vector<gfq_problem> even;
+        for (int i = 0; i < 512; i++) even.push_back(gfq_problem{7, 512, 512, 512, mem, mem, mem});
+        plan_check(even, true, &sliced);
+        expect(sliced == 0, "an even batch is not sliced", sliced);
+        // degenerate products beside a sliced one
+        std::vector<gfq_problem> degen = {{5, 0, 9000, 64, mem, mem, mem}, {5, 64, 0, 64, mem, mem, mem},
+                                          {5, 64, 9000, 0, mem, mem, mem}, {5, 64, 9000, 64, mem, mem, mem}};
+        plan_check(degen, true, &sliced);
+        expect(sliced == 1, "one of four sliced", sliced);
+        printf("ok plan_batch\n");
+    }
     printf("ok all\n");
     return 0;
 }

@@ -1,7 +1,7 @@
 """Batched products (one work-list launch per field and tile shape, workgroups taking
-(product, row tile, column tile) items longest first): every product of a mixed batch
-against the oracle and against the same product launched alone (bit-exact), graph replays,
-degenerate products."""
+(product, row tile, column tile, slab slice) items longest first, and a partial-sum launch for
+sliced products): every product of a mixed batch against the oracle and against the same
+product launched alone (bit-exact), graph replays, degenerate products, slab slices."""
 import numpy as np
 import pytest
 
@@ -159,3 +159,27 @@ def test_batch_narrow_tiles(gfq_gpu):
     g.matmul_batched(probs)
     g.sync()
     check_against_oracle_and_alone(g, probs, host, range(len(specs)))
+
+
+def test_batch_slab_slices(gfq_gpu):
+    """Products with few tiles and a long inner dimension (300 x 20000 x 700, every field) are
+    cut into slab slices whose partial products a partial-sum launch adds; the small products
+    beside them stay whole.  Every product against the oracle and its single launch, on two
+    launches of the batch, with completion times."""
+    g = gfq_gpu
+    specs = [(q, 300, 20000, 700) for q in (3, 4, 5, 7, 8, 9)]
+    specs += [(3 + (i % 2) * 2, 64 + i, 100 + 7 * i, 33 + 5 * i) for i in range(40)]
+    probs, host = make_batch(g, specs, 330)
+    b = g.Batch(probs)
+    slices = b.slices()
+    assert all(s > 1 for s in slices[:6]), slices[:6]
+    assert all(s == 1 for s in slices[6:]), slices[6:]
+    for rep in range(2):
+        for (*_, C) in probs:
+            C.fill_(0x33)
+        b.launch()
+        g.sync()
+        t = b.times_us()
+        assert all(x > 0 for x in t), t
+        check_against_oracle_and_alone(g, probs, host, range(len(specs)))
+    b.destroy()

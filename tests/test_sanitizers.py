@@ -102,3 +102,4 @@ def test_library_host_code_asan_ubsan(tmp_path):
     out = run(exe, env=env)
     assert out.splitlines()[-1] == "ok all"
     assert "ok tune_cache" in out and "ok choose_config" in out and "ok validation" in out
+    assert "ok plan_batch" in out
