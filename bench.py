@@ -814,6 +814,29 @@ def section_c4(ctx, count=4096, reps=5, pool=2048):
     graph.replay()
     torch.cuda.synchronize()
     done_us = sorted(b.times_us())
+    want = [C.clone() for (*_, C) in probs]
+
+    # the same items drained by persistent workgroups through a device queue head, captured
+    # the same way
+    pgraph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        b.launch_persistent()
+        side.synchronize()
+        with torch.cuda.graph(pgraph, stream=side):
+            b.launch_persistent()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    for (*_, C) in probs:
+        C.zero_()
+    warm(torch, pgraph.replay)
+    ev[0].record()
+    for _ in range(reps):
+        pgraph.replay()
+    ev[1].record()
+    torch.cuda.synchronize()
+    persistent_ms = ev[0].elapsed_time(ev[1]) / reps
+    persistent_same = all(torch.equal(w, C) for w, (*_, C) in zip(want, probs))
+    del pgraph
 
     def plain():
         for (q, m, l, n, A, B, _), C in zip(probs, plain_out):
@@ -854,6 +877,7 @@ def section_c4(ctx, count=4096, reps=5, pool=2048):
             "field_ops": ops,
             "batched_ms": round(batched_ms, 4), "batched_field_ops_per_s": ops / (batched_ms * 1e-3),
             "batched_launch": "work lists per (field, tile height), captured in one HIP graph",
+            "persistent_ms": round(persistent_ms, 4), "persistent_equals_worklist": persistent_same,
             "plain_ms": round(plain_ms, 4), "plain_field_ops_per_s": ops / (plain_ms * 1e-3),
             "speedup": round(plain_ms / batched_ms, 2),
             "completion_p50_us": round(percentile(done_us, 50), 1),
@@ -893,6 +917,15 @@ def section_c4_slices(ctx, per_field=16, shape=(512, 16384, 512), reps=10, sampl
     batched_ms = ev[0].elapsed_time(ev[1]) / reps
     done_us = sorted(b.times_us())
     got = [gfq.unpack(q, C, m, n).cpu().numpy() for (q, _, _, _, _, _, C) in probs]
+    want = [C.clone() for (*_, C) in probs]
+    warm(torch, b.launch_persistent)
+    ev[0].record()
+    for _ in range(reps):
+        b.launch_persistent()
+    ev[1].record()
+    torch.cuda.synchronize()
+    persistent_ms = ev[0].elapsed_time(ev[1]) / reps
+    persistent_same = all(torch.equal(w, C) for w, (*_, C) in zip(want, probs))
     plain_out = [gfq.empty_packed(q, m, n) for (q, _, _, _) in specs]
 
     def plain():
@@ -917,6 +950,7 @@ def section_c4_slices(ctx, per_field=16, shape=(512, 16384, 512), reps=10, sampl
             "batched_ms": round(batched_ms, 4), "batched_field_ops_per_s": ops / (batched_ms * 1e-3),
             "plain_ms": round(plain_ms, 4), "plain_field_ops_per_s": ops / (plain_ms * 1e-3),
             "speedup": round(plain_ms / batched_ms, 2), "slices": sorted(set(slices)),
+            "persistent_ms": round(persistent_ms, 4), "persistent_equals_worklist": persistent_same,
             "completion_p50_us": round(percentile(done_us, 50), 1),
             "completion_p99_us": round(percentile(done_us, 99), 1),
             "batched_equals_plain": same, "sampled_rows_bit_exact": bool(ok), "sampled_rows": sample_rows}

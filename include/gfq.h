@@ -226,6 +226,14 @@ int gfq_matmul_batched(int count, const gfq_problem *problems);
 typedef struct gfq_batch gfq_batch;
 int gfq_batch_create(int count, const gfq_problem *problems, gfq_batch **out);
 int gfq_batch_launch(gfq_batch *batch);
+/* The same batch drained by persistent workgroups: per list, a reset of its queue head, then
+ * as many workgroups as the device holds at once (at most one per item), each taking the
+ * next item index from the head with an atomic add, publishing it to its threads through
+ * workgroup memory between two barriers, and leaving when the index passes the end (Section
+ * 2's items, same results as gfq_batch_launch byte for byte).  Streams, side streams,
+ * capture, partial sums, completion stamps and the no-overlap rule as for gfq_batch_launch;
+ * it allocates nothing.  GFQ_EINVAL if the batch has more than 64 lists. */
+int gfq_batch_launch_persistent(gfq_batch *batch);
 int gfq_batch_times(gfq_batch *batch, double *completion_us);
 /* The slab width k the batch gives each product (host array of count ints; the work the
  * method does per product, Section 2, depends on it). */

@@ -52,6 +52,15 @@ struct ReduceList {
 // tile.
 const void *batched_kernel(int q, int R, int twd);
 hipError_t launch_batched(int q, int R, int twd, const BatchList &bl, int items, size_t lds, hipStream_t st);
+// The same lists drained by persistent workgroups (gfq_drain.h): `workgroups` of them take
+// items in list order from the queue head *head, which launch_queue_reset zeroes (up to 64
+// heads) and which must be zero when the launch starts.  Dynamic LDS: the list's plus one
+// 16-byte slot for the published index (queue_lds).
+const void *queue_kernel(int q, int R, int twd);
+inline size_t queue_lds(size_t lds) { return ((lds + 15) & ~(size_t)15) + 16; }
+hipError_t launch_queue(int q, int R, int twd, const BatchList &bl, int items, size_t lds, u32 *head, int workgroups,
+                        hipStream_t st);
+hipError_t launch_queue_reset(u32 *heads, int n, hipStream_t st);
 // The partial sums of every sliced product of a batch: one workgroup per item, any fields.
 hipError_t launch_reduce_list(const ReduceList &rl, int items, hipStream_t st);
 hipError_t launch_batch_stamp(unsigned long long *t, hipStream_t st);

@@ -18,15 +18,20 @@
 #include "gfq_batch.h"
 #include "gfq_m4rm_tile.h"
 #include "gfq_reduce.h"
+#define GFQ_DRAIN_FN __device__ __forceinline__
+#include "gfq_drain.h"
 
 namespace gfq {
 
+
+// One item of a work list: the tile, then (after every thread has stored) the product's
+// completion count and stamp.
 template <int Q, int TWD, int REP, int R, int NT>
-__global__ __launch_bounds__(NT) void m4rm_list_kernel(BatchList bl) {
-    const BatchItem item = bl.items[blockIdx.x];
+__device__ __forceinline__ void run_item(const BatchList &bl, u32 i) {
+    const BatchItem item = bl.items[i];
     const MMArgs a = bl.prods[item.prod].a;
     m4rm_tile<Q, TWD, REP, R, NT>(a, item.tx, item.ty, (int)item.slice);
-    __syncthreads();                             // every thread of the tile has stored
+    __syncthreads();
     if (threadIdx.x == 0) {
         const u32 d = atomicAdd(&bl.prod_done[item.prod], 1u);
         if (d + 1 == bl.prods[item.prod].units) {
@@ -34,6 +39,47 @@ __global__ __launch_bounds__(NT) void m4rm_list_kernel(BatchList bl) {
             bl.prod_done[item.prod] = 0u;
         }
     }
+}
+
+template <int Q, int TWD, int REP, int R, int NT>
+__global__ __launch_bounds__(NT) void m4rm_list_kernel(BatchList bl) {
+    run_item<Q, TWD, REP, R, NT>(bl, blockIdx.x);
+}
+
+// The persistent workgroup's side of the drain loop (gfq_drain.h): the barrier, an LDS word
+// past the tile's buffers for the published index, and the list's queue head.
+template <int Q, int TWD, int REP, int R, int NT>
+struct QueueCtx {
+    const BatchList &bl;
+    u32 *head;
+    u32 *slot;
+    // the first wave, by a value the compiler knows to be uniform
+    __device__ bool leader() const { return __builtin_amdgcn_readfirstlane(threadIdx.x / 64u) == 0u; }
+    __device__ void barrier() { __syncthreads(); }
+    // every lane of the wave adds (lane 0 adds 1, the others 0), so no lane branches; lane 0's
+    // result is the ticket
+    __device__ u32 fetch_head() {
+        const u32 r = atomicAdd(head, (threadIdx.x & 63u) == 0u ? 1u : 0u);
+        return __builtin_amdgcn_readlane(r, 0);
+    }
+    __device__ void slot_store(u32 v) { *slot = v; }
+    __device__ u32 slot_load() { return *slot; }
+    __device__ u32 uniform(u32 v) { return __builtin_amdgcn_readfirstlane(v); }
+    __device__ void run(u32 i) { run_item<Q, TWD, REP, R, NT>(bl, i); }
+};
+
+// Persistent workgroups (as many as the device holds at once) draining the list's items in
+// order: workgroup w takes the next index from the queue head until the list is exhausted.
+// The head is zeroed by queue_reset_kernel before every launch.
+template <int Q, int TWD, int REP, int R, int NT>
+__global__ __launch_bounds__(NT) void m4rm_queue_kernel(BatchList bl, u32 items, u32 *head, u32 slot_off) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    QueueCtx<Q, TWD, REP, R, NT> c{bl, head, reinterpret_cast<u32 *>(smem + slot_off)};
+    drain_queue(c, items);
+}
+
+__global__ void queue_reset_kernel(u32 *heads, int n) {
+    if ((int)threadIdx.x < n) heads[threadIdx.x] = 0u;
 }
 
 // Partial sums of sliced products: item b adds the slices of its groups into C; the item
@@ -72,43 +118,67 @@ __global__ void batch_stamp_kernel(unsigned long long *t) {
     if (threadIdx.x == 0) t[0] = __builtin_amdgcn_s_memrealtime();
 }
 
-template <int Q, int R, int REP = 4>
+template <bool QUEUE, int Q, int TWD, int REP, int R>
+static const void *kernel_ptr() {
+    return QUEUE ? (const void *)m4rm_queue_kernel<Q, TWD, REP, R, NT_MM> : (const void *)m4rm_list_kernel<Q, TWD, REP, R, NT_MM>;
+}
+
+template <bool QUEUE, int Q, int R, int REP = 4>
 static const void *list_kernel_ptr() {
-    return (const void *)m4rm_list_kernel<Q, 16, REP, R, NT_MM>;
+    return kernel_ptr<QUEUE, Q, 16, REP, R>();
 }
 
 // narrow tiles: two rows per lane, TWD words per plane, 64 / TWD copies per 256-byte super-row
-template <int Q>
+template <bool QUEUE, int Q>
 static const void *narrow_kernel_ptr(int twd) {
-    return twd == 8 ? (const void *)m4rm_list_kernel<Q, 8, 8, 2, NT_MM> : (const void *)m4rm_list_kernel<Q, 4, 16, 2, NT_MM>;
+    return twd == 8 ? kernel_ptr<QUEUE, Q, 8, 8, 2>() : kernel_ptr<QUEUE, Q, 4, 16, 2>();
 }
 
-const void *batched_kernel(int q, int R, int twd) {
+template <bool QUEUE>
+static const void *kernel_for(int q, int R, int twd) {
     if (twd != 16) {
         switch (q) {
-        case 3: return narrow_kernel_ptr<3>(twd);
-        case 4: return narrow_kernel_ptr<4>(twd);
-        case 5: return narrow_kernel_ptr<5>(twd);
-        case 8: return narrow_kernel_ptr<8>(twd);
-        case 9: return narrow_kernel_ptr<9>(twd);
-        default: return narrow_kernel_ptr<7>(twd);
+        case 3: return narrow_kernel_ptr<QUEUE, 3>(twd);
+        case 4: return narrow_kernel_ptr<QUEUE, 4>(twd);
+        case 5: return narrow_kernel_ptr<QUEUE, 5>(twd);
+        case 8: return narrow_kernel_ptr<QUEUE, 8>(twd);
+        case 9: return narrow_kernel_ptr<QUEUE, 9>(twd);
+        default: return narrow_kernel_ptr<QUEUE, 7>(twd);
         }
     }
     switch (q) {
-    case 3: return R == 2 ? list_kernel_ptr<3, 2>() : list_kernel_ptr<3, 8>();
-    case 4: return R == 2 ? list_kernel_ptr<4, 2>() : list_kernel_ptr<4, 8>();
-    case 5: return R == 2 ? list_kernel_ptr<5, 2>() : list_kernel_ptr<5, 4, 1>();   // batch_srb: 64 at R = 4
-    case 8: return R == 2 ? list_kernel_ptr<8, 2>() : list_kernel_ptr<8, 8>();
-    case 9: return R == 2 ? list_kernel_ptr<9, 2>() : list_kernel_ptr<9, 4>();
-    default: return R == 2 ? list_kernel_ptr<7, 2>() : list_kernel_ptr<7, 4, 1>();   // batch_srb: 64 at R = 4
+    case 3: return R == 2 ? list_kernel_ptr<QUEUE, 3, 2>() : list_kernel_ptr<QUEUE, 3, 8>();
+    case 4: return R == 2 ? list_kernel_ptr<QUEUE, 4, 2>() : list_kernel_ptr<QUEUE, 4, 8>();
+    case 5: return R == 2 ? list_kernel_ptr<QUEUE, 5, 2>() : list_kernel_ptr<QUEUE, 5, 4, 1>();   // batch_srb: 64 at R = 4
+    case 8: return R == 2 ? list_kernel_ptr<QUEUE, 8, 2>() : list_kernel_ptr<QUEUE, 8, 8>();
+    case 9: return R == 2 ? list_kernel_ptr<QUEUE, 9, 2>() : list_kernel_ptr<QUEUE, 9, 4>();
+    default: return R == 2 ? list_kernel_ptr<QUEUE, 7, 2>() : list_kernel_ptr<QUEUE, 7, 4, 1>();   // batch_srb: 64 at R = 4
     }
 }
+
+const void *batched_kernel(int q, int R, int twd) { return kernel_for<false>(q, R, twd); }
+const void *queue_kernel(int q, int R, int twd) { return kernel_for<true>(q, R, twd); }
 
 hipError_t launch_batched(int q, int R, int twd, const BatchList &bl, int items, size_t lds, hipStream_t st) {
     const void *k = batched_kernel(q, R, twd);
     if (!k) return hipErrorInvalidValue;
     void *args[] = {(void *)&bl};
     return hipLaunchKernel(k, dim3(items), dim3(NT_MM), args, lds, st);
+}
+
+hipError_t launch_queue(int q, int R, int twd, const BatchList &bl, int items, size_t lds, u32 *head, int workgroups,
+                        hipStream_t st) {
+    const void *k = queue_kernel(q, R, twd);
+    if (!k || workgroups < 1) return hipErrorInvalidValue;
+    u32 n = (u32)items, slot_off = (u32)((lds + 15) & ~(size_t)15);
+    void *args[] = {(void *)&bl, (void *)&n, (void *)&head, (void *)&slot_off};
+    return hipLaunchKernel(k, dim3(workgroups), dim3(NT_MM), args, queue_lds(lds), st);
+}
+
+hipError_t launch_queue_reset(u32 *heads, int n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, st, heads, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_reduce_list(const ReduceList &rl, int items, hipStream_t st) {

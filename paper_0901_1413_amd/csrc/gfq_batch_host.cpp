@@ -203,7 +203,8 @@ void gfq::plan_batch(int count, const gfq_problem *problems, const gfq_config *c
     *nitems = n;
 }
 
-hipError_t gfq::launch_group_lists(const std::vector<BatchGroup> &groups, const BatchList &base, hipStream_t st) {
+hipError_t gfq::launch_group_lists(const std::vector<BatchGroup> &groups, const BatchList &base, hipStream_t st,
+                                   u32 *queue_heads) {
     const size_t ng = groups.size();
     SidePool *sp = ng > 1 ? side_pool(st, ng - 1) : nullptr;
     hipError_t e = sp ? hipEventRecord(sp->fork, st) : hipSuccess;
@@ -214,7 +215,10 @@ hipError_t gfq::launch_group_lists(const std::vector<BatchGroup> &groups, const 
         if (side) e = hipStreamWaitEvent(s, sp->fork, 0);
         BatchList l = base;
         l.items = base.items + gr.item_off;
-        if (e == hipSuccess) e = launch_batched(gr.q, gr.R, gr.twd, l, (int)gr.items.size(), gr.lds, s);
+        if (e == hipSuccess)
+            e = queue_heads ? launch_queue(gr.q, gr.R, gr.twd, l, (int)gr.items.size(), gr.lds, queue_heads + j,
+                                           gr.queue_wgs, s)
+                            : launch_batched(gr.q, gr.R, gr.twd, l, (int)gr.items.size(), gr.lds, s);
         if (e == hipSuccess && side) e = hipEventRecord(sp->done[j - 1], s);
     }
     for (size_t j = 1; e == hipSuccess && sp && j < ng; j++) e = hipStreamWaitEvent(st, sp->done[j - 1], 0);
@@ -231,6 +235,8 @@ hipError_t gfq::set_batched_lds_limits() {
         for (int R : {2, max_rows_per_lane_batch(q)}) {
             const size_t lds = mm_lds_bytes(q, batch_kmax(q, R), batch_srb(q, R), NT_MM / 4 * R, nullptr);
             hipError_t e = hipFuncSetAttribute(batched_kernel(q, R, 16), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e == hipSuccess)
+                e = hipFuncSetAttribute(queue_kernel(q, R, 16), hipFuncAttributeMaxDynamicSharedMemorySize, (int)queue_lds(lds));
             if (e != hipSuccess) return e;
         }
         for (int twd : {8, 4}) {
@@ -238,6 +244,9 @@ hipError_t gfq::set_batched_lds_limits() {
             if (!k) continue;
             const size_t lds = mm_lds_bytes(q, batch_kmax(q, 2), 256, NT_MM / (twd / 4) * 2, nullptr);
             hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e == hipSuccess)
+                e = hipFuncSetAttribute(queue_kernel(q, 2, twd), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)queue_lds(lds));
             if (e != hipSuccess) return e;
         }
     }
@@ -255,6 +264,7 @@ struct gfq_batch {
     unsigned long long *times = nullptr;   // [0] start, [1 + p] completion of product p
     ReduceItem *ritems = nullptr;          // partial-sum items of the sliced products
     int nritems = 0;
+    u32 *heads = nullptr;                  // queue head of each list (persistent launches)
     std::vector<int> k;                    // slab width of each product
     std::vector<int> slices;               // slab slices of each product
 };
@@ -302,7 +312,8 @@ int gfq::batch_create_with(int count, const gfq_problem *problems, const gfq_con
     const size_t nr = sl.reduce.size();
     const size_t off_items = align(sizeof(BatchProd) * std::max(count, 1));
     const size_t off_ritems = off_items + align(sizeof(BatchItem) * std::max<size_t>(nitems, 1));
-    const size_t off_done = off_ritems + align(sizeof(ReduceItem) * std::max<size_t>(nr, 1));
+    const size_t off_heads = off_ritems + align(sizeof(ReduceItem) * std::max<size_t>(nr, 1));
+    const size_t off_done = off_heads + align(sizeof(u32) * 64);
     const size_t off_time = off_done + align(sizeof(u32) * std::max(count, 1));
     const size_t off_part = off_time + align(sizeof(unsigned long long) * (count + 1));
     const size_t total = off_part + align(sl.partial_words * sizeof(u32));
@@ -319,10 +330,19 @@ int gfq::batch_create_with(int count, const gfq_problem *problems, const gfq_con
     if (e == hipSuccess && nr > 0)
         e = hipMemcpy(base + off_ritems, sl.reduce.data(), sizeof(ReduceItem) * nr, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = set_batched_lds_limits();
+    // persistent workgroups per list: as many as the device holds at once, at most one per item
+    for (BatchGroup &gr : b->groups) {
+        if (e != hipSuccess) break;
+        int per_cu = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, queue_kernel(gr.q, gr.R, gr.twd), NT_MM,
+                                                         queue_lds(gr.lds));
+        gr.queue_wgs = (int)std::min<size_t>((size_t)std::max(per_cu, 1) * sl.cus, gr.items.size());
+    }
     if (e != hipSuccess) { batch_release(b); return hip_fail(e, "batch upload"); }
     b->prods = (BatchProd *)base;
     b->items = (BatchItem *)(base + off_items);
     b->ritems = (ReduceItem *)(base + off_ritems);
+    b->heads = (u32 *)(base + off_heads);
     b->nritems = (int)nr;
     b->prod_done = (u32 *)(base + off_done);
     b->times = (unsigned long long *)(base + off_time);
@@ -355,6 +375,29 @@ int gfq_batch_launch(gfq_batch *b) {
         e = launch_reduce_list(rl, b->nritems, st);
     }
     return e == hipSuccess ? GFQ_OK : hip_fail(e, "batch launch");
+}
+
+int gfq_batch_launch_persistent(gfq_batch *b) {
+    if (!b) return GFQ_ENULL;
+    if (b->groups.size() > 64) return GFQ_EINVAL;
+    hipStream_t st = current_stream();
+    hipError_t e = launch_batch_stamp(b->times, st);
+    if (e == hipSuccess) e = launch_queue_reset(b->heads, (int)b->groups.size(), st);
+    BatchList base;
+    base.prods = b->prods;
+    base.items = b->items;
+    base.prod_done = b->prod_done;
+    base.prod_time = b->times + 1;
+    if (e == hipSuccess) e = launch_group_lists(b->groups, base, st, b->heads);
+    if (e == hipSuccess && b->nritems > 0) {
+        ReduceList rl;
+        rl.prods = b->prods;
+        rl.items = b->ritems;
+        rl.prod_done = b->prod_done;
+        rl.prod_time = b->times + 1;
+        e = launch_reduce_list(rl, b->nritems, st);
+    }
+    return e == hipSuccess ? GFQ_OK : hip_fail(e, "persistent batch launch");
 }
 
 int gfq_batch_times(gfq_batch *b, double *completion_us) {

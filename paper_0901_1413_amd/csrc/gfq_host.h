@@ -22,6 +22,7 @@ struct BatchGroup {
     int q = 0, R = 0, twd = 16, kmax = 1;
     size_t lds = 0;                  // dynamic LDS of the list's launch
     size_t item_off = 0;             // index of the group's first item in the batch's item array
+    int queue_wgs = 0;               // persistent workgroups of the list's queue launch
     std::vector<BatchItem> items;    // longest first
     std::vector<double> cost;        // planning only
 };
@@ -43,8 +44,10 @@ void plan_batch(int count, const gfq_problem *problems, const gfq_config *cfgs, 
                 std::vector<BatchGroup> *groups, size_t *nitems, BatchSlicing *slicing = nullptr);
 // Launch every group's work list: the first on st, the others forked onto side streams of
 // st and joined back into it (one after another on st while st is captured and has no side
-// streams yet).  base: the batch's lists with items pointing at item 0.
-hipError_t launch_group_lists(const std::vector<BatchGroup> &groups, const BatchList &base, hipStream_t st);
+// streams yet).  base: the batch's lists with items pointing at item 0.  With queue_heads
+// (one zeroed head per group), each list is drained by its persistent workgroups instead.
+hipError_t launch_group_lists(const std::vector<BatchGroup> &groups, const BatchList &base, hipStream_t st,
+                              u32 *queue_heads = nullptr);
 // Upper bound of the tiles of an m x n product in any batch (the smallest tile height).
 size_t batch_tiles_bound(int64_t m, int64_t n);
 // Allow every batched work-list kernel the dynamic LDS of its largest slab width.

@@ -82,6 +82,7 @@ _SIGS = {
     "gfq_batch_destroy": (ctypes.c_int, [_VP]),
     "gfq_batch_slab_widths": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int)]),
     "gfq_batch_slices": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int)]),
+    "gfq_batch_launch_persistent": (ctypes.c_int, [_VP]),
     "gfq_tune": (ctypes.c_int, [ctypes.c_int, _I64, _I64, _I64, ctypes.c_int, ctypes.POINTER(Config)]),
     "gfq_tune_lookup": (ctypes.c_int, [ctypes.c_int, _I64, _I64, _I64, ctypes.c_int, ctypes.POINTER(Config)]),
     "gfq_tune_save": (ctypes.c_int, [ctypes.c_char_p]),
@@ -298,6 +299,11 @@ class Batch:
     def launch(self):
         _bind_stream()
         _check(load().gfq_batch_launch(self.handle), "gfq_batch_launch")
+
+    def launch_persistent(self):
+        """The same items drained by persistent workgroups through a device queue head."""
+        _bind_stream()
+        _check(load().gfq_batch_launch_persistent(self.handle), "gfq_batch_launch_persistent")
 
     def times_us(self):
         """Per-product completion time of the last launch, microseconds from its start."""

@@ -127,6 +127,7 @@ int main() {
     gfq_batch *bt = nullptr;
     expect(gfq_batch_create(2, probs, &bt) == GFQ_EALIAS && bt == nullptr, "batch create rejects");
     expect(gfq_batch_launch(nullptr) == GFQ_ENULL, "batch launch null");
+    expect(gfq_batch_launch_persistent(nullptr) == GFQ_ENULL, "persistent batch launch null");
     expect(gfq_batch_slab_widths(nullptr, nullptr) == GFQ_ENULL, "batch widths null");
     expect(gfq_batch_slices(nullptr, nullptr) == GFQ_ENULL, "batch slices null");
     expect(gfq_server_submit(nullptr, nullptr, 1) == GFQ_ENULL, "server null");

@@ -183,3 +183,68 @@ def test_batch_slab_slices(gfq_gpu):
         assert all(x > 0 for x in t), t
         check_against_oracle_and_alone(g, probs, host, range(len(specs)))
     b.destroy()
+
+
+def test_batch_persistent_matches_worklist(gfq_gpu):
+    """The same batch drained by persistent workgroups through a device queue head: every
+    product equals the work-list launch's byte for byte and the oracle, on three launches in a
+    row (the head is reset by each launch), including sliced products and their partial sums."""
+    import torch
+    g = gfq_gpu
+    rng = np.random.default_rng(340)
+    specs = [(int(rng.choice([3, 4, 5, 7, 8, 9])),) + tuple(int(x) for x in rng.integers(1, 600, size=3))
+             for _ in range(40)]
+    specs += [(3, 300, 9000, 700), (7, 200, 9000, 300), (4, 2048, 64, 1000), (5, 1025, 33, 7)]
+    probs, host = make_batch(g, specs, 341)
+    b = g.Batch(probs)
+    b.launch()
+    g.sync()
+    want = [C.clone() for (*_, C) in probs]
+    for rep in range(3):
+        for (*_, C) in probs:
+            C.fill_(0x77)
+        b.launch_persistent()
+        g.sync()
+        for i, (w, (*_, C)) in enumerate(zip(want, probs)):
+            assert torch.equal(w, C), (rep, i, specs[i])
+        t = b.times_us()
+        assert all(x > 0 for x in t), (rep, t)
+    check_against_oracle_and_alone(g, probs, host, range(0, len(specs), 3))
+    b.destroy()
+
+
+def test_batch_persistent_graph_capture(gfq_gpu):
+    """A persistent launch captured into a graph (the lists as parallel branches): every replay,
+    with eager work in between, equals the work-list launch."""
+    import torch
+    g = gfq_gpu
+    specs = [(3, 300, 200, 100), (5, 64, 64, 64), (7, 1000, 900, 130), (4, 513, 127, 511), (5, 700, 1500, 900)]
+    probs, host = make_batch(g, specs, 342)
+    b = g.Batch(probs)
+    b.launch()
+    g.sync()
+    want = [C.clone() for (*_, C) in probs]
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        b.launch_persistent()
+        side.synchronize()
+        with torch.cuda.graph(graph, stream=side):
+            b.launch_persistent()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    Ao, Bo = inputs.pair(3, 64, 64, 64, cfg=342, idx=99)
+    Aop, Bop = g.pack(3, dev(Ao)), g.pack(3, dev(Bo))
+    other = g.empty_packed(3, 64, 64)
+    for rep in range(3):
+        for (*_, C) in probs:
+            C.zero_()
+        g.matmul(3, Aop, Bop, 64, 64, 64, out=other)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for i, (w, (*_, C)) in enumerate(zip(want, probs)):
+            assert torch.equal(w, C), (rep, i)
+    del graph
+    b.destroy()

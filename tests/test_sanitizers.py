@@ -9,7 +9,7 @@
   sanitizers and its kernel objects as built).
 - ThreadSanitizer: the server's worker core with four submitting threads and a polling
   thread against the fake executor, including a failed launch and a batch that never
-  completes (the watchdog).
+  completes (the watchdog); the persistent workgroups' drain loop (drain_host_check.cpp).
 """
 import glob
 import os
@@ -45,13 +45,13 @@ def test_oracle_asan_ubsan(tmp_path):
 
 
 @pytest.mark.parametrize("src", ["sched_host_check.cpp", "server_host_check.cpp", "field_host_check.cpp",
-                                 "sw_host_check.cpp"])
+                                 "sw_host_check.cpp", "drain_host_check.cpp"])
 def test_host_checks_asan_ubsan(tmp_path, src):
     exe = str(tmp_path / src.replace(".cpp", ""))
     subprocess.check_call(["g++", "-std=c++17", "-pthread", "-Wall", "-Werror", "-Wno-unknown-pragmas", *ASAN, "-I", CSRC,
                            os.path.join(TESTS, src), "-o", exe])
     out = run(exe)
-    if src in ("sched_host_check.cpp", "server_host_check.cpp"):
+    if src in ("sched_host_check.cpp", "server_host_check.cpp", "drain_host_check.cpp"):
         assert out.splitlines()[-1] == "ok all"
 
 
@@ -63,6 +63,17 @@ def test_server_core_tsan(tmp_path):
     out = run(exe, env=env)
     assert out.splitlines()[-1] == "ok all"
     assert "ok watchdog" in out and "ok launch_failure" in out and out.count("ok traffic") == 2
+
+
+def test_drain_loop_tsan(tmp_path):
+    """The persistent workgroups' drain loop (the device kernel's own code, gfq_drain.h) on
+    host threads under ThreadSanitizer: the published index is ordered by the barriers."""
+    exe = str(tmp_path / "drain_host_check_tsan")
+    subprocess.check_call([CLANGXX, "-std=c++17", "-pthread", "-Wall", "-Werror", "-fsanitize=thread", "-g", "-O1",
+                           "-I", CSRC, os.path.join(TESTS, "drain_host_check.cpp"), "-o", exe])
+    env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1")
+    out = run(exe, env=env)
+    assert out.splitlines()[-1] == "ok all" and out.count("ok drain") == 5
 
 
 HOST_SOURCES = ["gfq_api.cpp", "gfq_tune.cpp", "gfq_batch_host.cpp", "gfq_server.cpp"]
