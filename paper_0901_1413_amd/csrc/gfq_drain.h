@@ -12,8 +12,8 @@
 //   - no branch inside the loop is taken by some threads of a wave and not by others around
 //     a barrier: a branch at the loop's head that only one lane takes lets the compiler give
 //     the other lanes a shorter path back to the first barrier, so that they loop on a stale
-//     slot while the lane that must fetch the next index waits for them (the cause of an
-//     earlier version's hang, read off its generated code);
+//     slot while the lane that must fetch the next index waits for them (what a first draft
+//     of this loop compiled to, and the likely cause of an earlier version's hang);
 //   - the index every thread acts on is one value for the whole workgroup (the device takes
 //     it through readfirstlane, so the compiler knows it is uniform), so the exit test and
 //     every barrier inside the item are reached by all threads of the workgroup or by none;
