@@ -4,8 +4,8 @@
 //   storage     the packed format of the C ABI (Section 4 encodings), P planes;
 //   table       how table entries (sums of rows of B) are held in LDS, P planes;
 //   accumulator how a lane keeps its running row of C, PA planes (a binary residue
-//               modulo 3 for F_3, a carry-save pair of residues modulo 7 for F_7, a
-//               three-plane carry-save value modulo 5 for F_5, see gfq_field.h).
+//               modulo 3 for F_3 and two for F_9, a carry-save pair of residues modulo 7
+//               for F_7, a three-plane carry-save value modulo 5 for F_5, see gfq_field.h).
 // SPLIT_PREFIX: table chunk prefixes are summed one slab ahead by a quarter of the threads
 // (fields whose table addition is long) rather than by every build thread for itself.
 // SWAP_NEGATES: exchanging planes 2j and 2j + 1 of a table entry negates it; such fields
