@@ -248,3 +248,28 @@ def test_batch_persistent_graph_capture(gfq_gpu):
             assert torch.equal(w, C), (rep, i)
     del graph
     b.destroy()
+
+
+def test_batch_persistent_narrow_and_degenerate(gfq_gpu):
+    """Persistent drains of narrow-tile lists (8- and 4-word tiles of tall, thin products),
+    two launches back to back on one stream (the second launch's head reset is ordered after
+    the first launch's drain), and of a batch of degenerate products (an l = 0 product, whose
+    tiles write zeros, and products without tiles)."""
+    g = gfq_gpu
+    specs = []
+    for q in (3, 4, 5, 7, 8, 9):
+        specs += [(q, 1500, 300, 100), (q, 700, 200, 250), (q, 2049, 129, 129)]
+    probs, host = make_batch(g, specs, 350)
+    b = g.Batch(probs)
+    b.launch_persistent()
+    b.launch_persistent()
+    g.sync()
+    check_against_oracle_and_alone(g, probs, host, range(len(specs)))
+    b.destroy()
+    empty, _ = make_batch(g, [(3, 5, 0, 7), (5, 0, 4, 4), (7, 4, 4, 0)], 351)
+    e = g.Batch(empty)
+    e.launch_persistent()
+    g.sync()
+    C = empty[0][6]
+    assert not bool((C[:g.packed_bytes(3, 5, 7)] != 0).any())          # l = 0: the zero product
+    e.destroy()
