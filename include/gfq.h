@@ -188,12 +188,14 @@ int gfq_matmul_sw(int q, int64_t m, int64_t l, int64_t n, const void *A, const v
                   const gfq_config *leaf);
 
 /* Run count independent products (fields and shapes may differ) as one launch per
- * (field, tile shape) whose workgroups take (product, row tile, column tile, slab slice)
- * items from a longest-first work list (the method of Section 2 per item), plus one
- * partial-sum launch when products are sliced.  problems is a host array.  Each product obeys the gfq_matmul
+ * (field, tile shape) whose persistent workgroups take (product, row tile, column tile,
+ * slab slice) items from a longest-first list through a device queue head (the method of
+ * Section 2 per item), plus one partial-sum launch when products are sliced.  problems is a
+ * host array.  Each product obeys the gfq_matmul
  * rules; a validation error in any product rejects the whole batch before anything is
- * launched.  Equivalent to gfq_batch_create + gfq_batch_launch; the batch's descriptors are
- * released by a later call or gfq_sync once the launch has finished. */
+ * launched.  Equivalent to gfq_batch_create + gfq_batch_launch_persistent (the faster drain
+ * on mixed batches); the batch's descriptors are released by a later call or gfq_sync once
+ * the launch has finished. */
 int gfq_matmul_batched(int count, const gfq_problem *problems);
 
 /* A prepared batch: products, launch parameters and work lists on the device.  Create it

@@ -1,5 +1,5 @@
 // gfq_api.cpp -- the C ABI declared in include/gfq.h: argument validation, launch
-// configuration, workspace and stream handling around the kernels of gfq_kernels.hip.
+// configuration, workspace and stream handling around the kernel launchers.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -494,7 +494,7 @@ int gfq_matmul_batched(int count, const gfq_problem *problems) {
     gfq_batch *b = nullptr;
     int st = gfq_batch_create(count, problems, &b);
     if (st != GFQ_OK) return st;
-    st = gfq_batch_launch(b);
+    st = gfq_batch_launch_persistent(b);
     hipEvent_t done = nullptr;
     hipError_t e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventRecord(done, t_stream);
