@@ -30,7 +30,7 @@ template <int Q, int TWD, int REP, int R, int NT>
 __device__ __forceinline__ void run_item(const BatchList &bl, u32 i) {
     const BatchItem item = bl.items[i];
     const MMArgs a = bl.prods[item.prod].a;
-    m4rm_tile<Q, TWD, REP, R, NT>(a, item.tx, item.ty, (int)item.slice);
+    m4rm_tile_fit<Q, TWD, REP, R, NT>(a, item.tx, item.ty, (int)item.slice);
     __syncthreads();
     if (threadIdx.x == 0) {
         const u32 d = atomicAdd(&bl.prod_done[item.prod], 1u);

@@ -66,10 +66,11 @@ template <int Q, int TWD, int REP> constexpr bool perm_addr_tile() {
     return gsw_tile<Q, TWD, REP>() && FT<Q>::PT == 2 && !FT<Q>::HALF_ROWS;
 }
 
-// One tile of the product: column tile bx, row tile by, slab slice bz of the problem `a`.
-// Called by every thread of an NT-thread workgroup; uses the workgroup's dynamic LDS.
+// The rows of one tile from row0 (R * NT / (TWD / 4) of them, fewer where the product
+// ends), column tile bx, slab slice bz of the problem `a`.  Called by every thread of an
+// NT-thread workgroup; uses the workgroup's dynamic LDS.
 template <int Q, int TWD, int REP, int R, int NT>
-__device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int bz) {
+__device__ __forceinline__ void m4rm_tile_rows(const MMArgs &a, int bx, int row0, int bz) {
     typedef FT<Q> F;
     // P planes per row in the packed operands, PT planes per table entry, D table rows
     // gathered per slab (GP planes of each), PA accumulator planes per word
@@ -115,7 +116,6 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
 
     const int tid = threadIdx.x;
     const int colw0 = bx * TWD;
-    const int row0 = by * TM;
     const int s_begin = bz * a.slabs_per_split;
     const int s_end = min(a.S, s_begin + a.slabs_per_split);
     const u32 kmask = (1u << k) - 1u;
@@ -496,7 +496,9 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
         const u32 lo = laneoff | ((s & 1) ? TB1 : 0u);
         const u32 *ib = Ib + (s % 3) * TM * IBW + rs * R * IBW;
         u32 iw[R * IBW];
-        if constexpr ((R * IBW) % 4 == 0) {
+        if constexpr (R * IBW == 1) {
+            iw[0] = ib[0];
+        } else if constexpr ((R * IBW) % 4 == 0) {
 #pragma unroll
             for (int w = 0; w < R * IBW; w += 4) {
                 const uint4 v = *reinterpret_cast<const uint4 *>(ib + w);
@@ -625,6 +627,41 @@ __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int b
             }
         }
     }
+}
+
+// One tile of the product: column tile bx, row tile by (R * NT / (TWD / 4) rows), slab
+// slice bz.
+template <int Q, int TWD, int REP, int R, int NT>
+__device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int bz) {
+    m4rm_tile_rows<Q, TWD, REP, R, NT>(a, bx, by * (NT / (TWD / 4) * R), bz);
+}
+
+// The same tile where the product's last row may cut it (the items of a batch, whose small
+// products leave most of a tile's rows empty): the tile body runs at the fewest rows per
+// lane (R, R / 2, ..., down to 1, F_9: 2) that cover the tile's rows.  Lane row r is tile
+// row rs + r * RS for row slot rs, so R' rows per lane cover the first R' * RS rows.  The
+// choice is the same for the whole workgroup, and every variant is straight-line code of its
+// own.  (The single-product kernels keep one variant: with the others compiled in beside it,
+// the F_5 8192^3 product ran 3% slower with the same instructions in its slab loop.)
+constexpr int fit_rows_min(int q) { return q == 9 ? 2 : 1; }   // F_9 at one row: more VGPRs
+
+template <int Q, int TWD, int REP, int R, int NT>
+__device__ __forceinline__ void m4rm_tile_fit_rows(const MMArgs &a, int bx, int row0, int bz, int need) {
+    if constexpr (R > fit_rows_min(Q)) {
+        if (need <= R / 2) {
+            m4rm_tile_fit_rows<Q, TWD, REP, R / 2, NT>(a, bx, row0, bz, need);
+            return;
+        }
+    }
+    m4rm_tile_rows<Q, TWD, REP, R, NT>(a, bx, row0, bz);
+}
+
+template <int Q, int TWD, int REP, int R, int NT>
+__device__ __forceinline__ void m4rm_tile_fit(const MMArgs &a, int bx, int by, int bz) {
+    constexpr int RS = NT / (TWD / 4);           // row slots: rows per lane row
+    const int row0 = by * (RS * R);
+    const int need = __builtin_amdgcn_readfirstlane((min(RS * R, a.m - row0) + RS - 1) / RS);
+    m4rm_tile_fit_rows<Q, TWD, REP, R, NT>(a, bx, row0, bz, need);
 }
 
 }  // namespace gfq

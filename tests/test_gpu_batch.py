@@ -273,3 +273,41 @@ def test_batch_persistent_narrow_and_degenerate(gfq_gpu):
     C = empty[0][6]
     assert not bool((C[:g.packed_bytes(3, 5, 7)] != 0).any())          # l = 0: the zero product
     e.destroy()
+
+
+FIT_M = (1, 40, 65, 100, 129, 200, 257, 300, 513, 700, 1025, 1100, 1600, 2049, 2100)
+
+
+@pytest.mark.parametrize("tall", [False, True])
+def test_batch_tile_fit_rows(gfq_gpu, tmp_path, tall):
+    """Batch items cut by a product's last row run the tile body at the fewest rows per lane
+    that cover the rows (R, R / 2, ..., 1; F_9: 2).  Products whose last row tile holds 1 ..
+    2100 rows, in every field, 100, 200 and 1500 columns wide (the narrow-tile and 16-word
+    groups), with the tile heights the library chooses (two rows per lane) and with batch
+    tuning entries of 2048-row tiles (the field's most rows per lane); the work-list and the
+    persistent launches, each product against the oracle and against its plain launch."""
+    import torch
+    g = gfq_gpu
+    if tall:
+        arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+        table = tmp_path / "tall_tiles.txt"
+        table.write_text("".join(f"{arch} 1 {q} {bm} 6 0 6 2048 1 0\n"
+                                 for q in (3, 4, 5, 7, 8, 9) for bm in range(6, 15)))
+        g.tune_clear()
+        g.tune_load(str(table))
+    try:
+        specs = [(q, m, 40, n) for q in (3, 4, 5, 7, 8, 9) for m in FIT_M for n in (100, 200, 1500)]
+        probs, host = make_batch(g, specs, 360 + int(tall))
+        b = g.Batch(probs)
+        b.launch()
+        g.sync()
+        check_against_oracle_and_alone(g, probs, host, range(len(specs)))
+        for (*_, C) in probs:
+            C.fill_(0x5A)
+        b.launch_persistent()
+        g.sync()
+        check_against_oracle_and_alone(g, probs, host, range(len(specs)))
+        b.destroy()
+    finally:
+        if tall:
+            g.tune_clear()

@@ -357,3 +357,28 @@ def test_wide_tiles_entry_parity(gfq_gpu, q, rows):
             A[e, t] = (e >> t) & 1
         A[e, k + (e % k)] = 1                # and one row of slab 1
     check(gfq_gpu, q, A, B, k=k, rows=rows)
+
+
+FIT_M = (1, 40, 65, 100, 129, 200, 257, 300, 513, 700, 1025, 1100, 1600, 2049, 2100)
+
+
+@pytest.mark.parametrize("q", FIELDS)
+@pytest.mark.parametrize("k,rows", [(0, 2048), (0, 1024), (0, 512), (4, 256), (10, 2048)])
+def test_ragged_last_row_tile(gfq_gpu, q, k, rows):
+    """Products whose last row tile holds 1 .. 2100 rows, at each tile height (k = 0: the
+    wide-tile slab width), with ragged slabs and column tiles; every element and packed byte
+    against the oracle."""
+    k = k or WIDE_K[q]
+    for i, m in enumerate(FIT_M):
+        A, B = inputs.pair(q, m, 3 * k + 1, 1500, cfg=232, idx=1000 * k + i)
+        check(gfq_gpu, q, A, B, k=k, rows=rows)
+
+
+@pytest.mark.parametrize("q", MATRIX_ROUTE_FIELDS)
+@pytest.mark.parametrize("rows", [2048, 512])
+def test_matrix_route_ragged_last_row_tile(gfq_gpu, q, rows):
+    """The matrix-level routes' products with last row tiles of 1 .. 2100 rows against the
+    oracle."""
+    for i, m in enumerate(FIT_M):
+        A, B = inputs.pair(q, m, 45, 700, cfg=233, idx=rows + i)
+        check(gfq_gpu, q, A, B, rows=rows, variant=gfq_gpu.VARIANT_KARATSUBA)
