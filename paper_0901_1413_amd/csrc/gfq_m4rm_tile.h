@@ -66,11 +66,12 @@ template <int Q, int TWD, int REP> constexpr bool perm_addr_tile() {
     return gsw_tile<Q, TWD, REP>() && FT<Q>::PT == 2 && !FT<Q>::HALF_ROWS;
 }
 
-// The rows of one tile from row0 (R * NT / (TWD / 4) of them, fewer where the product
-// ends), column tile bx, slab slice bz of the problem `a`.  Called by every thread of an
-// NT-thread workgroup; uses the workgroup's dynamic LDS.
-template <int Q, int TWD, int REP, int R, int NT>
-__device__ __forceinline__ void m4rm_tile_rows(const MMArgs &a, int bx, int row0, int bz) {
+// The tile of the product `a` whose first row is row0 (R * NT / (TWD / 4) rows, fewer where
+// the product ends) and whose first column word is colw0 (TWD words), over slab slice bz.
+// Called by every thread of an NT-thread workgroup; uses the workgroup's dynamic LDS.  ITEM:
+// the tile is one item of a batch (see the thread index below).
+template <int Q, int TWD, int REP, int R, int NT, bool ITEM = false>
+__device__ __forceinline__ void m4rm_tile_rows(const MMArgs &a, int colw0, int row0, int bz) {
     typedef FT<Q> F;
     // P planes per row in the packed operands, PT planes per table entry, D table rows
     // gathered per slab (GP planes of each), PA accumulator planes per word
@@ -114,8 +115,13 @@ __device__ __forceinline__ void m4rm_tile_rows(const MMArgs &a, int bx, int row0
     u32 *PB = Bst + 3 * KMAX * P * TWD;                         // [2][NCH][PT][TWD] (split prefixes)
     u32 *Ib = PB + (F::SPLIT_PREFIX ? 2 * NCH * PT * TWD : 0);  // [3][TM][IBW]
 
-    const int tid = threadIdx.x;
-    const int colw0 = bx * TWD;
+    // In a batch item the thread index passes through an empty asm statement, so that nothing
+    // derived from it is hoisted out of the tile: in a persistent workgroup's loop over items
+    // such values stay live across every tile variant of the loop and crowd the registers
+    // (15-25 VGPRs per batch kernel).  The single-product kernels keep the plain index: the
+    // opaque one ran the F_5 8192^3 product 3% slower.
+    int tid = threadIdx.x;
+    if constexpr (ITEM) asm volatile("" : "+v"(tid));
     const int s_begin = bz * a.slabs_per_split;
     const int s_end = min(a.S, s_begin + a.slabs_per_split);
     const u32 kmask = (1u << k) - 1u;
@@ -633,35 +639,52 @@ __device__ __forceinline__ void m4rm_tile_rows(const MMArgs &a, int bx, int row0
 // slice bz.
 template <int Q, int TWD, int REP, int R, int NT>
 __device__ __forceinline__ void m4rm_tile(const MMArgs &a, int bx, int by, int bz) {
-    m4rm_tile_rows<Q, TWD, REP, R, NT>(a, bx, by * (NT / (TWD / 4) * R), bz);
+    m4rm_tile_rows<Q, TWD, REP, R, NT>(a, bx * TWD, by * (NT / (TWD / 4) * R), bz);
 }
 
-// The same tile where the product's last row may cut it (the items of a batch, whose small
-// products leave most of a tile's rows empty): the tile body runs at the fewest rows per
-// lane (R, R / 2, ..., down to 1, F_9: 2) that cover the tile's rows.  Lane row r is tile
-// row rs + r * RS for row slot rs, so R' rows per lane cover the first R' * RS rows.  The
-// choice is the same for the whole workgroup, and every variant is straight-line code of its
-// own.  (The single-product kernels keep one variant: with the others compiled in beside it,
-// the F_5 8192^3 product ran 3% slower with the same instructions in its slab loop.)
+// The same tile where the product's edges may cut it (the items of a batch, whose small
+// products leave much of a tile empty).
+//   Rows: the tile body runs at the fewest rows per lane (R, R / 2, ..., down to 1, F_9: 2)
+//   that cover the tile's rows.  Lane row r is tile row rs + r * RS for row slot rs, so R'
+//   rows per lane cover the first R' * RS rows.
+//   Columns: a tile holding at most half its TWD words runs as a tile of TWD / 2 words with
+//   twice the copies per super-row (the same table bytes and LDS) and twice the row slots,
+//   so R / 2 rows per lane cover its rows.
+// Each choice is the same for the whole workgroup, and every variant is a straight-line copy
+// of the tile body of its own.  (The single-product kernels keep one variant: with the others
+// compiled in beside it, the F_5 8192^3 product ran 3% slower with the same instructions in
+// its slab loop.)
 constexpr int fit_rows_min(int q) { return q == 9 ? 2 : 1; }   // F_9 at one row: more VGPRs
 
 template <int Q, int TWD, int REP, int R, int NT>
-__device__ __forceinline__ void m4rm_tile_fit_rows(const MMArgs &a, int bx, int row0, int bz, int need) {
+__device__ __forceinline__ void m4rm_tile_fit_rows(const MMArgs &a, int colw0, int row0, int bz, int rows) {
+    constexpr int RS = NT / (TWD / 4);
     if constexpr (R > fit_rows_min(Q)) {
-        if (need <= R / 2) {
-            m4rm_tile_fit_rows<Q, TWD, REP, R / 2, NT>(a, bx, row0, bz, need);
+        if (rows <= RS * (R / 2)) {
+            m4rm_tile_fit_rows<Q, TWD, REP, R / 2, NT>(a, colw0, row0, bz, rows);
             return;
         }
     }
-    m4rm_tile_rows<Q, TWD, REP, R, NT>(a, bx, row0, bz);
+    m4rm_tile_rows<Q, TWD, REP, R, NT, true>(a, colw0, row0, bz);
+}
+
+template <int Q, int TWD, int R> constexpr bool fit_narrow_tile() {
+    return TWD >= 8 && R >= 2 * fit_rows_min(Q);
 }
 
 template <int Q, int TWD, int REP, int R, int NT>
 __device__ __forceinline__ void m4rm_tile_fit(const MMArgs &a, int bx, int by, int bz) {
     constexpr int RS = NT / (TWD / 4);           // row slots: rows per lane row
-    const int row0 = by * (RS * R);
-    const int need = __builtin_amdgcn_readfirstlane((min(RS * R, a.m - row0) + RS - 1) / RS);
-    m4rm_tile_fit_rows<Q, TWD, REP, R, NT>(a, bx, row0, bz, need);
+    const int colw0 = bx * TWD, row0 = by * (RS * R);
+    const int rows = __builtin_amdgcn_readfirstlane(min(RS * R, a.m - row0));
+    if constexpr (fit_narrow_tile<Q, TWD, R>()) {
+        const int words = __builtin_amdgcn_readfirstlane(min(TWD, a.Wn - colw0));
+        if (words <= TWD / 2) {
+            m4rm_tile_fit_rows<Q, TWD / 2, REP * 2, R / 2, NT>(a, colw0, row0, bz, rows);
+            return;
+        }
+    }
+    m4rm_tile_fit_rows<Q, TWD, REP, R, NT>(a, colw0, row0, bz, rows);
 }
 
 }  // namespace gfq

@@ -280,12 +280,14 @@ FIT_M = (1, 40, 65, 100, 129, 200, 257, 300, 513, 700, 1025, 1100, 1600, 2049, 2
 
 @pytest.mark.parametrize("tall", [False, True])
 def test_batch_tile_fit_rows(gfq_gpu, tmp_path, tall):
-    """Batch items cut by a product's last row run the tile body at the fewest rows per lane
-    that cover the rows (R, R / 2, ..., 1; F_9: 2).  Products whose last row tile holds 1 ..
-    2100 rows, in every field, 100, 200 and 1500 columns wide (the narrow-tile and 16-word
-    groups), with the tile heights the library chooses (two rows per lane) and with batch
-    tuning entries of 2048-row tiles (the field's most rows per lane); the work-list and the
-    persistent launches, each product against the oracle and against its plain launch."""
+    """Batch items cut by a product's edges run the tile body at the fewest rows per lane
+    that cover their rows (R, R / 2, ..., 1; F_9: 2), and at half the tile width when they
+    hold at most half its words.  Products whose last row tile holds 1 .. 2100 rows, in every
+    field, 100, 200, 1100 and 1500 columns wide (narrow tiles; 16-word tiles of 4, 7 and 3
+    words in the last column tile; 15 words), with the tile heights the library chooses (two
+    rows per lane) and with batch tuning entries of 2048-row tiles (the field's most rows per
+    lane); the work-list and the persistent launches, each product against the oracle and
+    against its plain launch."""
     import torch
     g = gfq_gpu
     if tall:
@@ -296,7 +298,7 @@ def test_batch_tile_fit_rows(gfq_gpu, tmp_path, tall):
         g.tune_clear()
         g.tune_load(str(table))
     try:
-        specs = [(q, m, 40, n) for q in (3, 4, 5, 7, 8, 9) for m in FIT_M for n in (100, 200, 1500)]
+        specs = [(q, m, 40, n) for q in (3, 4, 5, 7, 8, 9) for m in FIT_M for n in (100, 200, 1100, 1500)]
         probs, host = make_batch(g, specs, 360 + int(tall))
         b = g.Batch(probs)
         b.launch()
