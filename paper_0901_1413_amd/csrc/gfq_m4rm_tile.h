@@ -100,9 +100,10 @@ __device__ __forceinline__ void m4rm_tile_rows(const MMArgs &a, int colw0, int r
     static_assert(!GSW || (SRB == 128 && LPR == 8), "two rows of C per 16-lane pass");
     constexpr bool SWZ = (PT % 2 == 0) && SRB == 128 && !GSW;
     constexpr bool XSW = SWZ || GSW;             // odd planes read at the row's address ^ SRB
-    // gathers of two rows ahead where the accumulate per row is short (F_3: 32 instructions
-    // per row against four 128-bit reads) and the registers allow it
-    constexpr bool PF2 = GSW && R == 16;
+    // gathers of three rows ahead where the accumulate per row is short (F_3: 32 instructions
+    // per row against four 128-bit reads) and the registers allow it (250 VGPRs at 16 rows per
+    // lane; two rows ahead measured 3% slower on the F_3 8192^3 product)
+    constexpr bool PF3 = GSW && R == 16;
     static_assert(KMAX * P * CG <= NT, "one B staging chunk per thread");
     static_assert(REP * LPR <= 16, "super-row wider than a 16-lane read group");
     static_assert(NCH % REP == 0 || REP % NCH == 0, "replica rotation");
@@ -529,15 +530,16 @@ __device__ __forceinline__ void m4rm_tile_rows(const MMArgs &a, int colw0, int r
                 if (r + 1 < R) fetch_half(iw, r + 1, 0, lo, h0);
                 consume_half1(r, h1);
             }
-        } else if constexpr (PF2) {
-            // two rows of reads in flight: row r+2's are issued before row r is added
-            uint4 tq[3][D][GP];
+        } else if constexpr (PF3) {
+            // three rows of reads in flight: row r+3's are issued before row r is added
+            uint4 tq[4][D][GP];
             fetch(iw, 0, lo, tq[0]);
             if (R > 1) fetch(iw, 1, lo, tq[1]);
+            if (R > 2) fetch(iw, 2, lo, tq[2]);
 #pragma unroll
             for (int r = 0; r < R; r++) {
-                if (r + 2 < R) fetch(iw, r + 2, lo, tq[(r + 2) % 3]);
-                consume(r, tq[r % 3]);
+                if (r + 3 < R) fetch(iw, r + 3, lo, tq[(r + 3) % 4]);
+                consume(r, tq[r % 4]);
             }
         } else {
             uint4 ta[D][GP], tb[D][GP];
