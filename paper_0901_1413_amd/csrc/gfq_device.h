@@ -8,8 +8,11 @@
 //               for F_7, a three-plane carry-save value modulo 5 for F_5, see gfq_field.h).
 // SPLIT_PREFIX: table chunk prefixes are summed one slab ahead by a quarter of the threads
 // (fields whose table addition is long) rather than by every build thread for itself.
-// SWAP_NEGATES: exchanging planes 2j and 2j + 1 of a table entry negates it; such fields
-// define neg_sel, which negates an accumulator where a lane mask is set.
+// EXCHANGE_READS: a lane that reads every table entry with planes 2j and 2j + 1 exchanged (and,
+// where EXCHANGE_SLOTS, with its two gathers' table rows exchanged) accumulates a fixed
+// invertible linear image of its row of C: -C for F_3 and F_9 (exchanging the planes negates
+// an entry), x^2 C^2 for GF(4).  Such fields define exchange_fix, which maps an accumulator
+// back where a lane mask is set.
 // HALF_BUILD_ROWS: from this many rows per lane on, the gathers of a slab outweigh its
 // table build enough that only half of the waves (one per SIMD) build the table, each
 // walking twice as far, with half the chunk prefixes (measured faster for every field at
@@ -33,11 +36,12 @@ template <int Q> struct FT;
 // Table entries and the accumulator are binary residues mod 3 (b0 + 2 b1, 3 meaning 0); per
 // slab the accumulator receives T[phi_0] and -T[phi_1], two four-instruction residue
 // additions.  Exchanging the two planes of a residue multiplies it by 2 = -1 (mod 3)
-// (SWAP_NEGATES): a lane that reads every table entry with its planes exchanged
-// accumulates -C, and neg_sel turns it back.
+// (EXCHANGE_READS): a lane that reads every table entry with its planes exchanged
+// accumulates -C, and exchange_fix turns it back.
 template <> struct FT<3> {
     static constexpr int P = 2, PT = 2, D = 2, GP = 2, PA = 2;
-    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false, SWAP_NEGATES = true;
+    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false, EXCHANGE_READS = true;
+    static constexpr bool EXCHANGE_SLOTS = false;
     static constexpr int HALF_BUILD_ROWS = 8;
     static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0] ^ x[1]; f[1] = x[1]; }
@@ -51,7 +55,7 @@ template <> struct FT<3> {
         f3b_sub(x, t[1], c);
     }
     // the accumulator negated where gm is all ones (its planes exchanged), kept elsewhere
-    __device__ static void neg_sel(u32 *c, u32 gm) {
+    __device__ static void exchange_fix(u32 *c, u32 gm) {
         const u32 c0 = c[0];
         c[0] = lut3<0xCA>(gm, c[1], c0);          // gm ? c1 : c0
         c[1] = lut3<0xCA>(gm, c0, c[1]);
@@ -69,7 +73,7 @@ template <> struct FT<3> {
 // planes, so alpha_d T[phi_d] costs nothing; the accumulator is a carry-save pair mod 7.
 template <> struct FT<7> {
     static constexpr int P = 3, PT = 3, D = 3, GP = 3, PA = 6;
-    static constexpr bool SPLIT_PREFIX = true, HALF_ROWS = false, SWAP_NEGATES = false;
+    static constexpr bool SPLIT_PREFIX = true, HALF_ROWS = false, EXCHANGE_READS = false;
     static constexpr int HALF_BUILD_ROWS = 1 << 30;
     static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; f[2] = x[2]; }
@@ -109,7 +113,7 @@ template <> struct FT<7> {
 // is already canonical at the end.
 template <> struct FT<5> {
     static constexpr int P = 3, PT = 3, D = 3, GP = 3, PA = 3;
-    static constexpr bool SPLIT_PREFIX = true, HALF_ROWS = false, SWAP_NEGATES = false;
+    static constexpr bool SPLIT_PREFIX = true, HALF_ROWS = false, EXCHANGE_READS = false;
     static constexpr int HALF_BUILD_ROWS = 8;
     static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; f[2] = x[2]; }
@@ -136,9 +140,15 @@ template <> struct FT<5> {
 
 // GF(4) (Section 4.3).  Basis {1, x}, phi_d = c_d.  Per slab the row receives
 // T[phi_0] + x T[phi_1]; with x (c0 + c1 x) = c1 + (c0 + c1) x that is two XOR planes.
+// Exchanging the planes of an entry t gives c1 + c0 x = x t^2 (squaring is additive here and
+// x^3 = 1).  A lane that reads both table rows with planes exchanged and with the two rows
+// exchanged (EXCHANGE_SLOTS: T[phi_1] into the slot of T[phi_0] and back) adds
+// x T1^2 + x x T0^2 = x^2 (T0 + x T1)^2 per slab, so it accumulates L(C) with L(a) = x^2 a^2;
+// L is additive and its own inverse (x^6 = 1, a^4 = a), and L(c0 + c1 x) = c0 + (c0 + c1) x.
 template <> struct FT<4> {
     static constexpr int P = 2, PT = 2, D = 2, GP = 2, PA = 2;
-    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false, SWAP_NEGATES = false;
+    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false, EXCHANGE_READS = true;
+    static constexpr bool EXCHANGE_SLOTS = true;
     static constexpr int HALF_BUILD_ROWS = 8;
     static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; }
@@ -150,6 +160,8 @@ template <> struct FT<4> {
         c[0] = xor3(c[0], t[0][0], t[1][1]);
         c[1] = xor3(c[1], t[0][1], t[1][0]) ^ t[1][1];
     }
+    // L applied where gm is all ones
+    __device__ static void exchange_fix(u32 *c, u32 gm) { c[1] ^= c[0] & gm; }
     __device__ static void finish(const u32 *c, u32 *out) { out[0] = c[0]; out[1] = c[1]; }
     __device__ static void sadd(const u32 *a, const u32 *b, u32 *r) { tadd(a, b, r); }
     __device__ static void sneg(const u32 *a, u32 *r) { r[0] = a[0]; r[1] = a[1]; }
@@ -163,7 +175,7 @@ template <> struct FT<4> {
 // Same packed operands and product as FT<4>; selected by the configuration.
 template <> struct FT<GF4_KARATSUBA> {
     static constexpr int P = 2, PT = 3, D = 3, GP = 1, PA = 2;
-    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false, SWAP_NEGATES = false;
+    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false, EXCHANGE_READS = false;
     static constexpr int HALF_BUILD_ROWS = 8;
     static constexpr int gplane(int d, int) { return d; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; f[2] = x[0] ^ x[1]; }
@@ -187,7 +199,7 @@ template <> struct FT<GF4_KARATSUBA> {
 // x^2 T[phi_2] (g8_acc, six operations for three planes).
 template <> struct FT<8> {
     static constexpr int P = 3, PT = 3, D = 3, GP = 3, PA = 3;
-    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false, SWAP_NEGATES = false;
+    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false, EXCHANGE_READS = false;
     static constexpr int HALF_BUILD_ROWS = 8;
     static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; f[2] = x[2]; }
@@ -211,14 +223,15 @@ template <> struct FT<8> {
 // i (x + y i) = -y + x i the slab adds T0 - T1 + i T2 - i T3, i.e. real += T0.re - T1.re -
 // T2.im + T3.im and imaginary += T0.im - T1.im + T2.re - T3.re: eight four-instruction residue
 // additions (as F_3), four accumulator planes, so eight rows per lane fit.
-// Exchanging planes 2j and 2j + 1 negates both residues of an entry (SWAP_NEGATES), and the
+// Exchanging planes 2j and 2j + 1 negates both residues of an entry (EXCHANGE_READS), and the
 // residue additions on negated operands give the negated sum, so a lane that reads every entry
 // exchanged ends with the negated accumulator.
 template <> struct FT<9> {
     static constexpr int P = 4, PT = 4, D = 4, GP = 4, PA = 4;
     // HALF_ROWS: a row's gathers are consumed in two halves (accumulate_half), so only half a
     // row of 128-bit reads is in flight at a time
-    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = true, SWAP_NEGATES = true;
+    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = true, EXCHANGE_READS = true;
+    static constexpr bool EXCHANGE_SLOTS = false;
     static constexpr int HALF_BUILD_ROWS = 4;
     static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0] ^ x[1]; f[1] = x[1]; f[2] = x[2] ^ x[3]; f[3] = x[3]; }
@@ -247,7 +260,7 @@ template <> struct FT<9> {
         }
     }
     // the accumulator negated where gm is all ones (the planes of each residue exchanged)
-    __device__ static void neg_sel(u32 *c, u32 gm) {
+    __device__ static void exchange_fix(u32 *c, u32 gm) {
 #pragma unroll
         for (int j = 0; j < PA; j += 2) {
             const u32 c0 = c[j];
@@ -280,7 +293,7 @@ template <> struct FT<9> {
 // FT<8>; selected by the configuration.
 template <> struct FT<GF8_TRINOMIAL> {
     static constexpr int P = 3, PT = 6, D = 6, GP = 1, PA = 3;
-    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false, SWAP_NEGATES = false;
+    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false, EXCHANGE_READS = false;
     static constexpr int HALF_BUILD_ROWS = 8;
     static constexpr int gplane(int d, int) { return d; }
     __device__ static void phis(const u32 *x, u32 *f) {
@@ -311,7 +324,7 @@ template <> struct FT<GF8_TRINOMIAL> {
 // operands and product as FT<9>; selected by the configuration.
 template <> struct FT<F9_KARATSUBA> {
     static constexpr int P = 4, PT = 6, D = 6, GP = 2, PA = 12;
-    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false, SWAP_NEGATES = false;
+    static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false, EXCHANGE_READS = false;
     static constexpr int HALF_BUILD_ROWS = 1 << 30;
     static constexpr int gplane(int d, int p) { return (d >> 1) * 2 + p; }
     __device__ static void phis(const u32 *x, u32 *f) {

@@ -127,7 +127,7 @@ inline MMPlan mm_plan(int q, int k, int rowsTile) {
     int r = rowsTile * lpr / NT_MM;
     r = r <= 2 ? 2 : (r <= 4 ? 4 : (r <= 8 ? 8 : 16));
     if (r > max_rows_per_lane(q)) r = max_rows_per_lane(q);
-    if (r > 8 && p.twd != 16 && !(q == 3 && p.twd == 32)) r = 8;   // 16 rows per lane: 16-word tiles (F_3: and 32)
+    if (r > 8 && p.twd != 16 && !((q == 3 || q == 4) && p.twd == 32)) r = 8;   // 16 rows per lane: 16-word tiles (F_3, GF(4): and 32)
     if (r > 4 && p.twd < 16 && (q == 5 || q == 8 || q == GF8_TRINOMIAL)) r = 4;   // ... for F_5, GF(8) eight would
     if (r > 4 && p.twd < 32 && q == 9) r = 4;           // F_9: eight rows per lane on 32-word tiles only,
     if (r > 2 && p.twd < 16 && q == 9) r = 2;           // two on narrow ones (four would spill)

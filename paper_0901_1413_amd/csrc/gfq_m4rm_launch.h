@@ -100,7 +100,7 @@ static hipError_t launch_mm_rows(const MMArgs &a, const MMPlan &plan, const MMSt
         return launch_mm<STRIDED, Q, TWD, REP, 4>(a, plan, sd, st);       // eight rows per lane would spill
     } else {
         if (plan.R == 4) return launch_mm<STRIDED, Q, TWD, REP, 4>(a, plan, sd, st);
-        if constexpr (((Q == 4 || Q == GF4_KARATSUBA) && TWD == 16) || (Q == 3 && (TWD == 16 || TWD == 32))) {
+        if constexpr ((Q == GF4_KARATSUBA && TWD == 16) || ((Q == 3 || Q == 4) && (TWD == 16 || TWD == 32))) {
             if (plan.R == 16) return launch_mm<STRIDED, Q, TWD, REP, 16>(a, plan, sd, st);   // two planes per word
         }
         return launch_mm<STRIDED, Q, TWD, REP, 8>(a, plan, sd, st);

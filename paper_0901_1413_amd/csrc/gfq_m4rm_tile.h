@@ -32,8 +32,8 @@
 // 256 distinct consecutive bytes: with SRB = 256 the REP rows of C gathered by one 16-lane
 // group come from different copies.  With SRB = 128 a super-row is one 32-word row and a
 // group serves two rows of C, each in one half of the banks (planes swapped on odd entries
-// when their number is even, so that the half follows the entry; for F_3, whose entries are
-// negated by exchanging their planes, the second row reads them exchanged and never meets
+// when their number is even, so that the half follows the entry; for F_3, F_9 and GF(4), whose
+// accumulation survives exchanged planes, the second row reads them exchanged and never meets
 // the first); with SRB = 64 and less,
 // four or more rows of C share a group and conflict as their entries fall.  Table 0 sits
 // at LDS offset 0 and table 1 at TB1, a power of two not below the table size, so an
@@ -60,7 +60,12 @@ template <int H> struct half_tag { static constexpr int value = H; };
 // permutation (lane byte, entry byte, table-base bytes).  That needs the second table at a
 // multiple of 65536 bytes (the launcher checks it).
 template <int Q, int TWD, int REP> constexpr bool gsw_tile() {
-    return FT<Q>::SWAP_NEGATES && REP == 1 && TWD == 32;
+    return FT<Q>::EXCHANGE_READS && REP == 1 && TWD == 32;
+}
+// fields whose exchanged reads also exchange the two gathers' table rows (GF(4))
+template <class F> constexpr bool exchange_slots() {
+    if constexpr (F::EXCHANGE_READS) return F::EXCHANGE_SLOTS;
+    else return false;
 }
 template <int Q, int TWD, int REP> constexpr bool perm_addr_tile() {
     return gsw_tile<Q, TWD, REP>() && FT<Q>::PT == 2 && !FT<Q>::HALF_ROWS;
@@ -91,10 +96,12 @@ __device__ __forceinline__ void m4rm_tile_rows(const MMArgs &a, int colw0, int r
     // half and the two rows of a pass would always meet there: planes swap in pairs on odd
     // entries (plane p of entry e at (p ^ (e & 1)) * SRB), so the halves follow the entries.
     //
-    // Fields whose entries are negated by exchanging planes 2j and 2j + 1 (F::SWAP_NEGATES)
-    // avoid the meetings altogether: the second row of every pass (lanes 8-15 of each 16)
-    // reads plane p ^ 1 where the first reads plane p, so the two rows are always in
-    // opposite halves; that row accumulates -C and is negated before it is stored.
+    // Fields whose accumulation survives exchanged planes (F::EXCHANGE_READS: F_3 and F_9,
+    // whose entries exchanging planes 2j and 2j + 1 negates, and GF(4)) avoid the meetings
+    // altogether: the second row of every pass (lanes 8-15 of each 16) reads plane p ^ 1 where
+    // the first reads plane p, so the two rows are always in opposite halves; that row
+    // accumulates a fixed linear image of C (-C; GF(4), whose second row also takes its two
+    // gathers' table rows in exchanged order: x^2 C^2), mapped back before it is stored.
     constexpr bool GSW = gsw_tile<Q, TWD, REP>();
     constexpr bool PERM = perm_addr_tile<Q, TWD, REP>();
     static_assert(!GSW || (SRB == 128 && LPR == 8), "two rows of C per 16-lane pass");
@@ -214,6 +221,16 @@ __device__ __forceinline__ void m4rm_tile_rows(const MMArgs &a, int colw0, int r
                 for (int d = 0; d < IBW * 2; d++) {
                     const u32 e = d < D ? f[d < D ? d : 0] : 0u;
                     o[d] = e * (u32)(PT * SRB) + (SWZ ? (e & 1u) * (u32)SRB : 0u);   // plane 0's place
+                }
+                // the row is gathered by the lanes at row slot pos / R: the second row of a
+                // read pass takes the two table rows in exchanged order (GF(4))
+                if constexpr (GSW && exchange_slots<F>()) {
+                    static_assert(D == 2, "two gathers");
+                    if ((pos / R) & 1) {
+                        const u32 t = o[0];
+                        o[0] = o[1];
+                        o[1] = t;
+                    }
                 }
 #pragma unroll
                 for (int w = 0; w < IBW; w++) ib[pos * IBW + w] = o[2 * w] | (o[2 * w + 1] << 16);
@@ -625,7 +642,7 @@ __device__ __forceinline__ void m4rm_tile_rows(const MMArgs &a, int colw0, int r
                 u32 o[4][P];
 #pragma unroll
                 for (int i = 0; i < 4; i++) {
-                    if constexpr (GSW) F::neg_sel(acc[r][i], neg_row ? 0xffffffffu : 0u);
+                    if constexpr (GSW) F::exchange_fix(acc[r][i], neg_row ? 0xffffffffu : 0u);
                     F::finish(acc[r][i], o[i]);
                 }
 #pragma unroll

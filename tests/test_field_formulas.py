@@ -186,3 +186,31 @@ def test_column_schedule_search():
     assert acc["F_3"][:2] == (8, 3) and acc["F_7"][:2] == (18, 4)
     assert cs.f5_accumulate()[:2] == (20, 3)          # nine full adders and a half adder
     assert cs.f5add() == {"add": 8, "sub": 8}
+
+
+def test_gf4_exchanged_reads_identity():
+    """The GF(4) kernel's exchanged reads, checked with the oracle's GF(4) arithmetic (elements
+    c0 + c1 x as the integers c0 + 2 c1, products by 1 x 1 oracle products): exchanging the two
+    planes of t is x t^2; a row that reads both table rows exchanged and in exchanged order adds
+    swap(T1) + x swap(T0) = L(T0 + x T1) with L(a) = x^2 a^2; L is additive and its own inverse,
+    and L(c0 + c1 x) = c0 + (c0 + c1) x, the one masked XOR applied before the store."""
+    import numpy as np
+
+    import oracle
+
+    def mul(a, b):
+        return int(oracle.matmul(4, np.array([[a]], dtype=np.uint8), np.array([[b]], dtype=np.uint8))[0, 0])
+
+    X = 2
+    swap = lambda a: (a >> 1) | ((a & 1) << 1)
+    L = lambda a: mul(mul(X, X), mul(a, a))
+    for a in range(4):
+        assert swap(a) == mul(X, mul(a, a))
+        assert L(L(a)) == a
+        c0, c1 = a & 1, a >> 1
+        assert L(a) == c0 | ((c0 ^ c1) << 1)
+        for b in range(4):
+            assert L(a ^ b) == L(a) ^ L(b)                  # additive (addition is XOR)
+    for t0 in range(4):
+        for t1 in range(4):
+            assert swap(t1) ^ mul(X, swap(t0)) == L(t0 ^ mul(X, t1))

@@ -86,11 +86,11 @@ def test_strassen_winograd_8192_freivalds(gfq_gpu, q):
     assert freivalds(q, A, B, C, seed=100 + q)
 
 
-@pytest.mark.parametrize("q", [3, 5])
+@pytest.mark.parametrize("q", [3, 5, 4])
 def test_full_size_tuned_configuration(gfq_gpu, q):
     """The benchmark's launches: the shipped tuning table loaded, the 8192^3 product runs in
-    the configuration the table holds for its class (the one the benchmark times), and every
-    element passes Freivalds' check."""
+    the configuration the table holds for its class (the one the benchmark times; GF(4): the
+    exchanged-read 32-word tiles at k = 8), and every element passes Freivalds' check."""
     import os
     g = gfq_gpu
     N = 8192

@@ -340,12 +340,13 @@ def test_wide_tiles(gfq_gpu, q, rows, split):
     check(gfq_gpu, q, A, B, k=WIDE_K[q], rows=rows, split=split)
 
 
-@pytest.mark.parametrize("q,rows", [(3, 512), (3, 1024), (3, 256), (9, 0)])
+@pytest.mark.parametrize("q,rows", [(3, 512), (3, 1024), (3, 256), (9, 0), (4, 1024), (4, 512), (4, 256)])
 def test_wide_tiles_entry_parity(gfq_gpu, q, rows):
     """B = identity rows in a fixed order and A one-hot, so that every table entry of both
     parities is gathered and each product row equals one row of B: a plane swap left undone on
-    odd entries, or on the rows that read their planes exchanged (F_3: the second row of every
-    16-lane read pass, which accumulates the negated row), would show as swapped planes."""
+    odd entries, or on the rows that read their planes exchanged (F_3, F_9: the second row of
+    every 16-lane read pass, which accumulates the negated row; GF(4): that row also takes its
+    two table rows in exchanged order and accumulates x^2 C^2), would show as swapped planes."""
     k = WIDE_K[q]
     l, n = 2 * k, 1500
     rng = np.random.default_rng(231)
@@ -357,6 +358,12 @@ def test_wide_tiles_entry_parity(gfq_gpu, q, rows):
             A[e, t] = (e >> t) & 1
         A[e, k + (e % k)] = 1                # and one row of slab 1
     check(gfq_gpu, q, A, B, k=k, rows=rows)
+    if q == 4:
+        # coefficients x as well as 1: both gathers of a slab select entries of both parities
+        X = A.copy()
+        X[:, 1::2] *= 2
+        X[:, k:] = A[:, k:] * np.uint8(3)
+        check(gfq_gpu, q, X, B, k=k, rows=rows)
 
 
 FIT_M = (1, 40, 65, 100, 129, 200, 257, 300, 513, 700, 1025, 1100, 1600, 2049, 2100)
