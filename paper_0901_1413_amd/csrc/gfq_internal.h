@@ -52,6 +52,11 @@ inline int planes_of(int q) {
 inline int table_planes(int q) {
     return q == GF4_KARATSUBA ? 3 : ((q == GF8_TRINOMIAL || q == F9_KARATSUBA) ? 6 : planes_of(q));
 }
+
+// Table slots per entry: its planes, and for F_7 at 128-byte super-rows one more slot in front
+// holding a copy of plane 2 (the second row of every read pass reads the doubled entry from
+// it, conflict-free; see the product tile).
+inline int table_slots(int q, int srb) { return (q == 7 && srb == 128) ? 4 : table_planes(q); }
 inline int gathers_of(int q) {
     return (q == 3 || q == 4) ? 2 : (q == 9 ? 4 : ((q == GF8_TRINOMIAL || q == F9_KARATSUBA) ? 6 : 3));
 }
@@ -70,7 +75,7 @@ inline int max_rows_per_lane_batch(int q) { return q == 5 || q == 7 || q == 9 ? 
 // such that both table buffers fit TABLES_LDS (0 if none does).
 inline int srb_for(int q, int k) {
     for (int srb = 256; srb >= 16; srb >>= 1)
-        if (2 * ((size_t)1 << k) * table_planes(q) * srb <= TABLES_LDS) return srb;
+        if (2 * ((size_t)1 << k) * table_slots(q, srb) * srb <= TABLES_LDS) return srb;
     return 0;
 }
 // tile words per plane: 128-byte super-rows hold one 32-word row, 256-byte ones four copies
@@ -87,7 +92,7 @@ inline int batch_srb(int q, int R) { return ((q == 5 || q == 7) && R == 4) ? 64 
 inline int batch_kmax(int q, int R) {
     const int srb = batch_srb(q, R);
     int k = 1;
-    while (k < KMAX && 2 * ((size_t)1 << (k + 1)) * table_planes(q) * srb <= TABLES_LDS) k++;
+    while (k < KMAX && 2 * ((size_t)1 << (k + 1)) * table_slots(q, srb) * srb <= TABLES_LDS) k++;
     return k;
 }
 
@@ -104,7 +109,7 @@ struct MMPlan {
 
 inline size_t mm_lds_bytes(int q, int k, int srb, int TM, u32 *tb1_out) {
     const int P = planes_of(q), PT = table_planes(q), D = gathers_of(q);
-    const u32 tbytes = (u32)(1u << k) * PT * srb;
+    const u32 tbytes = (u32)(1u << k) * table_slots(q, srb) * srb;
     u32 tb1 = 16;
     while (tb1 < tbytes) tb1 <<= 1;
     if (tb1_out) *tb1_out = tb1;

@@ -62,6 +62,15 @@ template <int H> struct half_tag { static constexpr int value = H; };
 template <int Q, int TWD, int REP> constexpr bool gsw_tile() {
     return FT<Q>::EXCHANGE_READS && REP == 1 && TWD == 32;
 }
+// F_7 at 128-byte super-rows: each entry gets a fourth slot in front, a copy of plane 2, so
+// that the second row of a read pass can read the doubled entry (2t = (t2, t0, t1): doubling
+// modulo 7 rotates the planes) from slots 0, 1, 2 while the first reads t from slots 1, 2, 3.
+// Entries are 512 bytes, so slot j sits in half j mod 2 of the banks and the two rows never
+// meet; the second row accumulates 2C, and its result is multiplied by 4 (a rotation) before
+// the store.
+template <int Q, int TWD, int REP> constexpr bool dbl_copy_tile() {
+    return Q == 7 && REP == 1 && TWD == 32;
+}
 // fields whose exchanged reads also exchange the two gathers' table rows (GF(4))
 template <class F> constexpr bool exchange_slots() {
     if constexpr (F::EXCHANGE_READS) return F::EXCHANGE_SLOTS;
@@ -111,13 +120,16 @@ __device__ __forceinline__ void m4rm_tile_rows(const MMArgs &a, int colw0, int r
     // per row against four 128-bit reads) and the registers allow it (250 VGPRs at 16 rows per
     // lane; two rows ahead measured 3% slower on the F_3 8192^3 product)
     constexpr bool PF3 = GSW && R == 16;
+    constexpr bool DCP = dbl_copy_tile<Q, TWD, REP>();
+    static_assert(!DCP || (PT == 3 && SRB == 128 && !GSW && !SWZ), "doubled copy: three planes, 128-byte super-rows");
+    constexpr int ES = (PT + (DCP ? 1 : 0)) * SRB;   // bytes per table entry
     static_assert(KMAX * P * CG <= NT, "one B staging chunk per thread");
     static_assert(REP * LPR <= 16, "super-row wider than a 16-lane read group");
     static_assert(NCH % REP == 0 || REP % NCH == 0, "replica rotation");
 
     extern __shared__ __align__(16) unsigned char smem[];
     const int k = a.k;
-    const u32 tbytes = (u32)(1u << k) * PT * SRB;
+    const u32 tbytes = (u32)(1u << k) * ES;
     const u32 TB1 = a.tb1;                       // power of two >= tbytes, <= 65536
     u32 *Bst = reinterpret_cast<u32 *>(smem + TB1 + tbytes);   // [3][KMAX][P][TWD]
     u32 *PB = Bst + 3 * KMAX * P * TWD;                         // [2][NCH][PT][TWD] (split prefixes)
@@ -204,7 +216,7 @@ __device__ __forceinline__ void m4rm_tile_rows(const MMArgs &a, int colw0, int r
     auto apre_mask = [&](int j, int w) -> u32 {
         return (tid + j * NT < TM && row0 + srow(j) < a.m && w < a.Wl) ? 0xffffffffu : 0u;
     };
-    // offsets (u16, entry * PT * SRB) of the D table rows for slab s, for every tile row
+    // offsets (u16, entry * ES) of the D table rows for slab s, for every tile row
     auto stage_idx = [&](int s) {
         const int sh = (s * k) & 31;
         u32 *ib = Ib + (s % 3) * TM * IBW;
@@ -220,7 +232,7 @@ __device__ __forceinline__ void m4rm_tile_rows(const MMArgs &a, int colw0, int r
 #pragma unroll
                 for (int d = 0; d < IBW * 2; d++) {
                     const u32 e = d < D ? f[d < D ? d : 0] : 0u;
-                    o[d] = e * (u32)(PT * SRB) + (SWZ ? (e & 1u) * (u32)SRB : 0u);   // plane 0's place
+                    o[d] = e * (u32)ES + (SWZ ? (e & 1u) * (u32)SRB : 0u);   // slot 0's place
                 }
                 // the row is gathered by the lanes at row slot pos / R: the second row of a
                 // read pass takes the two table rows in exchanged order (GF(4))
@@ -289,7 +301,7 @@ __device__ __forceinline__ void m4rm_tile_rows(const MMArgs &a, int colw0, int r
     constexpr int LOG_NB = LOG_NCH - (HALF_BUILD ? 1 : 0);     // log2 of the building chunks
     constexpr int NB = 1 << LOG_NB;
     // the widest slab whose two tables fit 128 KiB at this super-row width
-    constexpr int KT = log2_floor(65536 / (PT * SRB)) < KMAX ? log2_floor(65536 / (PT * SRB)) : KMAX;
+    constexpr int KT = log2_floor(65536 / ES) < KMAX ? log2_floor(65536 / ES) : KMAX;
     constexpr int GMAX = KT > LOG_NB ? KT - LOG_NB : 0;         // longest walk: 2^GMAX entries
     constexpr int PFW = NB / 4;                                 // prefix threads per word
     constexpr int PFB = LOG_NB > 2 ? LOG_NB - 2 : 0;           // masked bits per prefix thread
@@ -364,6 +376,13 @@ __device__ __forceinline__ void m4rm_tile_rows(const MMArgs &a, int colw0, int r
         unsigned char *T = smem + ((s & 1) ? TB1 : 0u) + dw * 4;
         // entry of parity b at dst (plane order swapped in pairs on odd entries when SWZ)
         auto store = [&](unsigned char *dst, const u32 *v, u32 b) {
+            if constexpr (DCP) {
+                // slots: plane 2 (copy), planes 0, 1, 2
+                *reinterpret_cast<u32 *>(dst) = v[2];
+#pragma unroll
+                for (int p = 0; p < PT; p++) *reinterpret_cast<u32 *>(dst + (p + 1) * SRB) = v[p];
+                return;
+            }
 #pragma unroll
             for (int i = 0; i < REP; i++)
 #pragma unroll
@@ -406,7 +425,7 @@ __device__ __forceinline__ void m4rm_tile_rows(const MMArgs &a, int colw0, int r
                 }
             }
         }
-        unsigned char *eb = T + (u32)(ch << G) * (PT * SRB);
+        unsigned char *eb = T + (u32)(ch << G) * ES;
         store(eb, v, G == 0 ? (u32)(ch & 1) : 0u);
         if constexpr (GMAX > 0) {
             u32 wr[GMAX > 0 ? GMAX : 1][PT];
@@ -423,7 +442,7 @@ __device__ __forceinline__ void m4rm_tile_rows(const MMArgs &a, int colw0, int r
                 const int b = __builtin_ctz(j);
                 const int g = j ^ (j >> 1);
                 step(v, wr[b], (g >> b) & 1);
-                store(eb + g * (PT * SRB), v, (u32)(g & 1));      // j < 2^G: G >= 1, parity of g
+                store(eb + g * ES, v, (u32)(g & 1));             // j < 2^G: G >= 1, parity of g
             }
         }
     };
@@ -437,7 +456,9 @@ __device__ __forceinline__ void m4rm_tile_rows(const MMArgs &a, int colw0, int r
 
     const int rs = tid / LPR, cg = tid % LPR;
     const bool neg_row = GSW && ((tid / LPR) & 1);   // reads planes exchanged, accumulates -C
-    const u32 laneoff = (u32)(tid % (REP * LPR)) * 16u + (neg_row ? (u32)SRB : 0u);
+    // the first row of a doubled-copy pass reads slots 1, 2, 3, the second slots 0, 1, 2
+    const bool dbl_row = DCP && ((tid / LPR) & 1);
+    const u32 laneoff = (u32)(tid % (REP * LPR)) * 16u + (neg_row ? (u32)SRB : 0u) + ((DCP && !dbl_row) ? (u32)SRB : 0u);
 
     // gathers of one row: D table rows, GP planes each (plane F::gplane(d, p) of row d), 4 words
     // per lane
@@ -644,6 +665,13 @@ __device__ __forceinline__ void m4rm_tile_rows(const MMArgs &a, int colw0, int r
                 for (int i = 0; i < 4; i++) {
                     if constexpr (GSW) F::exchange_fix(acc[r][i], neg_row ? 0xffffffffu : 0u);
                     F::finish(acc[r][i], o[i]);
+                    if constexpr (DCP) {
+                        // the doubled row's 2C times 4: (c0, c1, c2) -> (c1, c2, c0)
+                        const u32 gm = dbl_row ? 0xffffffffu : 0u, o0 = o[i][0];
+                        o[i][0] = lut3<0xCA>(gm, o[i][1], o0);
+                        o[i][1] = lut3<0xCA>(gm, o[i][2], o[i][1]);
+                        o[i][2] = lut3<0xCA>(gm, o0, o[i][2]);
+                    }
                 }
 #pragma unroll
                 for (int p = 0; p < P; p++)

@@ -214,3 +214,22 @@ def test_gf4_exchanged_reads_identity():
     for t0 in range(4):
         for t1 in range(4):
             assert swap(t1) ^ mul(X, swap(t0)) == L(t0 ^ mul(X, t1))
+
+
+def test_f7_doubled_copy_reads():
+    """F_7's doubled-copy table layout: an entry t = (t0, t1, t2) is stored as the slots
+    (t2, t0, t1, t2); the first row of a read pass reads slots 1, 2, 3 (t itself), the second
+    slots 0, 1, 2, which is 2t (mod 7) for every 3-bit representative, so that row accumulates
+    2C; its canonical result times 4 is the rotation (c0, c1, c2) -> (c1, c2, c0), which keeps
+    canonical values canonical."""
+    val = lambda b: b[0] + 2 * b[1] + 4 * b[2]
+    for v in range(8):
+        t = (v & 1, (v >> 1) & 1, v >> 2)
+        slots = (t[2], t[0], t[1], t[2])
+        assert slots[1:4] == t
+        assert val(slots[0:3]) % 7 == (2 * val(t)) % 7
+    for C in range(7):                       # the second row finishes with 2C, canonical
+        c = (2 * C) % 7
+        b = (c & 1, (c >> 1) & 1, c >> 2)
+        r = (b[1], b[2], b[0])
+        assert val(r) == C

@@ -65,6 +65,9 @@ def test_server_poisson_mix_equals_alone_and_oracle(gfq_gpu):
     specs = mixed_specs(401, 240)
     rng = np.random.default_rng(402)
     gaps = rng.exponential(150.0, size=len(specs))            # about 6700 requests/s
+    # the last 40 arrive 150 ms after the others, so that the trace is served in more than one
+    # batch however long the host takes to submit it (a fresh process loads the kernels first)
+    gaps[200] += 150000.0
     srv = g.Server(budget_bytes=256 << 20, slots=3)
     try:
         reqs, keep, host = make(g, specs, 403, t0=0.0, gaps_us=gaps)
