@@ -13,6 +13,11 @@
 // invertible linear image of its row of C: -C for F_3 and F_9 (exchanging the planes negates
 // an entry), x^2 C^2 for GF(4).  Such fields define exchange_fix, which maps an accumulator
 // back where a lane mask is set.
+// FRONT_SLOT (three-plane fields F_7, GF(8)): at 128-byte super-rows a table entry gets a
+// fourth slot in front, front(t), with plane p of t at slot front_slot(p), such that reading
+// slots 0-2 in the order planes are read from slots 1-3 yields lam * t for a fixed nonzero
+// lam (F_7: 2t, GF(8): x t).  The second row of every read pass reads that way and
+// accumulates lam C; front_fix maps its finished row back where a lane mask is set.
 // HALF_BUILD_ROWS: from this many rows per lane on, the gathers of a slab outweigh its
 // table build enough that only half of the waves (one per SIMD) build the table, each
 // walking twice as far, with half the chunk prefixes (measured faster for every field at
@@ -74,6 +79,17 @@ template <> struct FT<3> {
 template <> struct FT<7> {
     static constexpr int P = 3, PT = 3, D = 3, GP = 3, PA = 6;
     static constexpr bool SPLIT_PREFIX = true, HALF_ROWS = false, EXCHANGE_READS = false;
+    // slots (t2, t0, t1, t2): slots 0-2 hold (t2, t0, t1) = 2t; the row of 2C is multiplied
+    // by 4, the rotation (c0, c1, c2) -> (c1, c2, c0)
+    static constexpr bool FRONT_SLOT = true;
+    static constexpr int front_slot(int p) { return p + 1; }
+    __device__ static u32 front(const u32 *t) { return t[2]; }
+    __device__ static void front_fix(u32 *o, u32 gm) {
+        const u32 o0 = o[0];
+        o[0] = lut3<0xCA>(gm, o[1], o0);          // gm ? o1 : o0
+        o[1] = lut3<0xCA>(gm, o[2], o[1]);
+        o[2] = lut3<0xCA>(gm, o0, o[2]);
+    }
     static constexpr int HALF_BUILD_ROWS = 1 << 30;
     static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; f[2] = x[2]; }
@@ -200,6 +216,18 @@ template <> struct FT<GF4_KARATSUBA> {
 template <> struct FT<8> {
     static constexpr int P = 3, PT = 3, D = 3, GP = 3, PA = 3;
     static constexpr bool SPLIT_PREFIX = false, HALF_ROWS = false, EXCHANGE_READS = false;
+    // slots (t0 + t2, t1, t2, t0): read as planes 0, 1, 2 from slots 2, 0, 1 they give
+    // (t2, t0 + t2, t1) = x t (x^3 = x + 1); the row of x C is multiplied by x^6 = x^2 + 1,
+    // (c0, c1, c2) -> (c0 + c1, c2, c0)
+    static constexpr bool FRONT_SLOT = true;
+    static constexpr int front_slot(int p) { return p == 0 ? 3 : p; }
+    __device__ static u32 front(const u32 *t) { return t[0] ^ t[2]; }
+    __device__ static void front_fix(u32 *o, u32 gm) {
+        const u32 o0 = o[0];
+        o[0] = o0 ^ (o[1] & gm);
+        o[1] = lut3<0xCA>(gm, o[2], o[1]);        // gm ? o2 : o1
+        o[2] = lut3<0xCA>(gm, o0, o[2]);
+    }
     static constexpr int HALF_BUILD_ROWS = 8;
     static constexpr int gplane(int, int p) { return p; }
     __device__ static void phis(const u32 *x, u32 *f) { f[0] = x[0]; f[1] = x[1]; f[2] = x[2]; }

@@ -53,10 +53,10 @@ inline int table_planes(int q) {
     return q == GF4_KARATSUBA ? 3 : ((q == GF8_TRINOMIAL || q == F9_KARATSUBA) ? 6 : planes_of(q));
 }
 
-// Table slots per entry: its planes, and for F_7 at 128-byte super-rows one more slot in front
-// holding a copy of plane 2 (the second row of every read pass reads the doubled entry from
+// Table slots per entry: its planes, and for F_7 and GF(8) at 128-byte super-rows one more
+// slot in front (the second row of every read pass reads a fixed multiple of the entry through
 // it, conflict-free; see the product tile).
-inline int table_slots(int q, int srb) { return (q == 7 && srb == 128) ? 4 : table_planes(q); }
+inline int table_slots(int q, int srb) { return ((q == 7 || q == 8) && srb == 128) ? 4 : table_planes(q); }
 inline int gathers_of(int q) {
     return (q == 3 || q == 4) ? 2 : (q == 9 ? 4 : ((q == GF8_TRINOMIAL || q == F9_KARATSUBA) ? 6 : 3));
 }

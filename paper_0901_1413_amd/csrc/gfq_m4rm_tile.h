@@ -42,6 +42,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "gfq_device.h"
 #include "gfq_internal.h"
 
@@ -62,14 +64,21 @@ template <int H> struct half_tag { static constexpr int value = H; };
 template <int Q, int TWD, int REP> constexpr bool gsw_tile() {
     return FT<Q>::EXCHANGE_READS && REP == 1 && TWD == 32;
 }
-// F_7 at 128-byte super-rows: each entry gets a fourth slot in front, a copy of plane 2, so
-// that the second row of a read pass can read the doubled entry (2t = (t2, t0, t1): doubling
-// modulo 7 rotates the planes) from slots 0, 1, 2 while the first reads t from slots 1, 2, 3.
-// Entries are 512 bytes, so slot j sits in half j mod 2 of the banks and the two rows never
-// meet; the second row accumulates 2C, and its result is multiplied by 4 (a rotation) before
-// the store.
+// Three-plane fields with a front slot (F_7, GF(8); F::FRONT_SLOT) at 128-byte super-rows:
+// each entry gets a fourth slot in front, so that the second row of a read pass reads
+// lam * t (F_7: the doubled entry, GF(8): x t) from slots 0, 1, 2 while the first reads t
+// from slots 1, 2, 3, each plane at the same offset from its row's base.  Entries are 512
+// bytes, so slot j sits in half j mod 2 of the banks and the two rows never meet; the second
+// row accumulates lam C, mapped back before the store.
+template <class F, class = void> struct has_front_slot : std::false_type {};
+template <class F> struct has_front_slot<F, std::void_t<decltype(F::FRONT_SLOT)>> : std::bool_constant<F::FRONT_SLOT> {};
 template <int Q, int TWD, int REP> constexpr bool dbl_copy_tile() {
-    return Q == 7 && REP == 1 && TWD == 32;
+    return has_front_slot<FT<Q>>::value && REP == 1 && TWD == 32;
+}
+// the slot of plane p relative to the row's base slot (front-slot tiles), else p
+template <class F, bool DCP> constexpr int plane_slot(int p) {
+    if constexpr (DCP) return F::front_slot(p) - 1;
+    else return p;
 }
 // fields whose exchanged reads also exchange the two gathers' table rows (GF(4))
 template <class F> constexpr bool exchange_slots() {
@@ -377,10 +386,10 @@ __device__ __forceinline__ void m4rm_tile_rows(const MMArgs &a, int colw0, int r
         // entry of parity b at dst (plane order swapped in pairs on odd entries when SWZ)
         auto store = [&](unsigned char *dst, const u32 *v, u32 b) {
             if constexpr (DCP) {
-                // slots: plane 2 (copy), planes 0, 1, 2
-                *reinterpret_cast<u32 *>(dst) = v[2];
+                // slot 0: the front value; plane p at slot F::front_slot(p)
+                *reinterpret_cast<u32 *>(dst) = F::front(v);
 #pragma unroll
-                for (int p = 0; p < PT; p++) *reinterpret_cast<u32 *>(dst + (p + 1) * SRB) = v[p];
+                for (int p = 0; p < PT; p++) *reinterpret_cast<u32 *>(dst + F::front_slot(p) * SRB) = v[p];
                 return;
             }
 #pragma unroll
@@ -487,7 +496,8 @@ __device__ __forceinline__ void m4rm_tile_rows(const MMArgs &a, int colw0, int r
 #pragma unroll
             for (int p = 0; p < GP; p++) {
                 const int pl = F::gplane(d, p);
-                const u32x4 v = (XSW && (pl & 1)) ? rowx[(pl & ~1) * (SRB / 16)] : row[(XSW ? (pl & ~1) : pl) * (SRB / 16)];
+                const u32x4 v = (XSW && (pl & 1)) ? rowx[(pl & ~1) * (SRB / 16)]
+                                                  : row[(XSW ? (pl & ~1) : plane_slot<F, DCP>(pl)) * (SRB / 16)];
                 t[d][p] = make_uint4(v.x, v.y, v.z, v.w);
             }
         }
@@ -516,7 +526,8 @@ __device__ __forceinline__ void m4rm_tile_rows(const MMArgs &a, int colw0, int r
 #pragma unroll
             for (int p = 0; p < GP; p++) {
                 const int pl = F::gplane(d, p);
-                const u32x4 v = (XSW && (pl & 1)) ? rowx[(pl & ~1) * (SRB / 16)] : row[(XSW ? (pl & ~1) : pl) * (SRB / 16)];
+                const u32x4 v = (XSW && (pl & 1)) ? rowx[(pl & ~1) * (SRB / 16)]
+                                                  : row[(XSW ? (pl & ~1) : plane_slot<F, DCP>(pl)) * (SRB / 16)];
                 t[dd][p] = make_uint4(v.x, v.y, v.z, v.w);
             }
         }
@@ -665,13 +676,7 @@ __device__ __forceinline__ void m4rm_tile_rows(const MMArgs &a, int colw0, int r
                 for (int i = 0; i < 4; i++) {
                     if constexpr (GSW) F::exchange_fix(acc[r][i], neg_row ? 0xffffffffu : 0u);
                     F::finish(acc[r][i], o[i]);
-                    if constexpr (DCP) {
-                        // the doubled row's 2C times 4: (c0, c1, c2) -> (c1, c2, c0)
-                        const u32 gm = dbl_row ? 0xffffffffu : 0u, o0 = o[i][0];
-                        o[i][0] = lut3<0xCA>(gm, o[i][1], o0);
-                        o[i][1] = lut3<0xCA>(gm, o[i][2], o[i][1]);
-                        o[i][2] = lut3<0xCA>(gm, o0, o[i][2]);
-                    }
+                    if constexpr (DCP) F::front_fix(o[i], dbl_row ? 0xffffffffu : 0u);
                 }
 #pragma unroll
                 for (int p = 0; p < P; p++)

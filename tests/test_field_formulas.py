@@ -233,3 +233,29 @@ def test_f7_doubled_copy_reads():
         b = (c & 1, (c >> 1) & 1, c >> 2)
         r = (b[1], b[2], b[0])
         assert val(r) == C
+
+
+def test_gf8_front_slot_reads():
+    """GF(8)'s front-slot table layout, checked with the oracle's GF(8) arithmetic (elements
+    c0 + c1 x + c2 x^2 as the integers c0 + 2 c1 + 4 c2): an entry t is stored as the slots
+    (t0 + t2, t1, t2, t0); the first row of a read pass reads planes 0, 1, 2 from slots 3, 1, 2
+    (t itself), the second from slots 2, 0, 1, which is x t; that row finishes with x C, and
+    (c0, c1, c2) -> (c0 + c1, c2, c0) is multiplication by x^6 = x^-1, which gives C back."""
+    import numpy as np
+
+    import oracle
+
+    def mul(a, b):
+        return int(oracle.matmul(8, np.array([[a]], dtype=np.uint8), np.array([[b]], dtype=np.uint8))[0, 0])
+
+    X = 2
+    bits = lambda v: (v & 1, (v >> 1) & 1, v >> 2)
+    num = lambda b: b[0] | (b[1] << 1) | (b[2] << 2)
+    for v in range(8):
+        t = bits(v)
+        slots = (t[0] ^ t[2], t[1], t[2], t[0])
+        assert num((slots[3], slots[1], slots[2])) == v
+        assert num((slots[2], slots[0], slots[1])) == mul(X, v)
+    for C in range(8):
+        c = bits(mul(X, C))
+        assert num((c[0] ^ c[1], c[2], c[0])) == C
