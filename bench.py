@@ -75,8 +75,8 @@ LDS_GEOM = {(3, 0): (2, 2, 2), (4, 0): (2, 2, 2), (5, 0): (3, 3, 3), (7, 0): (3,
 # valid only while the kernel sources hash to `src` (otherwise the roofline reports null).
 KERNEL_SOURCES = ("gfq_m4rm_launch.h", "gfq_m4rm_tile.h", "gfq_device.h", "gfq_field.h", "gfq_internal.h")
 MEASURED_TRAFFIC = {
-    3: {"src": "cc93155197f937fb", "read_mib": 54.3, "write_mib": 64.0},
-    5: {"src": "cc93155197f937fb", "read_mib": 129.3, "write_mib": 96.0},
+    3: {"src": "f52dc466b8f6a7bd", "read_mib": 54.3, "write_mib": 64.0},
+    5: {"src": "f52dc466b8f6a7bd", "read_mib": 129.3, "write_mib": 96.0},
 }
 
 
