@@ -340,13 +340,15 @@ def test_wide_tiles(gfq_gpu, q, rows, split):
     check(gfq_gpu, q, A, B, k=WIDE_K[q], rows=rows, split=split)
 
 
-@pytest.mark.parametrize("q,rows", [(3, 512), (3, 1024), (3, 256), (9, 0), (4, 1024), (4, 512), (4, 256)])
+@pytest.mark.parametrize("q,rows", [(3, 512), (3, 1024), (3, 256), (9, 0), (4, 1024), (4, 512), (4, 256),
+                                    (7, 256), (7, 512), (8, 512), (8, 256)])
 def test_wide_tiles_entry_parity(gfq_gpu, q, rows):
     """B = identity rows in a fixed order and A one-hot, so that every table entry of both
     parities is gathered and each product row equals one row of B: a plane swap left undone on
     odd entries, or on the rows that read their planes exchanged (F_3, F_9: the second row of
     every 16-lane read pass, which accumulates the negated row; GF(4): that row also takes its
-    two table rows in exchanged order and accumulates x^2 C^2), would show as swapped planes."""
+    two table rows in exchanged order and accumulates x^2 C^2), or through a front slot (F_7,
+    GF(8): that row reads 2t or x t), would show as wrong planes."""
     k = WIDE_K[q]
     l, n = 2 * k, 1500
     rng = np.random.default_rng(231)
@@ -358,10 +360,13 @@ def test_wide_tiles_entry_parity(gfq_gpu, q, rows):
             A[e, t] = (e >> t) & 1
         A[e, k + (e % k)] = 1                # and one row of slab 1
     check(gfq_gpu, q, A, B, k=k, rows=rows)
-    if q == 4:
-        # coefficients x as well as 1: both gathers of a slab select entries of both parities
+    if q in (4, 7, 8):
+        # coefficients of every basis element (x, x^2; 2, 4): every gather of a slab selects
+        # entries of both parities
         X = A.copy()
-        X[:, 1::2] *= 2
+        X[:, 1::3] *= 2
+        if q != 4:
+            X[:, 2::3] *= 4
         X[:, k:] = A[:, k:] * np.uint8(3)
         check(gfq_gpu, q, X, B, k=k, rows=rows)
 
