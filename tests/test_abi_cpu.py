@@ -135,3 +135,14 @@ def test_tune_cache_text_roundtrip(tmp_path):
     out2 = tmp_path / "empty.txt"
     gfq.tune_save(str(out2))
     assert [l for l in out2.read_text().splitlines() if not l.startswith("#")] == []
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: asked for more it exits with status 2 and says why, before
+    touching a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
